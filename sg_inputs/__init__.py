@@ -1,0 +1,153 @@
+"""Seeded synthetic workloads for the Smolyak H|psi> hot path.
+
+This module only draws random numbers and fixes workload shapes.  It holds none
+of the method's arithmetic (no term sets, tables, transforms or propagation), so
+that both the CPU oracle and the GPU path can take their inputs from it without
+sharing any code with each other.
+
+The Hamiltonian family used everywhere (stand-in for the paper's Sec. 5
+workloads, whose parameters the paper does not give):
+
+    H = sum_i 0.5*omega_i*(-d^2/dQ_i^2 + Q_i^2)
+        + sum_{i<j} c_ij Q_i^2 Q_j^2  [+ sum_{i<j} k_ij Q_i^2 Q_j]
+
+omega_i ~ U(0.5, 2.0), c_ij ~ U(-0.05, 0.05), k_ij ~ U(-0.02, 0.02); the
+initial state is a displaced Gaussian with shift_i ~ U(-1, 1).  The basis and
+grid size maps are nb(l) = 1 + 2 l Hermite functions and nq(l) = 2 + 2 l
+Gauss-Hermite points per level (the paper's N_l = A + B l, Sec. 2).
+
+Draw order per instance, from numpy.random.default_rng(seed):
+omega[D], c (i<j, row-major), k (i<j, row-major, only when the family has the
+cubic term), shift[D].
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+NB_A, NB_B, NQ_A, NQ_B = 1, 2, 2, 2
+DEFAULT_SEED = 0
+
+
+@dataclass
+class Instance:
+    """One Hamiltonian + initial state.  All arrays are float64, host side."""
+
+    D: int
+    L: int
+    omega: np.ndarray            # [D]
+    c: np.ndarray                # [D, D], only i<j entries are non-zero
+    k: np.ndarray                # [D, D], only i<j entries are non-zero
+    shift: np.ndarray            # [D]
+    nb_A: int = NB_A
+    nb_B: int = NB_B
+    nq_A: int = NQ_A
+    nq_B: int = NQ_B
+    meta: dict = field(default_factory=dict)
+
+
+def draw_instance(rng: np.random.Generator, D: int, L: int,
+                  with_k: bool = True) -> Instance:
+    omega = rng.uniform(0.5, 2.0, size=D)
+    c = np.zeros((D, D))
+    k = np.zeros((D, D))
+    iu = np.triu_indices(D, 1)
+    c[iu] = rng.uniform(-0.05, 0.05, size=len(iu[0]))
+    if with_k:
+        k[iu] = rng.uniform(-0.02, 0.02, size=len(iu[0]))
+    shift = rng.uniform(-1.0, 1.0, size=D)
+    return Instance(D=D, L=L, omega=omega, c=c, k=k, shift=shift)
+
+
+# ---------------------------------------------------------------------------
+# The five workloads.  Index i uses seed DEFAULT_SEED + i unless overridden.
+# ---------------------------------------------------------------------------
+
+def config0(seed: int | None = None) -> Instance:
+    """D=2, L=4, no cubic term; one apply + 100 Chebyshev steps of dt=0.1."""
+    rng = np.random.default_rng(DEFAULT_SEED + 0 if seed is None else seed)
+    inst = draw_instance(rng, 2, 4, with_k=False)
+    inst.meta = dict(name="d2_l4_fp64", dt=0.1, steps=100, check_every=10,
+                     precision="fp64")
+    return inst
+
+
+def config1(seed: int | None = None) -> Instance:
+    """D=6, L=6 with cubic term; 1000 steps of dt=0.05, checks every 100."""
+    rng = np.random.default_rng(DEFAULT_SEED + 1 if seed is None else seed)
+    inst = draw_instance(rng, 6, 6, with_k=True)
+    inst.meta = dict(name="d6_l6_fp64", dt=0.05, steps=1000, check_every=100,
+                     precision="fp64")
+    return inst
+
+
+def config2(seed: int | None = None) -> Instance:
+    """D=12, L=6 with cubic term; 500 steps of dt=0.05 in mixed precision."""
+    rng = np.random.default_rng(DEFAULT_SEED + 2 if seed is None else seed)
+    inst = draw_instance(rng, 12, 6, with_k=True)
+    inst.meta = dict(name="d12_l6_mixed", dt=0.05, steps=500, check_every=1,
+                     precision="mixed")
+    return inst
+
+
+def config3(seed: int | None = None, n_instances: int = 64) -> list[Instance]:
+    """64 independent instances, D ~ U{4..10}, L ~ U{4..7}; 200 mixed steps."""
+    rng = np.random.default_rng(DEFAULT_SEED + 3 if seed is None else seed)
+    out = []
+    for i in range(n_instances):
+        D = int(rng.integers(4, 11))
+        L = int(rng.integers(4, 8))
+        inst = draw_instance(rng, D, L, with_k=True)
+        inst.meta = dict(name=f"batch{i}_d{D}_l{L}", dt=0.05, steps=200,
+                         precision="mixed")
+        out.append(inst)
+    return out
+
+
+@dataclass
+class Request:
+    arrival_s: float
+    steps: int
+    inst: Instance
+
+
+def config4(seed: int | None = None, rate_hz: float = 20.0,
+            duration_s: float = 120.0) -> list[Request]:
+    """Poisson request stream; each request draws D ~ U{3..20},
+    L ~ U{3..6}, steps ~ U{50..2000}, then its Hamiltonian and shift.
+
+    The cap on the sparse-basis size is applied by the consumer, which knows
+    how to count the basis; this module only draws."""
+    rng = np.random.default_rng(DEFAULT_SEED + 4 if seed is None else seed)
+    t = 0.0
+    reqs = []
+    while True:
+        t += float(rng.exponential(1.0 / rate_hz))
+        if t >= duration_s:
+            break
+        D = int(rng.integers(3, 21))
+        L = int(rng.integers(3, 7))
+        steps = int(rng.integers(50, 2001))
+        inst = draw_instance(rng, D, L, with_k=True)
+        inst.meta = dict(name=f"req_d{D}_l{L}", dt=0.05, steps=steps,
+                         precision="mixed")
+        reqs.append(Request(arrival_s=t, steps=steps, inst=inst))
+    return reqs
+
+
+def random_state(rng: np.random.Generator, n: int) -> np.ndarray:
+    """A random complex128 vector of length n with unit 2-norm."""
+    v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    return v / np.linalg.norm(v)
+
+
+def small_instance(D: int, L: int, seed: int = 123, with_k: bool = True,
+                   nb=(NB_A, NB_B), nq=(NQ_A, NQ_B)) -> Instance:
+    """A small seeded instance for parity tests (any D, L, size maps)."""
+    rng = np.random.default_rng(seed)
+    inst = draw_instance(rng, D, L, with_k=with_k)
+    inst.nb_A, inst.nb_B = nb
+    inst.nq_A, inst.nq_B = nq
+    inst.meta = dict(name=f"small_d{D}_l{L}_s{seed}")
+    return inst
