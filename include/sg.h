@@ -1,0 +1,210 @@
+/*
+ * sg.h -- C ABI of the MI355X (gfx950) Smolyak sparse-grid library.
+ *
+ * The library computes the Smolyak operator action of a Hamiltonian on a
+ * wave packet stored in the compact Smolyak basis,
+ *
+ *     H_S |Psi> = sum_{l in R(l)} D_l  H |psi^l>          (eq_action_smolyak)
+ *
+ * term by term as in Alg. 1 (Operator action of one Smolyak term, Sec. 3):
+ * gather the term from the compact vector through the mapping table M^B,
+ * transform basis -> grid mode by mode (eq_transfer_b_to_g), apply the
+ * operator on the term's grid, transform grid -> basis (eq_transfer_g_to_b),
+ * and add D_l times the result into the compact output.  On top of it sits a
+ * Chebyshev propagator (the paper names the Chebyshev method for wave-packet
+ * propagation in Sec. 3 and uses it in Sec. 5), a batched multi-instance
+ * propagator and a continuous-batching server.
+ *
+ * Problem family (the paper's Hamiltonians are general; the library computes
+ * this polynomial family, Cartesian normal modes, hbar = 1):
+ *
+ *   H = sum_i 1/2 omega_i (-d^2/dQ_i^2 + Q_i^2)
+ *       + sum_{i<j} c_ij Q_i^2 Q_j^2 + sum_{i<j} k_ij Q_i^2 Q_j
+ *
+ * Primitive basis per mode: orthonormal Hermite functions ("Hm", Q0 = 0,
+ * scaleQ = 1, Sec. 4.5) with N^b_l = nb_A + nb_B l functions and
+ * N^q_l = nq_A + nq_B l Gauss-Hermite points at level l (N_l = A + B l,
+ * Sec. 2).  Term set R(l): l_i >= 0, L-D+1 <= |l| <= L, with
+ * D_l = (-1)^(L-|l|) C(D-1, L-|l|) (Sec. 2).
+ *
+ * Orderings (the ABI fixes them; Table 2 defines them):
+ *   - terms: l_1 varies fastest;
+ *   - positions inside a term: mode 1 fastest;
+ *   - compact basis: lexicographic in (n_1, ..., n_D), mode 1 slowest.
+ * Vectors on the device are complex128, interleaved (re, im), length N_cs.
+ *
+ * Conventions
+ *   - Every call returns an sg_status; nothing throws across the ABI.  On a
+ *     non-zero status sg_last_error() returns a thread-local message.
+ *   - Device pointers are HIP device pointers on the device that was current
+ *     when the problem was built; `stream` is a hipStream_t (NULL = the
+ *     default stream).  Calls that take a stream are asynchronous unless
+ *     stated otherwise.
+ *   - Handles own their device tables; the caller owns every vector it
+ *     passes.  Handles are not thread-safe: one caller thread per handle.
+ *   - Results are deterministic: the scatter-add is a fixed-order segmented
+ *     reduction with no floating-point atomics, so a call gives bit-identical
+ *     output run to run, and alone or inside a batch or a server mix.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SG_OK = 0,
+  SG_EINVAL = -1,      /* invalid argument or unsupported problem size      */
+  SG_ENOMEM = -2,      /* device/host allocation failed, or over a budget   */
+  SG_EDEVICE = -3,     /* a HIP runtime call failed                         */
+  SG_EAGAIN = -4,      /* serving: the request is not finished yet          */
+  SG_ENOTFOUND = -5,   /* serving: unknown ticket                           */
+  SG_ECANCELED = -6,   /* serving: the request was cancelled                */
+  SG_ETOL = -7         /* propagation: norm drift beyond the tolerance      */
+} sg_status;
+
+typedef enum {
+  /* Alg. 1 as stated: per term, the potential and the kinetic second-
+   * derivative matrices are applied on the term's grid; all FP64. */
+  SG_FP64 = 0,
+  /* Mixed: the separable harmonic part sum_i omega_i (n_i + 1/2) is applied
+   * exactly in FP64 on the compact basis (each term's quadrature reproduces it
+   * exactly and the D_l of the terms holding a basis function sum to 1), the
+   * coupling goes through the term grids with FP32 contractions on the
+   * matrix cores (FP32 accumulation), and the Smolyak sum, the Chebyshev state
+   * and all reductions stay FP64. */
+  SG_MIXED = 1
+} sg_precision;
+
+/* Problem description.  Caller-owned; sg_build_terms copies what it needs. */
+typedef struct {
+  int32_t D;             /* number of modes, 1..64                            */
+  int32_t L;             /* Smolyak level, 0..15                              */
+  int32_t nb_A, nb_B;    /* basis size map nb(l) = nb_A + nb_B l  (>=1, >=1)  */
+  int32_t nq_A, nq_B;    /* grid size map  nq(l) = nq_A + nq_B l, nq >= nb    */
+  const double *omega;   /* [D] harmonic frequencies (> 0)                    */
+  const double *c;       /* [D*D] row-major; entries i<j used: c_ij Q_i^2Q_j^2 */
+  const double *k;       /* [D*D] row-major; entries i<j used: k_ij Q_i^2 Q_j;
+                            NULL means all zero                               */
+} sg_problem_desc;
+
+typedef struct sg_problem sg_problem;
+
+typedef struct {
+  int64_t D, L;
+  int64_t n_terms;         /* N_st: terms of R(l) (all have D_l != 0)          */
+  int64_t n_cs;            /* compact basis size                               */
+  int64_t n_s;             /* term-major size sum_l prod_i nb(l_i)             */
+  int64_t grid_literal;    /* sum_l prod_i nq(l_i): the paper's term grids     */
+  int64_t grid_active;     /* sum_l prod_{l_i>0} nq(l_i): points evaluated     */
+  int64_t max_term_basis;  /* largest prod_{l_i>0} nb(l_i)                     */
+  int64_t max_term_grid;   /* largest prod_{l_i>0} nq(l_i)                     */
+  double flops_fp64;       /* algorithmic flops of one SG_FP64 apply           */
+  double flops_mixed;      /* algorithmic flops of one SG_MIXED apply          */
+  double bytes_fp64;       /* algorithmic HBM bytes of one apply (both modes)  */
+  int64_t device_bytes;    /* device memory held by the handle                 */
+} sg_info;
+
+/* Sizes of a problem without building it: out[0] = N_st, out[1] = N_s,
+ * out[2] = N_cs (Table 1 counts).  Host only.  Overflow -> SG_EINVAL. */
+sg_status sg_count_sizes(int32_t D, int32_t L, int32_t nb_A, int32_t nb_B,
+                         int64_t out[3]);
+
+/* Builds the term set, D_l, compact basis, M^B and its inverse, the per-level
+ * one-mode tables and the per-term operator coefficients on the host, and
+ * uploads them once to the current HIP device (synchronously).  *out receives
+ * a handle to release with sg_free. */
+sg_status sg_build_terms(const sg_problem_desc *desc, sg_problem **out);
+sg_status sg_free(sg_problem *p);
+
+/* Same host-side build without any device work: the handle supports
+ * sg_problem_info and the ordering exports below; calls that need the device
+ * return SG_EINVAL.  For inspection and for checking the term compiler on a
+ * machine without a GPU. */
+sg_status sg_build_terms_host(const sg_problem_desc *desc, sg_problem **out);
+
+sg_status sg_problem_info(const sg_problem *p, sg_info *out);
+
+/* Host copies of the ordering contract.
+ *   sg_basis_indices: n_out[i*D + j] = n_j of compact function i (0-based).
+ *   sg_term_levels:   levels[t*D + j] = l_j of term t, coeffs[t] = D_l.
+ *   sg_mapping_table: mb[s] = compact index of term-major position s (M^B,
+ *                     Table 2 order, 0-based). */
+sg_status sg_basis_indices(const sg_problem *p, int32_t *n_out);
+sg_status sg_term_levels(const sg_problem *p, int32_t *levels, int32_t *coeffs);
+sg_status sg_mapping_table(const sg_problem *p, int32_t *mb);
+
+/* Displaced Gaussian prod_i pi^{-1/4} exp(-(Q_i - shift_i)^2/2) projected on
+ * the compact basis (coherent-state coefficients) and normalised; writes
+ * complex128[N_cs] to psi_dev on `stream`.  *captured_norm (nullable) gets the
+ * norm of the projection before normalisation. */
+sg_status sg_init_gaussian(const sg_problem *p, const double *shift,
+                           void *psi_dev, double *captured_norm, void *stream);
+
+/* psi_out = H_S psi_in (eq_action_smolyak via Alg. 1).  psi_in and psi_out
+ * are distinct complex128[N_cs] device vectors.  Asynchronous on `stream`; no
+ * host synchronisation.  The handle's work buffers are reused: calls on one
+ * handle must be ordered on one stream. */
+sg_status sg_apply_H(sg_problem *p, const void *psi_in, void *psi_out,
+                     sg_precision prec, void *stream);
+
+/* Estimates [E_min, E_max] of H_S with `iters` Lanczos steps (FP64) from a
+ * fixed start vector, padded outward by 5% of the range plus the Ritz
+ * residuals.  Synchronises `stream`. */
+sg_status sg_spectral_bounds(sg_problem *p, int32_t iters, double *emin,
+                             double *emax, void *stream);
+
+typedef struct {
+  int32_t steps_done;
+  int32_t cheb_terms;        /* K: Chebyshev terms per step (K-1 applies)     */
+  int64_t applies;           /* H applies performed                            */
+  double emin, emax;         /* bounds used                                    */
+  double norm0, energy0;     /* at the first check                             */
+  double norm_last, energy_last;
+  double max_norm_drift;     /* max |norm - norm0| over the checks             */
+  double max_energy_drift;   /* max |E - E0| over the checks                   */
+} sg_prop_stats;
+
+/* Chebyshev propagation of psi (in place, complex128[N_cs]) over nsteps time
+ * steps of dt (hbar = 1):  psi <- exp(-i H_S dt)^nsteps psi.
+ * emin/emax bound the spectrum of H_S; NaN in either asks the library to
+ * estimate both (sg_spectral_bounds with 40 steps).  The series is cut at the
+ * first k > R = (emax-emin) dt / 2 where |J_k(R)| and |J_{k+1}(R)| are both
+ * below 1e-16.  Every `check_every` steps (0 = only at the start and end) the
+ * norm and energy are reduced in FP64 and read back (a host sync); if the
+ * norm drifts from its first value by more than `tol` the call stops and
+ * returns SG_ETOL.  stats (nullable) is filled on return.  norm_trace and
+ * energy_trace (nullable, host, length >= nsteps/check_every + 2) receive the
+ * checked values in order. */
+sg_status sg_propagate_chebyshev(sg_problem *p, void *psi, double dt,
+                                 int32_t nsteps, double emin, double emax,
+                                 double tol, sg_precision prec,
+                                 int32_t check_every, sg_prop_stats *stats,
+                                 double *norm_trace, double *energy_trace,
+                                 void *stream);
+
+/* Per-kernel timing for measurement.  sg_set_timing(p, 1) resets the
+ * counters and brackets every term-sweep and reduce launch made through this
+ * handle with a pair of HIP events on the launch stream (the events add a
+ * small gap between kernels; leave timing off for throughput runs).
+ * sg_get_timing waits for the recorded events and returns the summed kernel
+ * durations. */
+typedef struct {
+  double sweep_ms;           /* summed duration of the term-sweep kernels     */
+  int64_t sweep_launches;
+  double reduce_ms;          /* summed duration of the reduce kernels         */
+  int64_t reduce_launches;
+} sg_timing;
+sg_status sg_set_timing(sg_problem *p, int32_t enable);
+sg_status sg_get_timing(sg_problem *p, sg_timing *out);
+
+const char *sg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SG_H */

@@ -1,0 +1,325 @@
+"""Python binding of the MI355X Smolyak library (libsg.so, C ABI in
+include/sg.h).
+
+Argument marshalling only: every step of the operator action and of the
+propagation runs in the library's HIP kernels.  Device vectors are torch
+complex128 tensors on a ROCm device; streams are torch streams.  There is no
+fallback: if the native library is missing every call raises.
+
+The function names are the C ABI's; `Problem` is a small convenience owner of
+a problem handle.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+__all__ = [
+    "SG_OK", "SG_EINVAL", "SG_ENOMEM", "SG_EDEVICE", "SG_EAGAIN", "SG_ENOTFOUND",
+    "SG_ECANCELED", "SG_ETOL", "SG_FP64", "SG_MIXED", "SgError", "lib",
+    "library_path", "sg_count_sizes", "sg_build_terms", "sg_build_terms_host",
+    "sg_free", "sg_problem_info", "sg_basis_indices", "sg_term_levels",
+    "sg_mapping_table", "sg_init_gaussian", "sg_apply_H", "sg_spectral_bounds",
+    "sg_propagate_chebyshev", "sg_set_timing", "sg_get_timing", "Problem",
+]
+
+SG_OK, SG_EINVAL, SG_ENOMEM, SG_EDEVICE = 0, -1, -2, -3
+SG_EAGAIN, SG_ENOTFOUND, SG_ECANCELED, SG_ETOL = -4, -5, -6, -7
+SG_FP64, SG_MIXED = 0, 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libsg.so")
+
+
+class SgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"sg status {status}: {message}")
+        self.status = status
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("nb_A", ctypes.c_int32), ("nb_B", ctypes.c_int32),
+                ("nq_A", ctypes.c_int32), ("nq_B", ctypes.c_int32),
+                ("omega", ctypes.POINTER(ctypes.c_double)),
+                ("c", ctypes.POINTER(ctypes.c_double)),
+                ("k", ctypes.POINTER(ctypes.c_double))]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int64), ("L", ctypes.c_int64),
+                ("n_terms", ctypes.c_int64), ("n_cs", ctypes.c_int64),
+                ("n_s", ctypes.c_int64), ("grid_literal", ctypes.c_int64),
+                ("grid_active", ctypes.c_int64), ("max_term_basis", ctypes.c_int64),
+                ("max_term_grid", ctypes.c_int64), ("flops_fp64", ctypes.c_double),
+                ("flops_mixed", ctypes.c_double), ("bytes_fp64", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class PropStats(ctypes.Structure):
+    _fields_ = [("steps_done", ctypes.c_int32), ("cheb_terms", ctypes.c_int32),
+                ("applies", ctypes.c_int64), ("emin", ctypes.c_double),
+                ("emax", ctypes.c_double), ("norm0", ctypes.c_double),
+                ("energy0", ctypes.c_double), ("norm_last", ctypes.c_double),
+                ("energy_last", ctypes.c_double), ("max_norm_drift", ctypes.c_double),
+                ("max_energy_drift", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int64),
+                ("reduce_ms", ctypes.c_double), ("reduce_launches", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "sg_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "sg_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(Timing)]),
+    "sg_last_error": (ctypes.c_char_p, []),
+    "sg_count_sizes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "sg_build_terms": (ctypes.c_int, [ctypes.POINTER(ProblemDesc), ctypes.POINTER(_P)]),
+    "sg_build_terms_host": (ctypes.c_int, [ctypes.POINTER(ProblemDesc), ctypes.POINTER(_P)]),
+    "sg_free": (ctypes.c_int, [_P]),
+    "sg_problem_info": (ctypes.c_int, [_P, ctypes.POINTER(Info)]),
+    "sg_basis_indices": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "sg_term_levels": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32)]),
+    "sg_mapping_table": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "sg_init_gaussian": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), _P,
+                                        ctypes.POINTER(ctypes.c_double), _P]),
+    "sg_apply_H": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
+    "sg_spectral_bounds": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double), _P]),
+    "sg_propagate_chebyshev": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32,
+                                              ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_int, ctypes.c_int32,
+                                              ctypes.POINTER(PropStats),
+                                              ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double), _P]),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libsg.so (raises if it was not built)."""
+    global _LIB
+    if _LIB is None:
+        # torch ships its own HIP runtime with the same SONAME as the system
+        # one libsg.so links; loading torch first makes the dynamic loader
+        # resolve libsg.so's HIP dependency to that already-loaded runtime, so
+        # the process holds a single HIP runtime and device pointers and
+        # streams from torch are valid in the library.
+        import torch  # noqa: F401
+        path = library_path()
+        if not os.path.exists(path):
+            raise RuntimeError(
+                f"native library {path} is missing: build it with "
+                "`python -m paper_2111_13655_amd.build` (no fallback exists)")
+        L = ctypes.CDLL(path)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(status: int):
+    if status != SG_OK:
+        msg = lib().sg_last_error()
+        raise SgError(status, msg.decode() if msg else "")
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _vec_ptr(t, n_cs: int, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous complex128 device tensor")
+    if t.numel() != n_cs:
+        raise ValueError(f"{name} has {t.numel()} entries, expected N_cs = {n_cs}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _make_desc(D, L, omega, c, k, nb, nq):
+    omega = np.ascontiguousarray(omega, dtype=np.float64).reshape(D)
+    c = np.ascontiguousarray(c, dtype=np.float64).reshape(D * D)
+    kk = None if k is None else np.ascontiguousarray(k, dtype=np.float64).reshape(D * D)
+    desc = ProblemDesc(D, L, nb[0], nb[1], nq[0], nq[1], _dptr(omega), _dptr(c),
+                       _dptr(kk) if kk is not None else ctypes.POINTER(ctypes.c_double)())
+    return desc, (omega, c, kk)  # keep arrays alive
+
+
+# ---------------------------------------------------------------------------
+# C ABI, one function each
+# ---------------------------------------------------------------------------
+
+def sg_count_sizes(D: int, L: int, nb_A: int = 1, nb_B: int = 2):
+    out = (ctypes.c_int64 * 3)()
+    _check(lib().sg_count_sizes(D, L, nb_A, nb_B, out))
+    return int(out[0]), int(out[1]), int(out[2])
+
+
+def sg_build_terms(D, L, omega, c, k=None, nb=(1, 2), nq=(2, 2)) -> ctypes.c_void_p:
+    desc, keep = _make_desc(D, L, omega, c, k, nb, nq)
+    h = _P()
+    _check(lib().sg_build_terms(ctypes.byref(desc), ctypes.byref(h)))
+    return h
+
+
+def sg_build_terms_host(D, L, omega, c, k=None, nb=(1, 2), nq=(2, 2)) -> ctypes.c_void_p:
+    desc, keep = _make_desc(D, L, omega, c, k, nb, nq)
+    h = _P()
+    _check(lib().sg_build_terms_host(ctypes.byref(desc), ctypes.byref(h)))
+    return h
+
+
+def sg_free(h) -> None:
+    _check(lib().sg_free(h))
+
+
+def sg_problem_info(h) -> dict:
+    info = Info()
+    _check(lib().sg_problem_info(h, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def sg_basis_indices(h) -> np.ndarray:
+    inf = sg_problem_info(h)
+    out = np.zeros(inf["n_cs"] * inf["D"], dtype=np.int32)
+    _check(lib().sg_basis_indices(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return out.reshape(inf["n_cs"], inf["D"])
+
+
+def sg_term_levels(h):
+    inf = sg_problem_info(h)
+    lev = np.zeros(inf["n_terms"] * inf["D"], dtype=np.int32)
+    co = np.zeros(inf["n_terms"], dtype=np.int32)
+    _check(lib().sg_term_levels(h, lev.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                co.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return lev.reshape(inf["n_terms"], inf["D"]), co
+
+
+def sg_mapping_table(h) -> np.ndarray:
+    inf = sg_problem_info(h)
+    mb = np.zeros(inf["n_s"], dtype=np.int32)
+    _check(lib().sg_mapping_table(h, mb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return mb
+
+
+def sg_init_gaussian(h, shift, psi, stream=None) -> float:
+    n_cs = sg_problem_info(h)["n_cs"]
+    shift = np.ascontiguousarray(shift, dtype=np.float64)
+    cap = ctypes.c_double()
+    _check(lib().sg_init_gaussian(h, _dptr(shift), _vec_ptr(psi, n_cs, "psi"),
+                                  ctypes.byref(cap), _stream_ptr(stream)))
+    return cap.value
+
+
+def sg_apply_H(h, psi_in, psi_out, precision: int = SG_FP64, stream=None, n_cs=None) -> None:
+    if n_cs is None:
+        n_cs = sg_problem_info(h)["n_cs"]
+    _check(lib().sg_apply_H(h, _vec_ptr(psi_in, n_cs, "psi_in"),
+                            _vec_ptr(psi_out, n_cs, "psi_out"), int(precision),
+                            _stream_ptr(stream)))
+
+
+def sg_spectral_bounds(h, iters: int = 40, stream=None):
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(lib().sg_spectral_bounds(h, iters, ctypes.byref(lo), ctypes.byref(hi),
+                                    _stream_ptr(stream)))
+    return lo.value, hi.value
+
+
+def sg_propagate_chebyshev(h, psi, dt: float, nsteps: int, emin=math.nan, emax=math.nan,
+                           tol: float = 1e-8, precision: int = SG_FP64,
+                           check_every: int = 0, stream=None, traces: bool = False):
+    """Returns (status, stats dict, norm trace, energy trace)."""
+    n_cs = sg_problem_info(h)["n_cs"]
+    st = PropStats()
+    ntr = (nsteps // check_every + 2) if check_every > 0 else 2
+    ntr = max(ntr, 2)
+    nt = np.zeros(ntr)
+    et = np.zeros(ntr)
+    status = lib().sg_propagate_chebyshev(
+        h, _vec_ptr(psi, n_cs, "psi"), float(dt), int(nsteps), float(emin), float(emax),
+        float(tol), int(precision), int(check_every), ctypes.byref(st), _dptr(nt), _dptr(et),
+        _stream_ptr(stream))
+    if status not in (SG_OK, SG_ETOL):
+        _check(status)
+    d = st.as_dict()
+    n = min(ntr, (d["steps_done"] // check_every + 2) if check_every > 0 else 2)
+    return status, d, nt[:n], et[:n]
+
+
+def sg_set_timing(h, enable: bool) -> None:
+    _check(lib().sg_set_timing(h, 1 if enable else 0))
+
+
+def sg_get_timing(h) -> dict:
+    t = Timing()
+    _check(lib().sg_get_timing(h, ctypes.byref(t)))
+    return t.as_dict()
+
+
+class Problem:
+    """Owns one problem handle built on the current device."""
+
+    def __init__(self, D, L, omega, c, k=None, nb=(1, 2), nq=(2, 2), host_only=False):
+        self.handle = (sg_build_terms_host if host_only else sg_build_terms)(
+            D, L, omega, c, k, nb, nq)
+        self.info = sg_problem_info(self.handle)
+        self.n_cs = self.info["n_cs"]
+
+    @classmethod
+    def from_instance(cls, inst, host_only=False):
+        return cls(inst.D, inst.L, inst.omega, inst.c, inst.k,
+                   (inst.nb_A, inst.nb_B), (inst.nq_A, inst.nq_B), host_only=host_only)
+
+    def apply(self, psi_in, psi_out, precision=SG_FP64, stream=None):
+        sg_apply_H(self.handle, psi_in, psi_out, precision, stream, self.n_cs)
+
+    def close(self):
+        if self.handle is not None:
+            sg_free(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,344 @@
+// C ABI entry points: problem lifetime, ordering exports, initial state and
+// the operator action.  See include/sg.h for the contract of each call.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "sg_internal.h"
+
+namespace sg {
+thread_local std::string g_last_error;
+
+sg_status fail(sg_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+sg_status hip_fail(hipError_t e, const char *what) {
+  return fail(SG_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+template <typename T>
+hipError_t upload(T **dst, const T *src, size_t n, int64_t *bytes) {
+  size_t sz = n * sizeof(T);
+  if (sz == 0) sz = sizeof(T);
+  hipError_t e = hipMalloc((void **)dst, sz);
+  if (e != hipSuccess) return e;
+  *bytes += (int64_t)sz;
+  if (n) e = hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+constexpr int kTimingPairs = 2048;
+
+// Reads back every recorded (start, stop) pair and accumulates durations.
+hipError_t flush_timing(sg_problem *p) {
+  auto &T = p->timing;
+  if (T.used == 0) return hipSuccess;
+  hipError_t e = hipEventSynchronize(T.ev[2 * (T.used - 1) + 1]);
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < T.used; ++i) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, T.ev[2 * i], T.ev[2 * i + 1]);
+    if (e != hipSuccess) return e;
+    T.ms[T.kind[i]] += ms;
+    T.n[T.kind[i]] += 1;
+  }
+  T.used = 0;
+  return hipSuccess;
+}
+
+template <typename F>
+hipError_t timed(sg_problem *p, int kind, hipStream_t s, F launch) {
+  auto &T = p->timing;
+  if (!T.on) return launch();
+  if (T.used == kTimingPairs) {
+    hipError_t e = flush_timing(p);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipEventRecord(T.ev[2 * T.used], s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(T.ev[2 * T.used + 1], s);
+  if (e != hipSuccess) return e;
+  T.kind[T.used] = kind;
+  T.used += 1;
+  T.stream = s;
+  return hipSuccess;
+}
+
+void release(sg_problem *p) {
+  if (!p) return;
+  if (p->host_only) {
+    delete p;
+    return;
+  }
+  for (hipEvent_t ev : p->timing.ev) hipEventDestroy(ev);
+  hipFree(p->d_terms);
+  hipFree(p->d_sched);
+  hipFree(p->d_mb);
+  hipFree(p->d_inv_ptr);
+  hipFree(p->d_inv_col);
+  hipFree(p->d_tables);
+  hipFree(p->d_h0);
+  hipFree(p->d_c);
+  hipFree(p->d_k);
+  hipFree(p->d_tm);
+  hipFree(p->d_work);
+  hipFree(p->d_partials);
+  hipFree(p->d_result);
+  if (p->h_result) hipHostFree(p->h_result);
+  delete p;
+}
+
+}  // namespace
+
+hipError_t run_sweep(sg_problem *p, const double2 *psi, sg_precision prec, hipStream_t s) {
+  return timed(p, 0, s, [&] { return launch_sweep(p, psi, prec, s); });
+}
+
+hipError_t run_reduce(sg_problem *p, Epi epi, const double2 *psi_in, double2 *out,
+                      const ChebArgs *ca, hipStream_t s) {
+  return timed(p, 1, s, [&] { return launch_reduce(p, epi, psi_in, out, ca, s); });
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+const char *sg_last_error(void) { return g_last_error.c_str(); }
+
+sg_status sg_count_sizes(int32_t D, int32_t L, int32_t nb_A, int32_t nb_B, int64_t out[3]) {
+  if (!out) return fail(SG_EINVAL, "out is NULL");
+  sg_status st = count_sizes(D, L, nb_A, nb_B, out);
+  if (st != SG_OK) return fail(st, "invalid or overflowing size parameters");
+  return SG_OK;
+}
+
+sg_status sg_build_terms(const sg_problem_desc *desc, sg_problem **out) {
+  if (!out) return fail(SG_EINVAL, "out is NULL");
+  *out = nullptr;
+  sg_problem *p = new (std::nothrow) sg_problem();
+  if (!p) return fail(SG_ENOMEM, "host allocation failed");
+  std::string err;
+  sg_status st;
+  try {
+    st = compile_problem(desc, &p->h, &err);
+  } catch (const std::bad_alloc &) {
+    delete p;
+    return fail(SG_ENOMEM, "host allocation failed while compiling terms");
+  }
+  if (st != SG_OK) {
+    delete p;
+    return fail(st, err);
+  }
+  const Compiled &h = p->h;
+  if (2 * h.max_grid * (int64_t)sizeof(double2) > 160 * 1024) {
+    delete p;
+    return fail(SG_EINVAL, "a term grid exceeds the on-chip buffer (max 5120 points)");
+  }
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
+  int64_t &bytes = p->device_bytes;
+  const int64_t ns = (int64_t)h.MB.size();
+#define SG_UP(dst, vec)                                                  \
+  e = upload(&p->dst, (vec).data(), (vec).size(), &bytes);               \
+  if (e != hipSuccess) { release(p); return hip_fail(e, "upload " #dst); }
+  SG_UP(d_terms, h.terms)
+  SG_UP(d_sched, h.sched)
+  SG_UP(d_mb, h.MB)
+  SG_UP(d_inv_ptr, h.inv_ptr)
+  SG_UP(d_inv_col, h.inv_col)
+  SG_UP(d_tables, h.tables)
+  SG_UP(d_h0, h.h0)
+  SG_UP(d_c, h.c)
+  SG_UP(d_k, h.k)
+#undef SG_UP
+  size_t tm_bytes = (size_t)ns * sizeof(double2);
+  e = hipMalloc((void **)&p->d_tm, tm_bytes);
+  if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation of the term-major buffer failed"); }
+  bytes += (int64_t)tm_bytes;
+  size_t work_bytes = 4 * (size_t)h.ncs * sizeof(double2);
+  e = hipMalloc((void **)&p->d_work, work_bytes);
+  if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation of work vectors failed"); }
+  bytes += (int64_t)work_bytes;
+  p->n_partials = (int)std::max<int64_t>((h.ncs + 3) / 4, 256);
+  e = hipMalloc((void **)&p->d_partials, 2 * (size_t)p->n_partials * sizeof(double));
+  if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
+  bytes += 2 * (int64_t)p->n_partials * sizeof(double);
+  e = hipMalloc((void **)&p->d_result, 8 * sizeof(double));
+  if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
+  e = hipHostMalloc((void **)&p->h_result, 8 * sizeof(double), hipHostMallocDefault);
+  if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "pinned host allocation failed"); }
+  *out = p;
+  return SG_OK;
+}
+
+sg_status sg_build_terms_host(const sg_problem_desc *desc, sg_problem **out) {
+  if (!out) return fail(SG_EINVAL, "out is NULL");
+  *out = nullptr;
+  sg_problem *p = new (std::nothrow) sg_problem();
+  if (!p) return fail(SG_ENOMEM, "host allocation failed");
+  p->host_only = true;
+  std::string err;
+  sg_status st;
+  try {
+    st = compile_problem(desc, &p->h, &err);
+  } catch (const std::bad_alloc &) {
+    delete p;
+    return fail(SG_ENOMEM, "host allocation failed while compiling terms");
+  }
+  if (st != SG_OK) {
+    delete p;
+    return fail(st, err);
+  }
+  *out = p;
+  return SG_OK;
+}
+
+sg_status sg_free(sg_problem *p) {
+  if (!p) return SG_OK;
+  if (p->host_only) {
+    release(p);
+    return SG_OK;
+  }
+  int cur = 0;
+  hipGetDevice(&cur);
+  hipSetDevice(p->device);
+  release(p);
+  hipSetDevice(cur);
+  return SG_OK;
+}
+
+sg_status sg_problem_info(const sg_problem *p, sg_info *out) {
+  if (!p || !out) return fail(SG_EINVAL, "NULL argument");
+  const Compiled &h = p->h;
+  out->D = h.D;
+  out->L = h.L;
+  out->n_terms = h.nterms;
+  out->n_cs = h.ncs;
+  out->n_s = (int64_t)h.MB.size();
+  out->grid_literal = h.grid_literal;
+  out->grid_active = h.grid_active;
+  out->max_term_basis = h.max_basis;
+  out->max_term_grid = h.max_grid;
+  out->flops_fp64 = h.flops_fp64;
+  out->flops_mixed = h.flops_mixed;
+  out->bytes_fp64 = h.bytes_apply;
+  out->device_bytes = p->device_bytes;
+  return SG_OK;
+}
+
+sg_status sg_basis_indices(const sg_problem *p, int32_t *n_out) {
+  if (!p || !n_out) return fail(SG_EINVAL, "NULL argument");
+  for (size_t i = 0; i < p->h.compact.size(); ++i) n_out[i] = p->h.compact[i];
+  return SG_OK;
+}
+
+sg_status sg_term_levels(const sg_problem *p, int32_t *levels, int32_t *coeffs) {
+  if (!p) return fail(SG_EINVAL, "NULL problem");
+  if (levels)
+    for (size_t i = 0; i < p->h.lev.size(); ++i) levels[i] = p->h.lev[i];
+  if (coeffs)
+    for (size_t i = 0; i < p->h.coeff.size(); ++i) coeffs[i] = p->h.coeff[i];
+  return SG_OK;
+}
+
+sg_status sg_mapping_table(const sg_problem *p, int32_t *mb) {
+  if (!p || !mb) return fail(SG_EINVAL, "NULL argument");
+  std::memcpy(mb, p->h.MB.data(), p->h.MB.size() * sizeof(int32_t));
+  return SG_OK;
+}
+
+sg_status sg_init_gaussian(const sg_problem *p, const double *shift, void *psi_dev,
+                           double *captured_norm, void *stream) {
+  if (!p || !shift || !psi_dev) return fail(SG_EINVAL, "NULL argument");
+  if (p->host_only) return fail(SG_EINVAL, "handle was built without device tables");
+  const Compiled &h = p->h;
+  // coherent-state coefficients e^{-a^2/2} a^n / sqrt(n!), a = s/sqrt(2)
+  std::vector<double> tab((size_t)h.D * (h.nmax + 1));
+  for (int i = 0; i < h.D; ++i) {
+    if (!std::isfinite(shift[i])) return fail(SG_EINVAL, "shift must be finite");
+    const double a = shift[i] / std::sqrt(2.0);
+    double v = std::exp(-0.5 * a * a);
+    for (int n = 0; n <= h.nmax; ++n) {
+      if (n > 0) v *= a / std::sqrt((double)n);
+      tab[(size_t)i * (h.nmax + 1) + n] = v;
+    }
+  }
+  std::vector<double2> c(h.ncs);
+  double nrm2 = 0.0;
+  for (int64_t r = 0; r < h.ncs; ++r) {
+    double v = 1.0;
+    for (int i = 0; i < h.D; ++i) v *= tab[(size_t)i * (h.nmax + 1) + h.compact[(size_t)r * h.D + i]];
+    c[r] = make_double2(v, 0.0);
+    nrm2 += v * v;
+  }
+  const double nrm = std::sqrt(nrm2);
+  if (!(nrm > 0.0)) return fail(SG_EINVAL, "initial state has zero projection");
+  for (auto &x : c) x.x /= nrm;
+  if (captured_norm) *captured_norm = nrm;
+  hipError_t e = hipMemcpyAsync(psi_dev, c.data(), c.size() * sizeof(double2),
+                                hipMemcpyHostToDevice, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "upload initial state");
+  return SG_OK;
+}
+
+sg_status sg_apply_H(sg_problem *p, const void *psi_in, void *psi_out, sg_precision prec,
+                     void *stream) {
+  if (!p || !psi_in || !psi_out) return fail(SG_EINVAL, "NULL argument");
+  if (psi_in == psi_out) return fail(SG_EINVAL, "psi_in and psi_out must differ");
+  if (p->host_only) return fail(SG_EINVAL, "handle was built without device tables");
+  if (prec != SG_FP64 && prec != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = run_sweep(p, (const double2 *)psi_in, prec, s);
+  if (e != hipSuccess) return hip_fail(e, "term sweep launch");
+  ChebArgs ca{};
+  ca.split = prec == SG_MIXED ? 1 : 0;
+  e = run_reduce(p, Epi::Apply, (const double2 *)psi_in, (double2 *)psi_out, &ca, s);
+  if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  return SG_OK;
+}
+
+sg_status sg_set_timing(sg_problem *p, int32_t enable) {
+  if (!p) return fail(SG_EINVAL, "NULL problem");
+  if (p->host_only) return fail(SG_EINVAL, "handle was built without device tables");
+  auto &T = p->timing;
+  if (T.on) {
+    hipError_t e = flush_timing(p);
+    if (e != hipSuccess) return hip_fail(e, "timing flush");
+  }
+  if (enable && T.ev.empty()) {
+    T.ev.resize(2 * kTimingPairs);
+    T.kind.resize(kTimingPairs);
+    for (auto &ev : T.ev) {
+      hipError_t e = hipEventCreate(&ev);
+      if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+  }
+  T.on = enable != 0;
+  T.used = 0;
+  T.ms[0] = T.ms[1] = 0.0;
+  T.n[0] = T.n[1] = 0;
+  return SG_OK;
+}
+
+sg_status sg_get_timing(sg_problem *p, sg_timing *out) {
+  if (!p || !out) return fail(SG_EINVAL, "NULL argument");
+  hipError_t e = flush_timing(p);
+  if (e != hipSuccess) return hip_fail(e, "timing flush");
+  out->sweep_ms = p->timing.ms[0];
+  out->sweep_launches = p->timing.n[0];
+  out->reduce_ms = p->timing.ms[1];
+  out->reduce_launches = p->timing.n[1];
+  return SG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+"""GPU parity of sg_apply_H against the CPU oracle (FP64 path: 1e-12)."""
+import numpy as np
+import pytest
+
+import sg_inputs
+from oracle.action import Oracle, galerkin_masked_matrix, galerkin_rows
+from oracle.smolyak import CompactRanker
+from tests.gpu_util import empty, max_rel, rand_state, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-12
+
+
+def _sg():
+    import paper_2111_13655_amd as sg
+    return sg
+
+
+@pytest.mark.parametrize("D,L", [(1, 0), (3, 0), (1, 3), (1, 7), (2, 4), (2, 7), (3, 3),
+                                 (4, 2), (3, 5), (5, 3), (4, 4)])
+def test_apply_fp64_vs_route1(D, L):
+    sg = _sg()
+    inst = sg_inputs.small_instance(D, L, seed=100 + 10 * D + L)
+    say(f"apply fp64 D={D} L={L}")
+    O = Oracle(inst)
+    psi = rand_state(O.S.n_cs, 7)
+    ref = O.apply_literal(psi)
+    with sg.Problem.from_instance(inst) as P:
+        assert P.n_cs == O.S.n_cs
+        x, y = to_dev(psi), empty(P.n_cs)
+        P.apply(x, y, sg.SG_FP64)
+        out = to_host(y)
+    assert max_rel(out, ref) < TOL_FP64
+
+
+def test_apply_general_size_maps():
+    sg = _sg()
+    for nb, nq in [((2, 1), (3, 1)), ((1, 1), (2, 1)), ((1, 2), (3, 2))]:
+        inst = sg_inputs.small_instance(3, 3, seed=5, nb=nb, nq=nq)
+        say(f"apply size maps nb={nb} nq={nq}")
+        O = Oracle(inst)
+        psi = rand_state(O.S.n_cs, 3)
+        ref = O.apply_literal(psi)
+        with sg.Problem.from_instance(inst) as P:
+            x, y = to_dev(psi), empty(P.n_cs)
+            P.apply(x, y, sg.SG_FP64)
+            out = to_host(y)
+        assert max_rel(out, ref) < TOL_FP64, (nb, nq)
+
+
+def test_apply_config0_route1_and_route2():
+    sg = _sg()
+    inst = sg_inputs.config0()
+    O = Oracle(inst)
+    psi = rand_state(O.S.n_cs, 1)
+    r1 = O.apply_literal(psi)
+    r2 = galerkin_masked_matrix(inst) @ psi
+    with sg.Problem.from_instance(inst) as P:
+        x, y = to_dev(psi), empty(P.n_cs)
+        P.apply(x, y, sg.SG_FP64)
+        out = to_host(y)
+    assert max_rel(out, r1) < TOL_FP64
+    assert max_rel(out, r2) < TOL_FP64
+
+
+def test_apply_config1_full():
+    """(D, L) = (6, 6), the propagation benchmark's operator, full vector."""
+    sg = _sg()
+    inst = sg_inputs.config1()
+    say("apply config1 full")
+    H = galerkin_masked_matrix(inst)
+    psi = rand_state(H.shape[0], 2)
+    r2 = H @ psi
+    O = Oracle(inst)
+    r1 = O.apply_literal(psi)
+    with sg.Problem.from_instance(inst) as P:
+        x, y = to_dev(psi), empty(P.n_cs)
+        P.apply(x, y, sg.SG_FP64)
+        out = to_host(y)
+    assert max_rel(out, r1) < TOL_FP64
+    assert max_rel(out, r2) < TOL_FP64
+    assert np.linalg.norm(out - r1) / np.linalg.norm(r1) < TOL_FP64
+
+
+def test_apply_config2_sampled_rows_and_hermiticity():
+    """(D, L) = (12, 6), full size: sampled output rows from the closed form,
+    plus <phi|H psi> = conj(<psi|H phi>) over the whole vector."""
+    sg = _sg()
+    inst = sg_inputs.config2()
+    say("apply config2 sampled rows")
+    with sg.Problem.from_instance(inst) as P:
+        n = P.n_cs
+        psi = rand_state(n, 4)
+        phi = rand_state(n, 5)
+        x, y = to_dev(psi), empty(n)
+        P.apply(x, y, sg.SG_FP64)
+        Hpsi = to_host(y)
+        x2, y2 = to_dev(phi), empty(n)
+        P.apply(x2, y2, sg.SG_FP64)
+        Hphi = to_host(y2)
+        comp = sg.sg_basis_indices(P.handle)
+    rk = CompactRanker(inst.D, inst.L, 1, 2)
+    rng = np.random.default_rng(0)
+    rows = np.concatenate([[0, 1, n - 1], rng.choice(n, 200, replace=False)])
+    scale = np.abs(Hpsi).max()
+    for r, (cols, vals) in zip(rows, galerkin_rows(inst, rk, comp[rows])):
+        ref = np.dot(vals, psi[cols])
+        assert abs(Hpsi[r] - ref) < TOL_FP64 * scale, r
+    lhs = np.vdot(phi, Hpsi)
+    rhs = np.conj(np.vdot(psi, Hphi))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_apply_uncoupled_is_diagonal():
+    sg = _sg()
+    inst = sg_inputs.small_instance(5, 4, seed=9)
+    inst.c[:] = 0.0
+    inst.k[:] = 0.0
+    with sg.Problem.from_instance(inst) as P:
+        comp = sg.sg_basis_indices(P.handle)
+        E = (inst.omega[None, :] * (comp + 0.5)).sum(axis=1)
+        psi = rand_state(P.n_cs, 1)
+        x, y = to_dev(psi), empty(P.n_cs)
+        P.apply(x, y, sg.SG_FP64)
+        out = to_host(y)
+    assert max_rel(out, E * psi) < TOL_FP64
+
+
+def test_apply_bitwise_deterministic():
+    sg = _sg()
+    inst = sg_inputs.config1()
+    with sg.Problem.from_instance(inst) as P:
+        psi = rand_state(P.n_cs, 8)
+        x = to_dev(psi)
+        outs = []
+        for _ in range(3):
+            y = empty(P.n_cs)
+            P.apply(x, y, sg.SG_FP64)
+            outs.append(to_host(y))
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
+def test_apply_rejects_bad_arguments():
+    sg = _sg()
+    import torch
+    inst = sg_inputs.small_instance(2, 2, seed=1)
+    with sg.Problem.from_instance(inst) as P:
+        x = empty(P.n_cs)
+        with pytest.raises(ValueError):
+            P.apply(x, empty(P.n_cs + 1))
+        with pytest.raises(sg.SgError):
+            sg.lib()  # library present
+            st = sg.lib().sg_apply_H(P.handle, x.data_ptr(), x.data_ptr(), 0,
+                                     torch.cuda.current_stream().cuda_stream)
+            sg._check(st)
