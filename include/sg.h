@@ -187,6 +187,24 @@ sg_status sg_propagate_chebyshev(sg_problem *p, void *psi, double dt,
                                  double *norm_trace, double *energy_trace,
                                  void *stream);
 
+/* Mixed-precision policy.  With SG_MIXED, a term whose combination
+ * coefficient satisfies |D_l| <= max_fp32_coeff runs its grid contractions in
+ * FP32; the others (few, small terms whose rounding the Smolyak sum amplifies
+ * by |D_l|) run in FP64.  The default is 16.  Synchronous; also valid on a
+ * host-only handle. */
+sg_status sg_set_mixed_threshold(sg_problem *p, int32_t max_fp32_coeff);
+
+/* Precision autotuner.  Tries every threshold from "all terms in FP32" down
+ * to 0 (no FP32 term: the exact FP64 split) on the device vector psi
+ * (complex128[N_cs], not modified), measures the relative 2-norm error of the
+ * SG_MIXED apply against the SG_FP64 apply and the time of `reps` applies,
+ * and keeps the fastest threshold whose error is at most tol/2.  Threshold 0
+ * always qualifies (its error is FP64 rounding).  Writes the choice and its
+ * measured error (both nullable).  Synchronises `stream`; uses the handle's
+ * work buffers. */
+sg_status sg_tune_mixed(sg_problem *p, const void *psi, double tol, int32_t reps,
+                        int32_t *chosen, double *chosen_error, void *stream);
+
 /* Per-kernel timing for measurement.  sg_set_timing(p, 1) resets the
  * counters and brackets every term-sweep and reduce launch made through this
  * handle with a pair of HIP events on the launch stream (the events add a

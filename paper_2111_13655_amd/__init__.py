@@ -89,6 +89,10 @@ class Timing(ctypes.Structure):
 _P = ctypes.c_void_p
 _SIGNATURES = {
     "sg_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "sg_set_mixed_threshold": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "sg_tune_mixed": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_double), _P]),
     "sg_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(Timing)]),
     "sg_last_error": (ctypes.c_char_p, []),
     "sg_count_sizes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -278,6 +282,20 @@ def sg_propagate_chebyshev(h, psi, dt: float, nsteps: int, emin=math.nan, emax=m
     d = st.as_dict()
     n = min(ntr, (d["steps_done"] // check_every + 2) if check_every > 0 else 2)
     return status, d, nt[:n], et[:n]
+
+
+def sg_set_mixed_threshold(h, max_fp32_coeff: int) -> None:
+    _check(lib().sg_set_mixed_threshold(h, int(max_fp32_coeff)))
+
+
+def sg_tune_mixed(h, psi, tol: float = 1e-6, reps: int = 3, stream=None):
+    """Returns (chosen threshold, its measured relative error)."""
+    n_cs = sg_problem_info(h)["n_cs"]
+    ch = ctypes.c_int32()
+    er = ctypes.c_double()
+    _check(lib().sg_tune_mixed(h, _vec_ptr(psi, n_cs, "psi"), float(tol), int(reps),
+                               ctypes.byref(ch), ctypes.byref(er), _stream_ptr(stream)))
+    return ch.value, er.value
 
 
 def sg_set_timing(h, enable: bool) -> None:

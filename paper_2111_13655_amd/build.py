@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "libsg.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
 SOURCES = ["sg_terms.cpp", "sg_tables.cpp", "sg_api.cpp", "sg_cheb.cpp",
-           "sg_kernels.hip"]
+           "sg_tune.cpp", "sg_sweep.hip", "sg_reduce.hip"]
 
 ARCH = os.environ.get("SG_OFFLOAD_ARCH", "gfx950")
 

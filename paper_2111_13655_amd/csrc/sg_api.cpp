@@ -79,11 +79,16 @@ void release(sg_problem *p) {
   }
   for (hipEvent_t ev : p->timing.ev) hipEventDestroy(ev);
   hipFree(p->d_terms);
-  hipFree(p->d_sched);
+  hipFree(p->d_packs);
+  hipFree(p->d_tables32);
+  hipFree(p->d_tables32r);
   hipFree(p->d_mb);
   hipFree(p->d_inv_ptr);
   hipFree(p->d_inv_col);
+  hipFree(p->d_rows);
   hipFree(p->d_tables);
+  hipFree(p->d_lvt);
+  hipFree(p->d_pairs);
   hipFree(p->d_h0);
   hipFree(p->d_c);
   hipFree(p->d_k);
@@ -151,11 +156,18 @@ sg_status sg_build_terms(const sg_problem_desc *desc, sg_problem **out) {
   e = upload(&p->dst, (vec).data(), (vec).size(), &bytes);               \
   if (e != hipSuccess) { release(p); return hip_fail(e, "upload " #dst); }
   SG_UP(d_terms, h.terms)
-  SG_UP(d_sched, h.sched)
+  SG_UP(d_packs, h.packs)
+  p->d_packs_capacity = (int64_t)h.packs.size();
+  SG_UP(d_tables32, h.tables32)
+  SG_UP(d_tables32r, h.tables32r)
   SG_UP(d_mb, h.MB)
   SG_UP(d_inv_ptr, h.inv_ptr)
   SG_UP(d_inv_col, h.inv_col)
+  SG_UP(d_rows, h.rows)
   SG_UP(d_tables, h.tables)
+  SG_UP(d_pairs, h.pairs)
+  e = upload(&p->d_lvt, h.tdesc.lev, kMaxLevels, &bytes);
+  if (e != hipSuccess) { release(p); return hip_fail(e, "upload level tables"); }
   SG_UP(d_h0, h.h0)
   SG_UP(d_c, h.c)
   SG_UP(d_k, h.k)
@@ -168,7 +180,7 @@ sg_status sg_build_terms(const sg_problem_desc *desc, sg_problem **out) {
   e = hipMalloc((void **)&p->d_work, work_bytes);
   if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation of work vectors failed"); }
   bytes += (int64_t)work_bytes;
-  p->n_partials = (int)std::max<int64_t>((h.ncs + 3) / 4, 256);
+  p->n_partials = (int)std::max<int64_t>(reduce_blocks(p), 256);
   e = hipMalloc((void **)&p->d_partials, 2 * (size_t)p->n_partials * sizeof(double));
   if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
   bytes += 2 * (int64_t)p->n_partials * sizeof(double);
@@ -304,6 +316,27 @@ sg_status sg_apply_H(sg_problem *p, const void *psi_in, void *psi_out, sg_precis
   ca.split = prec == SG_MIXED ? 1 : 0;
   e = run_reduce(p, Epi::Apply, (const double2 *)psi_in, (double2 *)psi_out, &ca, s);
   if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  return SG_OK;
+}
+
+sg_status sg_set_mixed_threshold(sg_problem *p, int32_t max_fp32_coeff) {
+  if (!p) return fail(SG_EINVAL, "NULL problem");
+  if (max_fp32_coeff < 0) return fail(SG_EINVAL, "threshold must be >= 0");
+  p->h.mixed_max_fp32_coeff = max_fp32_coeff;
+  std::string err;
+  sg_status st = build_pack_sets(&p->h, &err);
+  if (st != SG_OK) return fail(st, err);
+  if (p->host_only) return SG_OK;
+  if ((int64_t)p->h.packs.size() > p->d_packs_capacity) {
+    hipFree(p->d_packs);
+    p->d_packs = nullptr;
+    hipError_t e = hipMalloc((void **)&p->d_packs, p->h.packs.size() * sizeof(PackDev));
+    if (e != hipSuccess) return fail(SG_ENOMEM, "device allocation of packs failed");
+    p->d_packs_capacity = (int64_t)p->h.packs.size();
+  }
+  hipError_t e = hipMemcpy(p->d_packs, p->h.packs.data(), p->h.packs.size() * sizeof(PackDev),
+                           hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "upload packs");
   return SG_OK;
 }
 

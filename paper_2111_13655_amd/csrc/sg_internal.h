@@ -20,6 +20,14 @@ constexpr int kMaxN = 16;
 // Per-term operator description, one per Smolyak term, in canonical (Table 2)
 // term order.  Level-0 modes are integrated out exactly (see term compiler),
 // so a term only carries its active modes.
+// Everything a kernel needs about a term sits at constant offsets here (and in
+// the term's pair-coefficient block), so a workgroup issues independent
+// scalar loads instead of chains of dependent ones.
+constexpr int kMaxPairs = kMaxActive * (kMaxActive - 1) / 2;
+__host__ __device__ constexpr int pair_index(int q, int r) {  // q < r < kMaxActive
+  return q * (2 * kMaxActive - q - 1) / 2 + (r - q - 1);
+}
+
 struct alignas(16) TermDev {
   int32_t off;       // start of the term in the term-major layout (N_s)
   int32_t nbasis;    // prod over active modes of nb
@@ -27,6 +35,13 @@ struct alignas(16) TermDev {
   int32_t na;        // number of active modes
   int8_t lev[kMaxActive];   // levels of the active modes, increasing mode id
   int8_t mode[kMaxActive];  // their mode ids
+  int32_t nb[kMaxActive];   // per active mode: basis size
+  int32_t nq[kMaxActive];   //   grid size
+  int32_t bt[kMaxActive];   //   offsets of its level's tables in the table array
+  int32_t wt[kMaxActive];
+  int32_t kg[kMaxActive];
+  int32_t xo[kMaxActive];
+  float rcp_nq[kMaxActive]; //   1/nq for fast index division
   double coeff;             // D_l
   double c0_full;           // constant part of the effective potential, FP64 path
   double c0_split;          // ... without the harmonic part (mixed path)
@@ -46,6 +61,30 @@ struct LevelDev {
 };
 
 constexpr int kMaxLevels = 16;
+
+// Term-sweep packing.  A workgroup (512 threads) runs one pack: one term with
+// more than kWaveMaxGrid grid points on all its wavefronts, or up to
+// kPackTerms smaller terms, one per wavefront.
+constexpr int kPackTerms = 8;
+constexpr int kWaveMaxGrid = 512;
+constexpr int kLdsPerCU = 160 * 1024;
+constexpr int kComputeUnits = 256;   // MI355X; used to size the packing only
+struct PackDev {
+  int32_t n;                  // terms in the pack
+  int32_t block;              // 1: term[0] runs on the whole workgroup
+  int32_t term[kPackTerms];
+  int32_t lds_off[kPackTerms];  // byte offset of each wavefront's LDS slice
+};
+struct PackSet {
+  int32_t first = 0;          // index of the first pack
+  int32_t count = 0;
+  int32_t lds_bytes = 0;      // dynamic LDS of the launch
+};
+// Pack sets: FP64 path (all terms), mixed path FP64 terms, mixed path FP32 terms.
+constexpr int kPackSets = 3;
+// Rows of the inverse mapping longer than this are reduced by a whole
+// wavefront, shorter ones by a group of 8 lanes.
+constexpr int kLongRow = 64;
 
 struct DeviceTables {
   LevelDev lev[kMaxLevels];
@@ -73,7 +112,16 @@ struct Compiled {
   std::vector<double> tables;
   DeviceTables tdesc;
   std::vector<TermDev> terms;        // [nterms]
-  std::vector<int32_t> sched;        // term ids, most expensive first
+  std::vector<double> pairs;         // [nterms][kMaxPairs][2]: c_pq, k_pq of active pairs
+  std::vector<float> tables32;       // the same tables in FP32 (mixed path)
+  std::vector<double> tables32r;     // FP32-rounded tables held in FP64 (mixed-path
+                                     // FP64 terms: same operator as the FP32 terms)
+  std::vector<double> cost;          // estimated work per term
+  std::vector<PackDev> packs;        // all pack sets, concatenated
+  PackSet sets[kPackSets];
+  int32_t mixed_max_fp32_coeff = 16; // mixed path: |D_l| at most this -> FP32
+  std::vector<int32_t> rows;         // compact rows, long rows first
+  int64_t n_long_rows = 0;
   // sizes
   int64_t grid_literal = 0, grid_active = 0, max_basis = 0, max_grid = 0;
   double flops_fp64 = 0, flops_mixed = 0, bytes_apply = 0;
@@ -83,6 +131,9 @@ struct Compiled {
 sg_status compile_problem(const sg_problem_desc *desc, Compiled *out,
                           std::string *err);
 sg_status count_sizes(int D, int L, int nbA, int nbB, int64_t out[3]);
+// (Re)builds the three pack sets from the term records and the mixed-path
+// coefficient threshold.
+sg_status build_pack_sets(Compiled *h, std::string *err);
 
 // One-mode tables (sg_tables.cpp)
 void gauss_hermite_nodes(int n, std::vector<double> *x, std::vector<double> *wt);
@@ -105,11 +156,17 @@ struct sg_problem {
   bool host_only = false;          // built without device tables
   // device tables
   sg::TermDev *d_terms = nullptr;
-  int32_t *d_sched = nullptr;
+  sg::PackDev *d_packs = nullptr;
+  int64_t d_packs_capacity = 0;
+  float *d_tables32 = nullptr;
+  double *d_tables32r = nullptr;
   int32_t *d_mb = nullptr;
   int32_t *d_inv_ptr = nullptr;
   int32_t *d_inv_col = nullptr;
+  int32_t *d_rows = nullptr;
   double *d_tables = nullptr;
+  sg::LevelDev *d_lvt = nullptr;   // [kMaxLevels]
+  double *d_pairs = nullptr;       // [nterms][kMaxPairs][2]
   double *d_h0 = nullptr;
   double *d_c = nullptr;           // [D*D]
   double *d_k = nullptr;           // [D*D]
@@ -163,7 +220,7 @@ hipError_t launch_dot(const sg_problem *p, const double2 *a, const double2 *b,
                       hipStream_t s);  // result in d_result[0..1] (re, im)
 hipError_t launch_axpby(int64_t n, double2 *y, const double2 *x, double a_re,
                         double a_im, double b, hipStream_t s);  // y = a x + b y
-int sweep_lds_bytes(const sg_problem *p, sg_precision prec);
+int64_t reduce_blocks(const sg_problem *p);
 
 // Launch with optional event timing (sg_api.cpp); the drivers use these.
 hipError_t run_sweep(sg_problem *p, const double2 *psi, sg_precision prec, hipStream_t s);

@@ -1,0 +1,554 @@
+// Term sweep of the Smolyak operator action (Alg. 1, Sec. 3) for gfx950.
+//
+// One launch covers every term.  A workgroup of 512 threads runs a "pack":
+// either one large term processed by all eight wavefronts, or up to eight
+// small terms processed one per wavefront with wave-level synchronisation.
+// The host packs terms by LDS need and estimated cost (longest first), so a
+// single dispatch fills the chip without charging small terms the LDS of the
+// largest one.  For one term:
+//   1. gather through M^B fused with the basis -> grid contraction of the
+//      first active mode (each thread loads whole fibers straight from HBM);
+//   2. basis -> grid along the remaining active modes (eq_transfer_b_to_g),
+//      ping-ponging between two LDS buffers;
+//   3. the operator on the grid: the effective potential (closed form, per
+//      fiber) fused with the kinetic second-derivative matrix of the first
+//      mode, then the kinetic matrices of the other modes accumulated (the
+//      mixed path carries no harmonic part and no kinetic term here: that part
+//      is diagonal and is added exactly in the reduce);
+//   4. grid -> basis (eq_transfer_g_to_b); the last mode's contraction writes
+//      D_l times the result, in FP64, straight to the term-major buffer.
+// Every contraction gives one thread a whole fiber along the contracted mode:
+// the fiber sits in registers and the one-mode matrix is wave-uniform, so its
+// entries arrive through scalar loads.  Per-term data sit at constant offsets
+// of the term record, so a wave issues independent scalar loads.
+// The arithmetic type R is double (FP64 path, and the high-|D_l| terms of the
+// mixed path) or float (the other terms of the mixed path).
+#include "sg_internal.h"
+
+namespace sg {
+
+namespace {
+
+constexpr int kThreads = 512;
+
+struct SweepArgs {
+  const TermDev *terms;
+  const PackDev *packs;
+  const int32_t *mb;
+  const double2 *psi;
+  double2 *tm;
+  const void *tab;       // one-mode tables in the arithmetic type
+  const double *pairs;
+  int std_maps;          // nb = 1 + 2l, nq = 2 + 2l
+  int split;             // operator without the separable harmonic part
+  int round32;           // FP64 arithmetic on FP32-rounded tables and coefficients
+};
+
+template <typename R> struct Cx;
+template <> struct Cx<double> {
+  typedef double2 T;
+  static __device__ __forceinline__ double2 make(double a, double b) { return make_double2(a, b); }
+};
+template <> struct Cx<float> {
+  typedef float2 T;
+  static __device__ __forceinline__ float2 make(float a, float b) { return make_float2(a, b); }
+};
+
+// Threads of one term: a single wavefront, or the whole workgroup.
+struct WaveGroup {
+  static constexpr int N = 64;
+  static __device__ __forceinline__ int tid() { return threadIdx.x & 63; }
+  static __device__ __forceinline__ void sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+};
+struct BlockGroup {
+  static constexpr int N = kThreads;
+  static __device__ __forceinline__ int tid() { return threadIdx.x; }
+  static __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+
+// floor(f / d) for 0 <= f, d < 2^20 via a float reciprocal (exact in this
+// range: f + 0.5 is at least 0.5 away from any multiple of d).
+__device__ __forceinline__ int fdiv(int f, float rcp) {
+  return __float2int_rz(((float)f + 0.5f) * rcp);
+}
+
+// A wave-uniform pointer re-derived inside a divergent loop, in the constant
+// (read-only global) address space.  readfirstlane is convergent, so it and
+// the scalar loads through the pointer stay in the loop body; hoisting all
+// matrix entries out of the fiber loop would spill them.
+template <typename R>
+using cptr = const __attribute__((address_space(4))) R *;
+template <typename R>
+__device__ __forceinline__ cptr<R> in_loop_uniform(const R *p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (cptr<R>)(((uint64_t)hi << 32) | lo);
+}
+
+// Compile-time size when N_ > 0, run-time size n otherwise (loops are then
+// unrolled to kMaxN with guards so that fibers stay in registers).
+#define SG_CN(N_) ((N_) > 0 ? (N_) : kMaxN)
+#define SG_IN(N_, k, n) ((N_) > 0 || (k) < (n))
+
+// ---------------------------------------------------------------------------
+// One-mode contraction over fibers.  Layout: out[lo + stride*(u + NO*hi)]
+// (+)= scale * sum_k M[u*NI + k] in[lo + stride*(k + NI*hi)].
+// ---------------------------------------------------------------------------
+template <typename G, typename R, int NI_, int NO_, bool ACC>
+__device__ __forceinline__ void contract(const typename Cx<R>::T *__restrict__ in,
+                                         typename Cx<R>::T *__restrict__ out,
+                                         const R *__restrict__ M, R scale, int ni, int no,
+                                         int stride, int nouter) {
+  typedef typename Cx<R>::T C;
+  const int NI = NI_ > 0 ? NI_ : ni;
+  const int NO = NO_ > 0 ? NO_ : no;
+  const int F = stride * nouter;
+  const float rcp = 1.0f / (float)stride;
+  for (int f = G::tid(); f < F; f += G::N) {
+    const int hi = fdiv(f, rcp);
+    const int lo = f - hi * stride;
+    const C *src = in + lo + hi * (stride * NI);
+    C *dst = out + lo + hi * (stride * NO);
+    const cptr<R> Mw = in_loop_uniform(M);
+    C x[SG_CN(NI_)];
+#pragma unroll
+    for (int k = 0; k < SG_CN(NI_); ++k) x[k] = SG_IN(NI_, k, NI) ? src[k * stride] : Cx<R>::make(0, 0);
+#pragma unroll 1
+    for (int u = 0; u < NO; ++u) {
+      R re = 0, im = 0;
+#pragma unroll
+      for (int k = 0; k < SG_CN(NI_); ++k) {
+        if (SG_IN(NI_, k, NI)) {
+          const R m = Mw[u * NI + k];
+          re = fma(m, x[k].x, re);
+          im = fma(m, x[k].y, im);
+        }
+      }
+      if (ACC) {
+        C o = dst[u * stride];
+        o.x = fma(scale, re, o.x);
+        o.y = fma(scale, im, o.y);
+        dst[u * stride] = o;
+      } else {
+        dst[u * stride] = Cx<R>::make(re, im);
+      }
+    }
+  }
+}
+
+// kind 0: basis -> grid (NI = nb, NO = nq); 1: kinetic on the grid
+// (NI = NO = nq); 2: grid -> basis (NI = nq, NO = nb)
+template <typename G, typename R, bool ACC>
+__device__ __forceinline__ void contract_level(int kind, int level, int std_maps, int nb, int nq,
+                                               const typename Cx<R>::T *in,
+                                               typename Cx<R>::T *out, const R *M, R scale,
+                                               int stride, int nouter) {
+  if (std_maps) {
+#define SG_CASE(L_, NB_, NQ_)                                                                    \
+  case L_:                                                                                       \
+    if (kind == 0) contract<G, R, NB_, NQ_, ACC>(in, out, M, scale, nb, nq, stride, nouter);    \
+    else if (kind == 1) contract<G, R, NQ_, NQ_, ACC>(in, out, M, scale, nq, nq, stride, nouter); \
+    else contract<G, R, NQ_, NB_, ACC>(in, out, M, scale, nq, nb, stride, nouter);              \
+    return;
+    switch (level) {
+      SG_CASE(1, 3, 4)
+      SG_CASE(2, 5, 6)
+      SG_CASE(3, 7, 8)
+      SG_CASE(4, 9, 10)
+      SG_CASE(5, 11, 12)
+      SG_CASE(6, 13, 14)
+      SG_CASE(7, 15, 16)
+      default: break;
+    }
+#undef SG_CASE
+  }
+  const int NI = kind == 0 ? nb : nq;
+  const int NO = kind == 2 ? nb : nq;
+  contract<G, R, 0, 0, ACC>(in, out, M, scale, NI, NO, stride, nouter);
+}
+
+// ---------------------------------------------------------------------------
+// Step 1 fused with the first basis -> grid contraction: fibers along mode 0
+// are contiguous runs of the term-major layout, so each thread gathers its
+// fiber through M^B and writes the nq transformed values to LDS.
+// ---------------------------------------------------------------------------
+template <typename G, typename R, int NI_, int NO_>
+__device__ __forceinline__ void gather_b2g_impl(const SweepArgs &a, int off, int nfib, int ni,
+                                                int no, const R *__restrict__ M,
+                                                typename Cx<R>::T *__restrict__ out) {
+  typedef typename Cx<R>::T C;
+  const int NI = NI_ > 0 ? NI_ : ni;
+  const int NO = NO_ > 0 ? NO_ : no;
+  for (int f = G::tid(); f < nfib; f += G::N) {
+    const int32_t *mb = a.mb + off + f * NI;
+    const cptr<R> Mw = in_loop_uniform(M);
+    C x[SG_CN(NI_)];
+#pragma unroll
+    for (int k = 0; k < SG_CN(NI_); ++k) {
+      if (SG_IN(NI_, k, NI)) {
+        const double2 v = a.psi[mb[k]];
+        x[k] = Cx<R>::make((R)v.x, (R)v.y);
+      } else {
+        x[k] = Cx<R>::make(0, 0);
+      }
+    }
+    C *dst = out + f * NO;
+#pragma unroll 1
+    for (int u = 0; u < NO; ++u) {
+      R re = 0, im = 0;
+#pragma unroll
+      for (int k = 0; k < SG_CN(NI_); ++k) {
+        if (SG_IN(NI_, k, NI)) {
+          const R m = Mw[u * NI + k];
+          re = fma(m, x[k].x, re);
+          im = fma(m, x[k].y, im);
+        }
+      }
+      dst[u] = Cx<R>::make(re, im);
+    }
+  }
+}
+
+template <typename G, typename R>
+__device__ __forceinline__ void gather_b2g(const SweepArgs &a, int level, int nb, int nq, int off,
+                                           int nfib, const R *M, typename Cx<R>::T *out) {
+  if (a.std_maps) {
+    switch (level) {
+      case 1: gather_b2g_impl<G, R, 3, 4>(a, off, nfib, nb, nq, M, out); return;
+      case 2: gather_b2g_impl<G, R, 5, 6>(a, off, nfib, nb, nq, M, out); return;
+      case 3: gather_b2g_impl<G, R, 7, 8>(a, off, nfib, nb, nq, M, out); return;
+      case 4: gather_b2g_impl<G, R, 9, 10>(a, off, nfib, nb, nq, M, out); return;
+      case 5: gather_b2g_impl<G, R, 11, 12>(a, off, nfib, nb, nq, M, out); return;
+      case 6: gather_b2g_impl<G, R, 13, 14>(a, off, nfib, nb, nq, M, out); return;
+      case 7: gather_b2g_impl<G, R, 15, 16>(a, off, nfib, nb, nq, M, out); return;
+      default: break;
+    }
+  }
+  gather_b2g_impl<G, R, 0, 0>(a, off, nfib, nb, nq, M, out);
+}
+
+// ---------------------------------------------------------------------------
+// Step 4's last contraction: grid -> basis along the slowest active mode
+// (nouter = 1), written as D_l * result in FP64 to the term-major buffer.
+// ---------------------------------------------------------------------------
+template <typename G, typename R, int NI_, int NO_>
+__device__ __forceinline__ void g2b_store_impl(const typename Cx<R>::T *__restrict__ in,
+                                               double2 *__restrict__ tm,
+                                               const R *__restrict__ M, double cf, int ni,
+                                               int no, int stride) {
+  typedef typename Cx<R>::T C;
+  const int NI = NI_ > 0 ? NI_ : ni;
+  const int NO = NO_ > 0 ? NO_ : no;
+  for (int lo = G::tid(); lo < stride; lo += G::N) {
+    const cptr<R> Mw = in_loop_uniform(M);
+    C x[SG_CN(NI_)];
+#pragma unroll
+    for (int k = 0; k < SG_CN(NI_); ++k)
+      x[k] = SG_IN(NI_, k, NI) ? in[lo + k * stride] : Cx<R>::make(0, 0);
+#pragma unroll 1
+    for (int u = 0; u < NO; ++u) {
+      R re = 0, im = 0;
+#pragma unroll
+      for (int k = 0; k < SG_CN(NI_); ++k) {
+        if (SG_IN(NI_, k, NI)) {
+          const R m = Mw[u * NI + k];
+          re = fma(m, x[k].x, re);
+          im = fma(m, x[k].y, im);
+        }
+      }
+      tm[lo + u * stride] = make_double2(cf * (double)re, cf * (double)im);
+    }
+  }
+}
+
+template <typename G, typename R>
+__device__ __forceinline__ void g2b_store(int std_maps, int level, int nb, int nq,
+                                          const typename Cx<R>::T *in, double2 *tm, const R *M,
+                                          double cf, int stride) {
+  if (std_maps) {
+    switch (level) {
+      case 1: g2b_store_impl<G, R, 4, 3>(in, tm, M, cf, nq, nb, stride); return;
+      case 2: g2b_store_impl<G, R, 6, 5>(in, tm, M, cf, nq, nb, stride); return;
+      case 3: g2b_store_impl<G, R, 8, 7>(in, tm, M, cf, nq, nb, stride); return;
+      case 4: g2b_store_impl<G, R, 10, 9>(in, tm, M, cf, nq, nb, stride); return;
+      case 5: g2b_store_impl<G, R, 12, 11>(in, tm, M, cf, nq, nb, stride); return;
+      case 6: g2b_store_impl<G, R, 14, 13>(in, tm, M, cf, nq, nb, stride); return;
+      case 7: g2b_store_impl<G, R, 16, 15>(in, tm, M, cf, nq, nb, stride); return;
+      default: break;
+    }
+  }
+  g2b_store_impl<G, R, 0, 0>(in, tm, M, cf, nq, nb, stride);
+}
+
+// ---------------------------------------------------------------------------
+// Step 3, first part: dst = V_eff * src (+ kin_0 K_0 x_0 src on the FP64
+// path) over fibers along mode 0.  Along one fiber only Q_0 varies, so the
+// potential is A + B Q_0^2 + C Q_0 with A, B, C computed once per fiber from
+// V_eff = c0 + sum_p (alpha_p Q_p^2 + beta_p Q_p)
+//       + sum_{p<q} (c_pq Q_p^2 Q_q^2 + k_pq Q_p^2 Q_q).
+// ---------------------------------------------------------------------------
+template <typename G, typename R, int NQ_, bool KIN>
+__device__ __forceinline__ void potential_impl(const SweepArgs &a, const TermDev *T,
+                                               const typename Cx<R>::T *__restrict__ src,
+                                               typename Cx<R>::T *__restrict__ dst, int nfib) {
+  typedef typename Cx<R>::T C;
+  const R *tab = (const R *)a.tab;
+  const int na = T->na;
+  const int NQ = NQ_ > 0 ? NQ_ : T->nq[0];
+  const R *x0 = tab + T->xo[0];
+  const R *K0 = tab + T->kg[0];
+  const R kin0 = (R)T->kin[0];
+  const bool split = a.split != 0;
+  // mixed-path FP64 terms round coefficients as the FP32 terms do
+  const bool r32 = a.round32 != 0;
+  auto cv = [r32](double v) -> R { return (R)(r32 ? (double)(float)v : v); };
+  const R c0 = cv(split ? T->c0_split : T->c0_full);
+  const R al0 = cv(split ? T->alpha_split[0] : T->alpha_full[0]);
+  const R be0 = cv(T->beta[0]);
+  const double *pc = a.pairs + (size_t)(T - a.terms) * (2 * kMaxPairs);
+  for (int f = G::tid(); f < nfib; f += G::N) {
+    R xq[kMaxActive];
+    int rem = f;
+#pragma unroll
+    for (int q = 1; q < kMaxActive; ++q) {
+      xq[q] = 0;
+      if (q < na) {
+        const int hi = fdiv(rem, T->rcp_nq[q]);
+        const int u = rem - hi * T->nq[q];
+        rem = hi;
+        xq[q] = tab[T->xo[q] + u];
+      }
+    }
+    R A = c0, B = al0, Cc = be0;
+#pragma unroll
+    for (int q = 1; q < kMaxActive; ++q) {
+      if (q < na) {
+        const R x2 = xq[q] * xq[q];
+        const R alq = cv(split ? T->alpha_split[q] : T->alpha_full[q]);
+        A = fma(alq, x2, A);
+        A = fma(cv(T->beta[q]), xq[q], A);
+        B = fma(cv(pc[2 * pair_index(0, q)]), x2, B);
+        B = fma(cv(pc[2 * pair_index(0, q) + 1]), xq[q], B);
+#pragma unroll
+        for (int r = q + 1; r < kMaxActive; ++r) {
+          if (r < na) {
+            A = fma(cv(pc[2 * pair_index(q, r)]) * x2, xq[r] * xq[r], A);
+            A = fma(cv(pc[2 * pair_index(q, r) + 1]) * x2, xq[r], A);
+          }
+        }
+      }
+    }
+    const C *s = src + f * NQ;
+    C *d = dst + f * NQ;
+    const cptr<R> Kw = in_loop_uniform(K0);
+    const cptr<R> xw = in_loop_uniform(x0);
+    C x[SG_CN(NQ_)];
+    if (KIN) {
+#pragma unroll
+      for (int u = 0; u < SG_CN(NQ_); ++u) x[u] = SG_IN(NQ_, u, NQ) ? s[u] : Cx<R>::make(0, 0);
+    }
+#pragma unroll 1
+    for (int u = 0; u < NQ; ++u) {
+      const R xv = xw[u];
+      const R V = fma(fma(B, xv, Cc), xv, A);
+      const C xu = s[u];
+      R re = V * xu.x, im = V * xu.y;
+      if (KIN) {
+        R kr = 0, ki = 0;
+#pragma unroll
+        for (int k = 0; k < SG_CN(NQ_); ++k) {
+          if (SG_IN(NQ_, k, NQ)) {
+            const R m = Kw[u * NQ + k];
+            kr = fma(m, x[k].x, kr);
+            ki = fma(m, x[k].y, ki);
+          }
+        }
+        re = fma(kin0, kr, re);
+        im = fma(kin0, ki, im);
+      }
+      d[u] = Cx<R>::make(re, im);
+    }
+  }
+}
+
+template <typename G, typename R>
+__device__ __forceinline__ void potential(const SweepArgs &a, const TermDev *T, int level0,
+                                          const typename Cx<R>::T *src, typename Cx<R>::T *dst,
+                                          int nfib) {
+  const bool kin = a.split == 0;
+  if (a.std_maps) {
+#define SG_PCASE(L_, NQ_)                                                   \
+  case L_:                                                                  \
+    if (kin) potential_impl<G, R, NQ_, true>(a, T, src, dst, nfib);         \
+    else potential_impl<G, R, NQ_, false>(a, T, src, dst, nfib);            \
+    return;
+    switch (level0) {
+      SG_PCASE(1, 4)
+      SG_PCASE(2, 6)
+      SG_PCASE(3, 8)
+      SG_PCASE(4, 10)
+      SG_PCASE(5, 12)
+      SG_PCASE(6, 14)
+      SG_PCASE(7, 16)
+      default: break;
+    }
+#undef SG_PCASE
+  }
+  if (kin) potential_impl<G, R, 0, true>(a, T, src, dst, nfib);
+  else potential_impl<G, R, 0, false>(a, T, src, dst, nfib);
+}
+
+// The whole of Alg. 1 for one term, by the threads of G, with two LDS
+// buffers of `buf` complex values each.
+template <typename G, typename R>
+__device__ __forceinline__ void run_term(const SweepArgs &a, const TermDev *T,
+                                         typename Cx<R>::T *lds, int buf) {
+  typedef typename Cx<R>::T C;
+  const R *tab = (const R *)a.tab;
+  const int na = T->na;
+  const int nbasis = T->nbasis;
+  const int ngrid = T->ngrid;
+  const int off = T->off;
+  const double cf = T->coeff;
+  if (na == 0) {  // every mode at a one-function level: a scalar term
+    if (G::tid() == 0) {
+      const double c0 = a.split ? T->c0_split : T->c0_full;
+      const double2 x = a.psi[a.mb[off]];
+      a.tm[off] = make_double2(cf * c0 * x.x, cf * c0 * x.y);
+    }
+    return;
+  }
+  C *src = lds, *dst = lds + buf;
+
+  // steps 1-2: gather + basis -> grid along mode 0, then the other modes
+  {
+    const int nb0 = T->nb[0], nq0 = T->nq[0];
+    gather_b2g<G, R>(a, T->lev[0], nb0, nq0, off, nbasis / nb0, tab + T->bt[0], src);
+    G::sync();
+    int stride = nq0;
+    int nouter = nbasis / nb0;
+    for (int p = 1; p < na; ++p) {
+      const int nb = T->nb[p], nq = T->nq[p];
+      nouter /= nb;
+      contract_level<G, R, false>(0, T->lev[p], a.std_maps, nb, nq, src, dst, tab + T->bt[p],
+                                  (R)1, stride, nouter);
+      G::sync();
+      C *tmp = src; src = dst; dst = tmp;
+      stride *= nq;
+    }
+  }
+  // step 3: potential (+ mode-0 kinetic), then the other modes' kinetic
+  {
+    const int nq0 = T->nq[0];
+    potential<G, R>(a, T, T->lev[0], src, dst, ngrid / nq0);
+    G::sync();
+    if (!a.split) {
+      int stride = nq0;
+      int nouter = ngrid / nq0;
+      for (int p = 1; p < na; ++p) {
+        const int nb = T->nb[p], nq = T->nq[p];
+        nouter /= nq;
+        contract_level<G, R, true>(1, T->lev[p], a.std_maps, nb, nq, src, dst, tab + T->kg[p],
+                                   (R)T->kin[p], stride, nouter);
+        G::sync();
+        stride *= nq;
+      }
+    }
+    C *tmp = src; src = dst; dst = tmp;
+  }
+  // step 4: grid -> basis; the last mode writes D_l * result to HBM
+  {
+    int stride = 1;
+    int nouter = ngrid;
+    for (int p = 0; p < na - 1; ++p) {
+      const int nb = T->nb[p], nq = T->nq[p];
+      nouter /= nq;
+      contract_level<G, R, false>(2, T->lev[p], a.std_maps, nb, nq, src, dst, tab + T->wt[p],
+                                  (R)1, stride, nouter);
+      G::sync();
+      C *tmp = src; src = dst; dst = tmp;
+      stride *= nb;
+    }
+    const int p = na - 1;
+    g2b_store<G, R>(a.std_maps, T->lev[p], T->nb[p], T->nq[p], src, a.tm + off, tab + T->wt[p],
+                    cf, stride);
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
+  extern __shared__ char lds_raw[];
+  typedef typename Cx<R>::T C;
+  const PackDev *P = a.packs + blockIdx.x;
+  if (P->block) {
+    const TermDev *T = a.terms + P->term[0];
+    run_term<BlockGroup, R>(a, T, (C *)lds_raw, T->ngrid);
+    return;
+  }
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (w >= P->n) return;
+  const TermDev *T = a.terms + P->term[w];
+  run_term<WaveGroup, R>(a, T, (C *)(lds_raw + P->lds_off[w]), T->ngrid);
+}
+
+template <typename R>
+hipError_t launch_packs(const SweepArgs &a, int npacks, int lds, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)sweep_kernel<R>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(sweep_kernel<R>, dim3((unsigned)npacks), dim3(kThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sweep(const sg_problem *p, const double2 *psi, sg_precision prec,
+                        hipStream_t s) {
+  SweepArgs a;
+  a.terms = p->d_terms;
+  a.mb = p->d_mb;
+  a.psi = psi;
+  a.tm = p->d_tm;
+  a.pairs = p->d_pairs;
+  a.std_maps = (p->h.nbA == 1 && p->h.nbB == 2 && p->h.nqA == 2 && p->h.nqB == 2) ? 1 : 0;
+  a.split = prec == SG_MIXED ? 1 : 0;
+  // FP64 terms of a mixed launch use the FP32-rounded tables, so that every
+  // term applies the same one-mode operators and the Smolyak combination
+  // cancels their rounding as it does when all terms run in FP32; with no
+  // FP32 term at all, the exact tables are used.
+  const bool any32 = p->h.sets[2].count > 0;
+  a.round32 = (prec == SG_MIXED && any32) ? 1 : 0;
+  hipError_t e = hipSuccess;
+  if (prec == SG_FP64) {
+    const PackSet &ps = p->h.sets[0];
+    if (ps.count == 0) return hipSuccess;
+    a.packs = p->d_packs + ps.first;
+    a.tab = p->d_tables;
+    return launch_packs<double>(a, ps.count, ps.lds_bytes, s);
+  }
+  // mixed: terms with large |D_l| in FP64, the rest in FP32
+  const PackSet &p64 = p->h.sets[1], &p32 = p->h.sets[2];
+  if (p64.count > 0) {
+    a.packs = p->d_packs + p64.first;
+    a.tab = any32 ? p->d_tables32r : p->d_tables;
+    e = launch_packs<double>(a, p64.count, p64.lds_bytes, s);
+    if (e != hipSuccess) return e;
+  }
+  if (p32.count > 0) {
+    a.packs = p->d_packs + p32.first;
+    a.tab = p->d_tables32;
+    e = launch_packs<float>(a, p32.count, p32.lds_bytes, s);
+  }
+  return e;
+}
+
+}  // namespace sg

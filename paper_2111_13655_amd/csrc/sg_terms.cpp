@@ -321,6 +321,7 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
 
   // ---- per-term operator coefficients -------------------------------------
   h.terms.resize(h.nterms);
+  h.pairs.assign((size_t)h.nterms * kMaxPairs * 2, 0.0);
   h.grid_literal = h.grid_active = h.max_basis = h.max_grid = 0;
   h.flops_fp64 = h.flops_mixed = 0.0;
   std::vector<double> cost(h.nterms);
@@ -340,11 +341,29 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
     T.coeff = h.coeff[t];
     int64_t nbas = 1, ngr = 1;
     for (size_t p = 0; p < act.size(); ++p) {
-      T.lev[p] = (int8_t)lv[act[p]];
+      const int l = lv[act[p]];
+      T.lev[p] = (int8_t)l;
       T.mode[p] = (int8_t)act[p];
-      nbas *= size_map(h.nbA, h.nbB, lv[act[p]]);
-      ngr *= size_map(h.nqA, h.nqB, lv[act[p]]);
+      T.nb[p] = size_map(h.nbA, h.nbB, l);
+      T.nq[p] = size_map(h.nqA, h.nqB, l);
+      T.bt[p] = h.tdesc.lev[l].bt;
+      T.wt[p] = h.tdesc.lev[l].wt;
+      T.kg[p] = h.tdesc.lev[l].kg;
+      T.xo[p] = h.tdesc.lev[l].x;
+      T.rcp_nq[p] = 1.0f / (float)T.nq[p];
+      nbas *= T.nb[p];
+      ngr *= T.nq[p];
     }
+    for (size_t p = act.size(); p < (size_t)kMaxActive; ++p) {
+      T.nb[p] = T.nq[p] = 1;
+      T.rcp_nq[p] = 1.0f;
+    }
+    double *pr = &h.pairs[(size_t)t * kMaxPairs * 2];
+    for (size_t q = 0; q < act.size(); ++q)
+      for (size_t r = q + 1; r < act.size(); ++r) {
+        pr[2 * pair_index((int)q, (int)r)] = h.c[(size_t)act[q] * D + act[r]];
+        pr[2 * pair_index((int)q, (int)r) + 1] = h.k[(size_t)act[q] * D + act[r]];
+      }
     T.nbasis = (int32_t)nbas;
     T.ngrid = (int32_t)ngr;
     auto C = [&](int i, int j) { return h.c[size_t(std::min(i, j)) * D + std::max(i, j)]; };
@@ -403,11 +422,129 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
   h.bytes_apply = 32.0 * (double)h.ncs + 8.0 * (double)h.MB.size() + 4.0 * (double)h.ncs +
                   32.0 * (double)h.MB.size() + (double)sizeof(TermDev) * (double)h.nterms;
 
-  h.sched.resize(h.nterms);
-  std::iota(h.sched.begin(), h.sched.end(), 0);
-  std::stable_sort(h.sched.begin(), h.sched.end(),
-                   [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+  h.cost = cost;
+  h.tables32.assign(h.tables.begin(), h.tables.end());
+  h.tables32r.assign(h.tables32.begin(), h.tables32.end());
+  sg_status ps = build_pack_sets(&h, err);
+  if (ps != SG_OK) return ps;
+
+  // reduce rows: long rows (a wavefront each) first, then short rows
+  h.rows.clear();
+  h.rows.reserve(h.ncs);
+  for (int64_t r = 0; r < h.ncs; ++r)
+    if (h.inv_ptr[r + 1] - h.inv_ptr[r] > kLongRow) h.rows.push_back((int32_t)r);
+  h.n_long_rows = (int64_t)h.rows.size();
+  for (int64_t r = 0; r < h.ncs; ++r)
+    if (h.inv_ptr[r + 1] - h.inv_ptr[r] <= kLongRow) h.rows.push_back((int32_t)r);
   return SG_OK;
+}
+
+namespace {
+
+// Packs the given terms for one sweep launch.  Terms above kWaveMaxGrid grid
+// points get a workgroup each; the others are dealt, longest first, to the
+// least loaded of B packs of at most kPackTerms terms (one wavefront each),
+// with B large enough to give every compute unit work.  Each term needs two
+// LDS buffers of ngrid complex values of elem_bytes each.
+sg_status pack_terms(const Compiled &h, const std::vector<int32_t> &ids, int elem_bytes,
+                     std::vector<PackDev> *out, PackSet *set, std::string *err) {
+  set->first = (int32_t)out->size();
+  set->count = 0;
+  set->lds_bytes = 0;
+  if (ids.empty()) return SG_OK;
+  auto slice = [&](int32_t t) {
+    const int b = 2 * h.terms[t].ngrid * elem_bytes;
+    return (b + 15) & ~15;
+  };
+  std::vector<int32_t> big, small;
+  for (int32_t t : ids) (h.terms[t].ngrid > kWaveMaxGrid ? big : small).push_back(t);
+  auto by_cost = [&](int32_t a, int32_t b) { return h.cost[a] > h.cost[b]; };
+  std::stable_sort(big.begin(), big.end(), by_cost);
+  std::stable_sort(small.begin(), small.end(), by_cost);
+  int lds = 0;
+  for (int32_t t : big) {
+    if (slice(t) > kLdsPerCU) {
+      *err = "a term grid exceeds the on-chip buffer";
+      return SG_EINVAL;
+    }
+    lds = std::max(lds, slice(t));
+  }
+  // packs of small terms: enough of them to occupy every compute unit
+  const int64_t nsmall = (int64_t)small.size();
+  int64_t nbins = (nsmall + kPackTerms - 1) / kPackTerms;
+  const int small_lds = kPackTerms * ((2 * kWaveMaxGrid * elem_bytes + 15) & ~15);
+  const int per_cu = std::max(1, kLdsPerCU / std::max(lds, small_lds));
+  const int64_t want = (int64_t)kComputeUnits * per_cu - (int64_t)big.size();
+  nbins = std::max<int64_t>(nbins, std::min<int64_t>(nsmall, want));
+  struct Bin {
+    double load;
+    int64_t id;
+  };
+  auto worse = [](const Bin &a, const Bin &b) {
+    return a.load > b.load || (a.load == b.load && a.id > b.id);
+  };
+  std::vector<Bin> heap;
+  std::vector<PackDev> bins((size_t)nbins);
+  std::vector<int> bin_bytes((size_t)nbins, 0);
+  for (int64_t i = 0; i < nbins; ++i) {
+    std::memset(&bins[i], 0, sizeof(PackDev));
+    heap.push_back({0.0, i});
+  }
+  std::make_heap(heap.begin(), heap.end(), worse);
+  for (int32_t t : small) {
+    std::pop_heap(heap.begin(), heap.end(), worse);
+    Bin b = heap.back();
+    heap.pop_back();
+    PackDev &pk = bins[b.id];
+    pk.term[pk.n] = t;
+    pk.lds_off[pk.n] = bin_bytes[b.id];
+    bin_bytes[b.id] += slice(t);
+    pk.n += 1;
+    b.load += h.cost[t];
+    if (pk.n < kPackTerms) {
+      heap.push_back(b);
+      std::push_heap(heap.begin(), heap.end(), worse);
+    }
+  }
+  for (int32_t t : big) {
+    PackDev pk;
+    std::memset(&pk, 0, sizeof(pk));
+    pk.n = 1;
+    pk.block = 1;
+    pk.term[0] = t;
+    out->push_back(pk);
+  }
+  // small packs, most loaded first
+  std::vector<int64_t> order((size_t)nbins);
+  std::vector<double> load((size_t)nbins, 0.0);
+  for (int64_t i = 0; i < nbins; ++i) {
+    order[i] = i;
+    for (int j = 0; j < bins[i].n; ++j) load[i] += h.cost[bins[i].term[j]];
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return load[a] > load[b]; });
+  for (int64_t i : order) {
+    if (bins[i].n == 0) continue;
+    out->push_back(bins[i]);
+    lds = std::max(lds, bin_bytes[i]);
+  }
+  set->count = (int32_t)(out->size() - set->first);
+  set->lds_bytes = lds;
+  return SG_OK;
+}
+
+}  // namespace
+
+sg_status build_pack_sets(Compiled *h, std::string *err) {
+  h->packs.clear();
+  std::vector<int32_t> all, mix64, mix32;
+  for (int64_t t = 0; t < h->nterms; ++t) {
+    all.push_back((int32_t)t);
+    (std::abs(h->coeff[t]) <= h->mixed_max_fp32_coeff ? mix32 : mix64).push_back((int32_t)t);
+  }
+  sg_status st = pack_terms(*h, all, (int)sizeof(double2), &h->packs, &h->sets[0], err);
+  if (st == SG_OK) st = pack_terms(*h, mix64, (int)sizeof(double2), &h->packs, &h->sets[1], err);
+  if (st == SG_OK) st = pack_terms(*h, mix32, (int)sizeof(float2), &h->packs, &h->sets[2], err);
+  return st;
 }
 
 }  // namespace sg
