@@ -187,6 +187,81 @@ sg_status sg_propagate_chebyshev(sg_problem *p, void *psi, double dt,
                                  double *norm_trace, double *energy_trace,
                                  void *stream);
 
+/* Batched propagation of independent problems (same device).  Every
+ * Chebyshev term of every instance runs in one term-sweep launch and one
+ * reduce launch: the terms of all instances are packed together into
+ * workgroups (largest first, least-loaded pack), and the reduce work items of
+ * all instances share one grid.  Instances keep their own spectral bounds,
+ * series length and time step; an instance whose series is shorter sits out
+ * the remaining terms of a step.  Each instance's result is bitwise the one
+ * sg_propagate_chebyshev gives it alone (same per-term code, same fixed-order
+ * reduction).  The batch references the problems; they must outlive it. */
+typedef struct sg_batch sg_batch;
+sg_status sg_batch_create(sg_problem *const *problems, int32_t n, sg_batch **out);
+/* psi[i]: device complex128[N_cs(i)] of instance i, propagated in place by
+ * nsteps steps of dt[i].  emin/emax: per-instance bounds (NaN: estimated by
+ * sg_spectral_bounds).  check_every as in sg_propagate_chebyshev (norms and
+ * energies of all instances are reduced together).  stats: nullable array of
+ * n.  use_graph != 0 replays each step from a captured hipGraph (on a stream
+ * the library owns, ordered after and before `stream` by events).  Returns
+ * SG_ETOL if any instance drifts beyond tol. */
+sg_status sg_batch_propagate(sg_batch *b, void *const *psi, const double *dt, int32_t nsteps,
+                             const double *emin, const double *emax, double tol,
+                             sg_precision prec, int32_t check_every, int32_t use_graph,
+                             sg_prop_stats *stats, void *stream);
+sg_status sg_batch_free(sg_batch *b);
+
+/* Continuous-batching server of propagation requests on one device.
+ *
+ * A request is a problem description, a displaced-Gaussian initial state
+ * (shift[D]), a time step and a number of Chebyshev steps.  A scheduler
+ * thread compiles submitted requests on host worker threads, admits them
+ * while the device memory they need (tables + vectors) fits the budget and a
+ * slot is free, keeps every admitted wave packet resident on the device, and
+ * at each tick advances all resident requests by one Chebyshev step in one
+ * batched launch sequence (requests admitted meanwhile join at the next
+ * tick).  A finished request's state is copied to host and its device memory
+ * released.  Each request's result is bitwise the one it gets alone (same
+ * per-term code and fixed-order reductions): the precision policy is the
+ * configuration's, never tuned per request. */
+typedef struct {
+  int64_t hbm_budget_bytes;  /* device bytes resident requests may hold;
+                                0 = 80% of the free memory at creation       */
+  int32_t max_slots;         /* resident requests at most (> 0)              */
+  sg_precision prec;
+  int32_t check_every;       /* norm/energy check interval in steps (0: none) */
+  double tol;                /* norm drift beyond this fails the request (SG_ETOL) */
+  int32_t mixed_threshold;   /* SG_MIXED: sg_set_mixed_threshold value (< 0: default) */
+  int32_t compile_threads;   /* host compile workers (0: 4)                  */
+} sg_serve_config;
+
+typedef struct {
+  int32_t status;            /* SG_OK, SG_ETOL, SG_ECANCELED, ... (request result) */
+  int32_t D, L;
+  int64_t n_cs;              /* length of the state                           */
+  void *psi_host;            /* caller buffer, complex128[n_cs]; NULL: skip copy */
+  int64_t psi_capacity;      /* its length in complex values                  */
+  sg_prop_stats stats;
+  double t_submit, t_admit, t_done;   /* seconds on the server's clock        */
+} sg_result;
+
+typedef struct sg_server sg_server;
+sg_status sg_serve_create(const sg_serve_config *cfg, sg_server **out);
+/* Copies what it needs; returns at once.  SG_ENOMEM if the request could
+ * never fit the budget, SG_EINVAL for an invalid description. */
+sg_status sg_serve_submit(sg_server *s, const sg_problem_desc *desc, const double *shift,
+                          double dt, int32_t nsteps, uint64_t *ticket);
+/* SG_OK and *out filled when the request is finished (its record is then
+ * dropped; a second poll gives SG_ENOTFOUND), SG_EAGAIN while it is queued or
+ * running, SG_ENOTFOUND for an unknown ticket.  out->psi_host receives the
+ * final state when its capacity suffices. */
+sg_status sg_serve_poll(sg_server *s, uint64_t ticket, sg_result *out);
+/* Cancels a queued or running request (it finishes with SG_ECANCELED). */
+sg_status sg_serve_cancel(sg_server *s, uint64_t ticket);
+/* Counters: queued, resident, finished requests and ticks run. */
+sg_status sg_serve_counters(sg_server *s, int64_t out[4]);
+sg_status sg_serve_destroy(sg_server *s);
+
 /* Mixed-precision policy.  With SG_MIXED, a term whose combination
  * coefficient satisfies |D_l| <= max_fp32_coeff runs its grid contractions in
  * FP32; the others (few, small terms whose rounding the Smolyak sum amplifies

@@ -23,7 +23,10 @@ __all__ = [
     "library_path", "sg_count_sizes", "sg_build_terms", "sg_build_terms_host",
     "sg_free", "sg_problem_info", "sg_basis_indices", "sg_term_levels",
     "sg_mapping_table", "sg_init_gaussian", "sg_apply_H", "sg_spectral_bounds",
-    "sg_propagate_chebyshev", "sg_set_timing", "sg_get_timing", "Problem",
+    "sg_propagate_chebyshev", "sg_set_timing", "sg_get_timing", "sg_set_mixed_threshold",
+    "sg_tune_mixed", "sg_batch_create", "sg_batch_propagate", "sg_batch_free",
+    "ServeConfig", "sg_serve_create", "sg_serve_submit", "sg_serve_poll", "sg_serve_cancel",
+    "sg_serve_counters", "sg_serve_destroy", "Problem",
 ]
 
 SG_OK, SG_EINVAL, SG_ENOMEM, SG_EDEVICE = 0, -1, -2, -3
@@ -87,6 +90,21 @@ class Timing(ctypes.Structure):
 
 
 _P = ctypes.c_void_p
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("prec", ctypes.c_int), ("check_every", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("mixed_threshold", ctypes.c_int32),
+                ("compile_threads", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("D", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("n_cs", ctypes.c_int64), ("psi_host", ctypes.c_void_p),
+                ("psi_capacity", ctypes.c_int64), ("stats", PropStats),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
 _SIGNATURES = {
     "sg_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "sg_set_mixed_threshold": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -116,6 +134,21 @@ _SIGNATURES = {
                                               ctypes.POINTER(PropStats),
                                               ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_double), _P]),
+    "sg_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)]),
+    "sg_batch_propagate": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_double),
+                                          ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                          ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(PropStats), _P]),
+    "sg_batch_free": (ctypes.c_int, [_P]),
+    "sg_serve_create": (ctypes.c_int, [ctypes.POINTER(ServeConfig), ctypes.POINTER(_P)]),
+    "sg_serve_submit": (ctypes.c_int, [_P, ctypes.POINTER(ProblemDesc),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
+    "sg_serve_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(Result)]),
+    "sg_serve_cancel": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "sg_serve_counters": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "sg_serve_destroy": (ctypes.c_int, [_P]),
 }
 
 
@@ -306,6 +339,92 @@ def sg_get_timing(h) -> dict:
     t = Timing()
     _check(lib().sg_get_timing(h, ctypes.byref(t)))
     return t.as_dict()
+
+
+def sg_batch_create(handles) -> ctypes.c_void_p:
+    arr = (_P * len(handles))(*[h.value if isinstance(h, _P) else h for h in handles])
+    b = _P()
+    _check(lib().sg_batch_create(arr, len(handles), ctypes.byref(b)))
+    return b
+
+
+def sg_batch_propagate(b, psis, dts, nsteps: int, emins=None, emaxs=None, tol: float = 1e-8,
+                       precision: int = SG_FP64, check_every: int = 0, use_graph: bool = False,
+                       stream=None):
+    """psis: list of device complex128 tensors (the instances' states, in place).
+    Returns (status, list of stats dicts)."""
+    n = len(psis)
+    for t in psis:
+        _vec_ptr(t, t.numel(), "psi")
+    ptrs = (_P * n)(*[t.data_ptr() for t in psis])
+    dt = np.ascontiguousarray(dts, dtype=np.float64).reshape(n)
+    lo = None if emins is None else np.ascontiguousarray(emins, dtype=np.float64).reshape(n)
+    hi = None if emaxs is None else np.ascontiguousarray(emaxs, dtype=np.float64).reshape(n)
+    null = ctypes.POINTER(ctypes.c_double)()
+    st = (PropStats * n)()
+    status = lib().sg_batch_propagate(
+        b, ptrs, _dptr(dt), int(nsteps), _dptr(lo) if lo is not None else null,
+        _dptr(hi) if hi is not None else null, float(tol), int(precision), int(check_every),
+        1 if use_graph else 0, st, _stream_ptr(stream))
+    if status not in (SG_OK, SG_ETOL):
+        _check(status)
+    return status, [st[i].as_dict() for i in range(n)]
+
+
+def sg_batch_free(b) -> None:
+    _check(lib().sg_batch_free(b))
+
+
+def sg_serve_create(max_slots: int = 64, hbm_budget_bytes: int = 0, precision: int = SG_FP64,
+                    check_every: int = 0, tol: float = 0.0, mixed_threshold: int = -1,
+                    compile_threads: int = 0) -> ctypes.c_void_p:
+    cfg = ServeConfig(int(hbm_budget_bytes), int(max_slots), int(precision), int(check_every),
+                      float(tol), int(mixed_threshold), int(compile_threads))
+    s = _P()
+    _check(lib().sg_serve_create(ctypes.byref(cfg), ctypes.byref(s)))
+    return s
+
+
+def sg_serve_submit(s, D, L, omega, c, k, shift, dt: float, nsteps: int,
+                    nb=(1, 2), nq=(2, 2)) -> int:
+    desc, keep = _make_desc(D, L, omega, c, k, nb, nq)
+    sh = np.ascontiguousarray(shift, dtype=np.float64).reshape(D)
+    t = ctypes.c_uint64()
+    _check(lib().sg_serve_submit(s, ctypes.byref(desc), _dptr(sh), float(dt), int(nsteps),
+                                 ctypes.byref(t)))
+    return t.value
+
+
+def sg_serve_poll(s, ticket: int, n_cs_capacity: int = 0):
+    """None while the request runs; else a dict with status, stats, times and
+    (when n_cs_capacity suffices) the final state as a numpy complex128 array.
+    Raises SgError(SG_ENOTFOUND) for an unknown ticket."""
+    buf = np.zeros(max(int(n_cs_capacity), 0), dtype=np.complex128)
+    r = Result()
+    r.psi_host = buf.ctypes.data if buf.size else None
+    r.psi_capacity = buf.size
+    status = lib().sg_serve_poll(s, ctypes.c_uint64(ticket), ctypes.byref(r))
+    if status == SG_EAGAIN:
+        return None
+    _check(status)
+    out = {"status": r.status, "D": r.D, "L": r.L, "n_cs": r.n_cs, "stats": r.stats.as_dict(),
+           "t_submit": r.t_submit, "t_admit": r.t_admit, "t_done": r.t_done}
+    out["psi"] = buf[: r.n_cs] if buf.size >= r.n_cs > 0 else None
+    return out
+
+
+def sg_serve_cancel(s, ticket: int) -> None:
+    _check(lib().sg_serve_cancel(s, ctypes.c_uint64(ticket)))
+
+
+def sg_serve_counters(s) -> dict:
+    out = (ctypes.c_int64 * 4)()
+    _check(lib().sg_serve_counters(s, out))
+    return {"queued": out[0], "resident": out[1], "finished": out[2], "ticks": out[3]}
+
+
+def sg_serve_destroy(s) -> None:
+    _check(lib().sg_serve_destroy(s))
 
 
 class Problem:

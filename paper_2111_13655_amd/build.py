@@ -14,7 +14,8 @@ OUT = os.path.join(HERE, "libsg.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
 SOURCES = ["sg_terms.cpp", "sg_tables.cpp", "sg_api.cpp", "sg_cheb.cpp",
-           "sg_tune.cpp", "sg_sweep.hip", "sg_reduce.hip"]
+           "sg_tune.cpp", "sg_plan.cpp", "sg_batch.cpp", "sg_serve.cpp",
+           "sg_sweep.hip", "sg_reduce.hip"]
 
 ARCH = os.environ.get("SG_OFFLOAD_ARCH", "gfx950")
 
@@ -45,7 +46,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

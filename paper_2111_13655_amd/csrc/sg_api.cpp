@@ -78,8 +78,11 @@ void release(sg_problem *p) {
     return;
   }
   for (hipEvent_t ev : p->timing.ev) hipEventDestroy(ev);
+  if (p->plan) {
+    plan_free(p->plan);
+    delete p->plan;
+  }
   hipFree(p->d_terms);
-  hipFree(p->d_packs);
   hipFree(p->d_tables32);
   hipFree(p->d_tables32r);
   hipFree(p->d_mb);
@@ -87,14 +90,12 @@ void release(sg_problem *p) {
   hipFree(p->d_inv_col);
   hipFree(p->d_rows);
   hipFree(p->d_tables);
-  hipFree(p->d_lvt);
   hipFree(p->d_pairs);
   hipFree(p->d_h0);
-  hipFree(p->d_c);
-  hipFree(p->d_k);
   hipFree(p->d_tm);
   hipFree(p->d_work);
   hipFree(p->d_partials);
+  hipFree(p->d_cheb_a);
   hipFree(p->d_result);
   if (p->h_result) hipHostFree(p->h_result);
   delete p;
@@ -102,13 +103,14 @@ void release(sg_problem *p) {
 
 }  // namespace
 
-hipError_t run_sweep(sg_problem *p, const double2 *psi, sg_precision prec, hipStream_t s) {
-  return timed(p, 0, s, [&] { return launch_sweep(p, psi, prec, s); });
+hipError_t run_sweep(sg_problem *owner, const Plan *pl, const LaunchCtl &c, hipStream_t s) {
+  if (!owner) return launch_sweep(pl, c, s);
+  return timed(owner, 0, s, [&] { return launch_sweep(pl, c, s); });
 }
 
-hipError_t run_reduce(sg_problem *p, Epi epi, const double2 *psi_in, double2 *out,
-                      const ChebArgs *ca, hipStream_t s) {
-  return timed(p, 1, s, [&] { return launch_reduce(p, epi, psi_in, out, ca, s); });
+hipError_t run_reduce(sg_problem *owner, const Plan *pl, const LaunchCtl &c, hipStream_t s) {
+  if (!owner) return launch_reduce(pl, c, s);
+  return timed(owner, 1, s, [&] { return launch_reduce(pl, c, s); });
 }
 
 }  // namespace sg
@@ -143,11 +145,27 @@ sg_status sg_build_terms(const sg_problem_desc *desc, sg_problem **out) {
     delete p;
     return fail(st, err);
   }
+  return upload_problem(p, out);
+}
+
+}  // extern "C"
+
+namespace sg {
+
+int64_t estimate_device_bytes(const Compiled &h) {
+  const int64_t ns = (int64_t)h.MB.size();
+  return (int64_t)h.terms.size() * (int64_t)sizeof(TermDev) + (int64_t)h.pairs.size() * 8 +
+         ns * 4 * 2 + (h.ncs + 1) * 4 + h.ncs * 4 + h.ncs * 8 + ns * 16 + 4 * h.ncs * 16 +
+         2 * std::max<int64_t>(h.n_items, 256) * 8 + (int64_t)h.tables.size() * 20 +
+         (int64_t)sizeof(double) * (kMaxChebTerms + 8);
+}
+
+// Uploads a compiled problem to the current device (takes ownership of p;
+// frees it on failure).
+sg_status upload_problem(sg_problem *p, sg_problem **out) {
+  std::string err;
+  sg_status st;
   const Compiled &h = p->h;
-  if (2 * h.max_grid * (int64_t)sizeof(double2) > 160 * 1024) {
-    delete p;
-    return fail(SG_EINVAL, "a term grid exceeds the on-chip buffer (max 5120 points)");
-  }
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
   int64_t &bytes = p->device_bytes;
@@ -156,8 +174,6 @@ sg_status sg_build_terms(const sg_problem_desc *desc, sg_problem **out) {
   e = upload(&p->dst, (vec).data(), (vec).size(), &bytes);               \
   if (e != hipSuccess) { release(p); return hip_fail(e, "upload " #dst); }
   SG_UP(d_terms, h.terms)
-  SG_UP(d_packs, h.packs)
-  p->d_packs_capacity = (int64_t)h.packs.size();
   SG_UP(d_tables32, h.tables32)
   SG_UP(d_tables32r, h.tables32r)
   SG_UP(d_mb, h.MB)
@@ -166,11 +182,7 @@ sg_status sg_build_terms(const sg_problem_desc *desc, sg_problem **out) {
   SG_UP(d_rows, h.rows)
   SG_UP(d_tables, h.tables)
   SG_UP(d_pairs, h.pairs)
-  e = upload(&p->d_lvt, h.tdesc.lev, kMaxLevels, &bytes);
-  if (e != hipSuccess) { release(p); return hip_fail(e, "upload level tables"); }
   SG_UP(d_h0, h.h0)
-  SG_UP(d_c, h.c)
-  SG_UP(d_k, h.k)
 #undef SG_UP
   size_t tm_bytes = (size_t)ns * sizeof(double2);
   e = hipMalloc((void **)&p->d_tm, tm_bytes);
@@ -180,17 +192,35 @@ sg_status sg_build_terms(const sg_problem_desc *desc, sg_problem **out) {
   e = hipMalloc((void **)&p->d_work, work_bytes);
   if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation of work vectors failed"); }
   bytes += (int64_t)work_bytes;
-  p->n_partials = (int)std::max<int64_t>(reduce_blocks(p), 256);
-  e = hipMalloc((void **)&p->d_partials, 2 * (size_t)p->n_partials * sizeof(double));
+  const int64_t npart = std::max<int64_t>(h.n_items, 256);
+  e = hipMalloc((void **)&p->d_partials, 2 * (size_t)npart * sizeof(double));
   if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
-  bytes += 2 * (int64_t)p->n_partials * sizeof(double);
+  bytes += 2 * npart * (int64_t)sizeof(double);
+  e = hipMalloc((void **)&p->d_cheb_a, kMaxChebTerms * sizeof(double));
+  if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
   e = hipMalloc((void **)&p->d_result, 8 * sizeof(double));
   if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
   e = hipHostMalloc((void **)&p->h_result, 8 * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "pinned host allocation failed"); }
+  p->plan = new (std::nothrow) Plan();
+  if (!p->plan) { release(p); return fail(SG_ENOMEM, "host allocation failed"); }
+  st = plan_build(p->plan, {p}, &err);
+  if (st == SG_OK) st = plan_upload(p->plan, nullptr);
+  if (st != SG_OK) {
+    std::string msg = sg_last_error();
+    release(p);
+    return fail(st, msg.empty() ? err : msg);
+  }
+  bytes += p->plan->scratch_bytes;
   *out = p;
   return SG_OK;
 }
+
+void release_problem(sg_problem *p) { release(p); }
+
+}  // namespace sg
+
+extern "C" {
 
 sg_status sg_build_terms_host(const sg_problem_desc *desc, sg_problem **out) {
   if (!out) return fail(SG_EINVAL, "out is NULL");
@@ -310,11 +340,14 @@ sg_status sg_apply_H(sg_problem *p, const void *psi_in, void *psi_out, sg_precis
   if (p->host_only) return fail(SG_EINVAL, "handle was built without device tables");
   if (prec != SG_FP64 && prec != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = run_sweep(p, (const double2 *)psi_in, prec, s);
+  LaunchCtl c;
+  c.mode = Mode::Apply;
+  c.prec = prec;
+  c.x0o = (double2 *)psi_in;
+  c.x1o = (double2 *)psi_out;
+  hipError_t e = run_sweep(p, p->plan, c, s);
   if (e != hipSuccess) return hip_fail(e, "term sweep launch");
-  ChebArgs ca{};
-  ca.split = prec == SG_MIXED ? 1 : 0;
-  e = run_reduce(p, Epi::Apply, (const double2 *)psi_in, (double2 *)psi_out, &ca, s);
+  e = run_reduce(p, p->plan, c, s);
   if (e != hipSuccess) return hip_fail(e, "reduce launch");
   return SG_OK;
 }
@@ -323,21 +356,11 @@ sg_status sg_set_mixed_threshold(sg_problem *p, int32_t max_fp32_coeff) {
   if (!p) return fail(SG_EINVAL, "NULL problem");
   if (max_fp32_coeff < 0) return fail(SG_EINVAL, "threshold must be >= 0");
   p->h.mixed_max_fp32_coeff = max_fp32_coeff;
-  std::string err;
-  sg_status st = build_pack_sets(&p->h, &err);
-  if (st != SG_OK) return fail(st, err);
   if (p->host_only) return SG_OK;
-  if ((int64_t)p->h.packs.size() > p->d_packs_capacity) {
-    hipFree(p->d_packs);
-    p->d_packs = nullptr;
-    hipError_t e = hipMalloc((void **)&p->d_packs, p->h.packs.size() * sizeof(PackDev));
-    if (e != hipSuccess) return fail(SG_ENOMEM, "device allocation of packs failed");
-    p->d_packs_capacity = (int64_t)p->h.packs.size();
-  }
-  hipError_t e = hipMemcpy(p->d_packs, p->h.packs.data(), p->h.packs.size() * sizeof(PackDev),
-                           hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "upload packs");
-  return SG_OK;
+  std::string err;
+  sg_status st = plan_build(p->plan, {p}, &err);
+  if (st != SG_OK) return fail(st, err);
+  return plan_upload(p->plan, nullptr);
 }
 
 sg_status sg_set_timing(sg_problem *p, int32_t enable) {

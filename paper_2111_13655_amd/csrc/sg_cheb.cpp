@@ -44,6 +44,14 @@ void bessel_j_sequence(double x, int n, double *out) {
   for (int k = 0; k < n; ++k) out[k] = j[k] / norm;
 }
 
+int chebyshev_series(double R, std::vector<double> *a) {
+  const int K = chebyshev_terms(R, 1e-16);
+  a->assign(K, 0.0);
+  bessel_j_sequence(R, K, a->data());
+  for (int k = 1; k < K; ++k) (*a)[k] *= 2.0;
+  return K;
+}
+
 int chebyshev_terms(double R, double tol) {
   int k = (int)std::floor(R) + 1;
   std::vector<double> j;
@@ -155,22 +163,22 @@ sg_status sg_propagate_chebyshev(sg_problem *p, void *psi, double dt, int32_t ns
   if (!(emax > emin)) return fail(SG_EINVAL, "emax must exceed emin");
   const int64_t n = p->h.ncs;
   const double half = 0.5 * (emax - emin), ebar = 0.5 * (emax + emin);
-  const double R = half * dt;
-  const int K = chebyshev_terms(R, 1e-16);
-  std::vector<double> a(K);
-  bessel_j_sequence(R, K, a.data());
-  for (int k = 1; k < K; ++k) a[k] *= 2.0;
-  double2 *X[2] = {(double2 *)psi, p->d_work + 0 * n};
-  double2 *ACC = p->d_work + 1 * n;
-  ChebArgs ca{};
-  ca.ebar = ebar;
-  ca.inv_half = 1.0 / half;
-  ca.acc = ACC;
-  ca.final_out = (double2 *)psi;
-  ca.phase_re = std::cos(-ebar * dt);
-  ca.phase_im = std::sin(-ebar * dt);
-  ca.split = prec == SG_MIXED ? 1 : 0;
-  ca.a_0 = a[0];
+  std::vector<double> a;
+  const int K = chebyshev_series(half * dt, &a);
+  if (K < 2 || K > kMaxChebTerms) return fail(SG_EINVAL, "Chebyshev series length out of range");
+  hipError_t e = hipMemcpyAsync(p->d_cheb_a, a.data(), K * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "upload series");
+  Plan *pl = p->plan;
+  InstDev &I = pl->inst[0];
+  I.K = K;
+  I.ebar = ebar;
+  I.inv_half = 1.0 / half;
+  I.phase_re = std::cos(-ebar * dt);
+  I.phase_im = std::sin(-ebar * dt);
+  I.active = 1;
+  sg_status st0 = plan_upload_inst(pl, s);
+  if (st0 != SG_OK) return st0;
+
   sg_prop_stats st{};
   st.cheb_terms = K;
   st.emin = emin;
@@ -178,7 +186,6 @@ sg_status sg_propagate_chebyshev(sg_problem *p, void *psi, double dt, int32_t ns
   int ntrace = 0;
   bool have0 = false;
   sg_status ret = SG_OK;
-  hipError_t e;
   auto record = [&](double nrm2, double ene) {
     const double nrm = std::sqrt(nrm2), E = ene / nrm2;
     if (!have0) {
@@ -194,20 +201,19 @@ sg_status sg_propagate_chebyshev(sg_problem *p, void *psi, double dt, int32_t ns
     if (energy_trace) energy_trace[ntrace] = E;
     ++ntrace;
   };
+  LaunchCtl c;
+  c.mode = Mode::Cheb;
+  c.prec = prec;
+  c.x0o = (double2 *)psi;
   for (int step = 0; step < nsteps; ++step) {
     const bool check = step == 0 || (check_every > 0 && step % check_every == 0);
     for (int k = 1; k < K; ++k) {
-      const double2 *vin = X[(k - 1) % 2];
-      if ((e = run_sweep(p, vin, prec, s)) != hipSuccess) return hip_fail(e, "sweep");
-      ca.first = k == 1;
-      ca.last = k == K - 1;
-      ca.want_partials = (k == 1 && check) ? 1 : 0;
-      ca.prev = X[k % 2];
-      ca.a_k = a[k];
-      if ((e = run_reduce(p, Epi::Cheb, vin, nullptr, &ca, s)) != hipSuccess)
-        return hip_fail(e, "reduce");
+      c.k = k;
+      c.want_partials = (k == 1 && check) ? 1 : 0;
+      if ((e = run_sweep(p, pl, c, s)) != hipSuccess) return hip_fail(e, "sweep");
+      if ((e = run_reduce(p, pl, c, s)) != hipSuccess) return hip_fail(e, "reduce");
       if (k == 1 && check) {
-        if ((e = launch_finalize_partials(p, s)) != hipSuccess) return hip_fail(e, "finalize");
+        if ((e = launch_finalize(pl, s)) != hipSuccess) return hip_fail(e, "finalize");
         double nrm2, ene;
         sg_status rs = read_result(p, s, &nrm2, &ene);
         if (rs != SG_OK) return rs;
@@ -221,7 +227,7 @@ sg_status sg_propagate_chebyshev(sg_problem *p, void *psi, double dt, int32_t ns
   }
   if (ret == SG_OK) {
     // final norm and energy
-    double2 *w = p->d_work + 2 * n;
+    double2 *w = p->d_work + 3 * n;
     sg_status as = sg_apply_H(p, psi, w, prec, stream);
     if (as != SG_OK) return as;
     double nr, ni, er, ei;

@@ -62,32 +62,74 @@ struct LevelDev {
 
 constexpr int kMaxLevels = 16;
 
+struct DeviceTables {
+  LevelDev lev[kMaxLevels];
+};
+
+// Per-instance view read by the kernels.  A launch covers one or more
+// problem instances ("plan"); packs and reduce items name their instance.
+struct InstDev {
+  const TermDev *terms;
+  const double *pairs;
+  const int32_t *mb;
+  const int32_t *inv_ptr;
+  const int32_t *inv_col;
+  const int32_t *rows;      // long rows first, then short rows
+  const double *h0;
+  const double *tab64;      // one-mode tables, exact
+  const float *tab32;       // the same in FP32
+  const double *tab32r;     // FP32-rounded, held in FP64
+  double2 *tm;              // term-major results
+  double2 *x0, *x1;         // apply: x0 -> x1.  Chebyshev: phi buffers, x0 = psi
+  double2 *acc;             // Chebyshev running sum
+  double *partials;         // [2 * nitems] norm / energy partial sums
+  double *result;           // [2] finalised sums
+  const double *cheb_a;     // [K] series coefficients (2 - delta_k0) J_k(R)
+  int64_t ncs;
+  int64_t nlong;            // long rows
+  int32_t nitems;           // reduce work items of this instance
+  int32_t std_maps;         // nb = 1 + 2l, nq = 2 + 2l
+  int32_t round32;          // mixed path: FP64 terms read the FP32-rounded tables
+  int32_t K;                // Chebyshev terms (applies per step = K-1)
+  double ebar, inv_half, phase_re, phase_im;
+  int32_t active;           // 0: the launch skips this instance
+  int32_t pad;
+};
+
 // Term-sweep packing.  A workgroup (512 threads) runs one pack: one term with
 // more than kWaveMaxGrid grid points on all its wavefronts, or up to
-// kPackTerms smaller terms, one per wavefront.
+// kPackTerms smaller terms, one per wavefront.  A term whose two grid buffers
+// do not fit in LDS runs on a whole workgroup with its buffers in a global
+// scratch region (L2-resident).
 constexpr int kPackTerms = 8;
 constexpr int kWaveMaxGrid = 512;
 constexpr int kLdsPerCU = 160 * 1024;
 constexpr int kComputeUnits = 256;   // MI355X; used to size the packing only
 struct PackDev {
-  int32_t n;                  // terms in the pack
-  int32_t block;              // 1: term[0] runs on the whole workgroup
+  int32_t n;                    // terms in the pack
+  int32_t block;                // 1: term[0] on the whole workgroup, 2: same in scratch
+  int32_t inst[kPackTerms];
   int32_t term[kPackTerms];
   int32_t lds_off[kPackTerms];  // byte offset of each wavefront's LDS slice
+  int64_t scratch_off;          // block == 2: byte offset in the plan's scratch
 };
 struct PackSet {
-  int32_t first = 0;          // index of the first pack
+  int32_t first = 0;            // index of the first pack
   int32_t count = 0;
-  int32_t lds_bytes = 0;      // dynamic LDS of the launch
+  int32_t lds_bytes = 0;        // dynamic LDS of the launch
 };
 // Pack sets: FP64 path (all terms), mixed path FP64 terms, mixed path FP32 terms.
 constexpr int kPackSets = 3;
 // Rows of the inverse mapping longer than this are reduced by a whole
 // wavefront, shorter ones by a group of 8 lanes.
 constexpr int kLongRow = 64;
-
-struct DeviceTables {
-  LevelDev lev[kMaxLevels];
+constexpr int kShortLanes = 8;
+// One reduce work item = one wavefront: a long row, or 8 short rows.
+struct RedItem {
+  int32_t inst;
+  int32_t first;    // index into the instance's row list
+  int32_t local;    // item index inside the instance (partial-sum slot)
+  int32_t pad;
 };
 
 // Host-side term compiler output.
@@ -117,11 +159,10 @@ struct Compiled {
   std::vector<double> tables32r;     // FP32-rounded tables held in FP64 (mixed-path
                                      // FP64 terms: same operator as the FP32 terms)
   std::vector<double> cost;          // estimated work per term
-  std::vector<PackDev> packs;        // all pack sets, concatenated
-  PackSet sets[kPackSets];
   int32_t mixed_max_fp32_coeff = 16; // mixed path: |D_l| at most this -> FP32
   std::vector<int32_t> rows;         // compact rows, long rows first
   int64_t n_long_rows = 0;
+  int64_t n_items = 0;               // reduce work items
   // sizes
   int64_t grid_literal = 0, grid_active = 0, max_basis = 0, max_grid = 0;
   double flops_fp64 = 0, flops_mixed = 0, bytes_apply = 0;
@@ -131,9 +172,6 @@ struct Compiled {
 sg_status compile_problem(const sg_problem_desc *desc, Compiled *out,
                           std::string *err);
 sg_status count_sizes(int D, int L, int nbA, int nbB, int64_t out[3]);
-// (Re)builds the three pack sets from the term records and the mixed-path
-// coefficient threshold.
-sg_status build_pack_sets(Compiled *h, std::string *err);
 
 // One-mode tables (sg_tables.cpp)
 void gauss_hermite_nodes(int n, std::vector<double> *x, std::vector<double> *wt);
@@ -147,6 +185,8 @@ void hermite_function_values(int nb, double x, double *b);
 void bessel_j_sequence(double x, int n, double *out);
 int chebyshev_terms(double R, double tol);
 
+struct Plan;
+
 }  // namespace sg
 
 // Device-resident state of a built problem.
@@ -156,8 +196,6 @@ struct sg_problem {
   bool host_only = false;          // built without device tables
   // device tables
   sg::TermDev *d_terms = nullptr;
-  sg::PackDev *d_packs = nullptr;
-  int64_t d_packs_capacity = 0;
   float *d_tables32 = nullptr;
   double *d_tables32r = nullptr;
   int32_t *d_mb = nullptr;
@@ -165,19 +203,17 @@ struct sg_problem {
   int32_t *d_inv_col = nullptr;
   int32_t *d_rows = nullptr;
   double *d_tables = nullptr;
-  sg::LevelDev *d_lvt = nullptr;   // [kMaxLevels]
   double *d_pairs = nullptr;       // [nterms][kMaxPairs][2]
   double *d_h0 = nullptr;
-  double *d_c = nullptr;           // [D*D]
-  double *d_k = nullptr;           // [D*D]
   // work buffers
   double2 *d_tm = nullptr;         // term-major results [N_s]
-  double2 *d_work = nullptr;       // 3 * N_cs: Chebyshev P, ACC, spare
-  double *d_partials = nullptr;    // reduction partials
-  double *d_result = nullptr;      // 4 doubles
+  double2 *d_work = nullptr;       // 4 * N_cs: Chebyshev phi, ACC, spares
+  double *d_partials = nullptr;    // [2 * n_items] reduction partials
+  double *d_cheb_a = nullptr;      // [kMaxChebTerms] series coefficients
+  double *d_result = nullptr;      // 8 doubles
   double *h_result = nullptr;      // pinned host mirror of d_result
   int64_t device_bytes = 0;
-  int n_partials = 0;
+  sg::Plan *plan = nullptr;        // launch plan of this problem alone
   // optional per-kernel timing with HIP events (sg_set_timing)
   struct Timing {
     bool on = false;
@@ -191,41 +227,68 @@ struct sg_problem {
 };
 
 namespace sg {
-// Kernel launchers (sg_kernels.hip)
-enum class Epi : int { Apply = 0, Cheb = 1 };
 
-struct ChebArgs {
-  const double2 *psi_in;   // the vector H was applied to (phi_k)
-  double2 *prev;           // phi_{k-1} on input, phi_{k+1} on output
-  double2 *acc;            // running sum
-  double2 *final_out;      // ChebLast: exp(-i Ebar dt) * acc
-  double ebar, inv_half;   // Ebar and 2 / dE
-  double a_k;              // coefficient of the produced phi
-  double a_0;              // ChebFirst: coefficient of phi_0
-  double phase_re, phase_im;
-  int split;               // add the exact FP64 diagonal part
-  int want_partials;       // first: norm/energy partials
-  int first;               // produce phi_1 from phi_0
-  int last;                // write exp(-i Ebar dt) * acc instead of phi, acc
+constexpr int kMaxChebTerms = 4096;
+
+// A launch plan: the instances one sweep/reduce launch covers, their packs
+// and reduce items, resident on the device.
+struct Plan {
+  std::vector<sg_problem *> probs;
+  std::vector<InstDev> inst;       // host mirror
+  std::vector<PackDev> packs;
+  PackSet sets[kPackSets];
+  std::vector<RedItem> items;
+  InstDev *d_inst = nullptr;
+  PackDev *d_packs = nullptr;
+  RedItem *d_items = nullptr;
+  char *d_scratch = nullptr;
+  int64_t scratch_bytes = 0;
+  int64_t packs_capacity = 0, items_capacity = 0, inst_capacity = 0, scratch_capacity = 0;
+  bool any32 = false;              // some term of some instance runs in FP32
 };
 
-hipError_t launch_sweep(const sg_problem *p, const double2 *psi, sg_precision prec,
-                        hipStream_t s);
-hipError_t launch_reduce(const sg_problem *p, Epi epi, const double2 *psi_in,
-                         double2 *out, const ChebArgs *ca, hipStream_t s);
-hipError_t launch_finalize_partials(const sg_problem *p, hipStream_t s);
-hipError_t launch_init_vector(const sg_problem *p, const double *coef_dev,
-                              double2 *psi, hipStream_t s);
+// Plans (sg_plan.cpp)
+sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::string *err);
+sg_status plan_upload(Plan *pl, hipStream_t s);   // packs, items, scratch, descriptors
+sg_status plan_upload_inst(Plan *pl, hipStream_t s);  // descriptors only
+void plan_free(Plan *pl);
+// Fills the static part of an instance descriptor from a problem.
+void inst_from_problem(const sg_problem *p, InstDev *d);
+
+// Kernel launchers.  `k` is the Chebyshev term being produced (1..K-1);
+// apply mode ignores it.  x0o / x1o, when non-null, replace the x0 / x1
+// buffers of a single-instance plan.
+enum class Mode : int { Apply = 0, Cheb = 1 };
+struct LaunchCtl {
+  Mode mode = Mode::Apply;
+  sg_precision prec = SG_FP64;
+  int k = 1;
+  int want_partials = 0;
+  double2 *x0o = nullptr;
+  double2 *x1o = nullptr;
+};
+hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s);
+hipError_t launch_reduce(const Plan *pl, const LaunchCtl &c, hipStream_t s);
+hipError_t launch_finalize(const Plan *pl, hipStream_t s);  // per-instance partials
 hipError_t launch_dot(const sg_problem *p, const double2 *a, const double2 *b,
                       hipStream_t s);  // result in d_result[0..1] (re, im)
 hipError_t launch_axpby(int64_t n, double2 *y, const double2 *x, double a_re,
                         double a_im, double b, hipStream_t s);  // y = a x + b y
-int64_t reduce_blocks(const sg_problem *p);
 
 // Launch with optional event timing (sg_api.cpp); the drivers use these.
-hipError_t run_sweep(sg_problem *p, const double2 *psi, sg_precision prec, hipStream_t s);
-hipError_t run_reduce(sg_problem *p, Epi epi, const double2 *psi_in, double2 *out,
-                      const ChebArgs *ca, hipStream_t s);
+hipError_t run_sweep(sg_problem *timing_owner, const Plan *pl, const LaunchCtl &c,
+                     hipStream_t s);
+hipError_t run_reduce(sg_problem *timing_owner, const Plan *pl, const LaunchCtl &c,
+                      hipStream_t s);
 sg_status fail(sg_status st, const std::string &msg);
 sg_status hip_fail(hipError_t e, const char *what);
+
+// Device upload of a compiled problem (takes ownership; frees on failure),
+// its device-memory estimate, and release.
+sg_status upload_problem(sg_problem *p, sg_problem **out);
+int64_t estimate_device_bytes(const Compiled &h);
+void release_problem(sg_problem *p);
+
+// Chebyshev series for one instance: K and coefficients for R = dE dt / 2.
+int chebyshev_series(double R, std::vector<double> *a);
 }  // namespace sg

@@ -1,0 +1,249 @@
+// Launch plans: the instances one term-sweep / reduce launch covers.
+//
+// Packing (the term -> workgroup schedule).  Terms above kWaveMaxGrid grid
+// points get a workgroup each (in global scratch when their two grid buffers
+// exceed the LDS of a compute unit); the others are dealt, most expensive
+// first, to the least loaded of B packs of at most kPackTerms terms (one
+// wavefront each), with B large enough to give every compute unit work.
+// Terms of different instances mix freely: every term is computed by the
+// same code whatever its pack, so results do not depend on the mix.
+//
+// Reduce items: one wavefront per long row, one per eight short rows, in each
+// instance's row order; an item's partial sums go to its own slot so that the
+// per-instance norm / energy sums run in a fixed order.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "sg_internal.h"
+
+namespace sg {
+
+namespace {
+
+struct Cand {
+  int32_t inst;
+  int32_t term;
+  double cost;
+  int slice;   // bytes of the two grid buffers
+  int ngrid;
+};
+
+void pack_set(const std::vector<Cand> &cands, std::vector<PackDev> *out, PackSet *set,
+              int64_t *scratch_bytes) {
+  set->first = (int32_t)out->size();
+  set->count = 0;
+  set->lds_bytes = 0;
+  if (cands.empty()) return;
+  std::vector<Cand> big, small;
+  for (const Cand &c : cands) (c.ngrid > kWaveMaxGrid ? big : small).push_back(c);
+  auto by_cost = [](const Cand &a, const Cand &b) { return a.cost > b.cost; };
+  std::stable_sort(big.begin(), big.end(), by_cost);
+  std::stable_sort(small.begin(), small.end(), by_cost);
+  int lds = 0;
+  for (const Cand &c : big)
+    if (c.slice <= kLdsPerCU) lds = std::max(lds, c.slice);
+  int small_slice = 0;
+  for (const Cand &c : small) small_slice = std::max(small_slice, c.slice);
+  const int small_lds = kPackTerms * small_slice;
+  const int per_cu = std::max(1, kLdsPerCU / std::max(1, std::max(lds, small_lds)));
+  const int64_t nsmall = (int64_t)small.size();
+  int64_t nbins = (nsmall + kPackTerms - 1) / kPackTerms;
+  const int64_t want = (int64_t)kComputeUnits * per_cu - (int64_t)big.size();
+  nbins = std::max<int64_t>(nbins, std::min<int64_t>(nsmall, want));
+  struct Bin {
+    double load;
+    int64_t id;
+  };
+  auto worse = [](const Bin &a, const Bin &b) {
+    return a.load > b.load || (a.load == b.load && a.id > b.id);
+  };
+  std::vector<Bin> heap;
+  std::vector<PackDev> bins((size_t)nbins);
+  std::vector<int> bin_bytes((size_t)nbins, 0);
+  std::vector<double> bin_load((size_t)nbins, 0.0);
+  for (int64_t i = 0; i < nbins; ++i) {
+    std::memset(&bins[i], 0, sizeof(PackDev));
+    heap.push_back({0.0, i});
+  }
+  std::make_heap(heap.begin(), heap.end(), worse);
+  for (const Cand &c : small) {
+    std::pop_heap(heap.begin(), heap.end(), worse);
+    Bin b = heap.back();
+    heap.pop_back();
+    PackDev &pk = bins[b.id];
+    pk.inst[pk.n] = c.inst;
+    pk.term[pk.n] = c.term;
+    pk.lds_off[pk.n] = bin_bytes[b.id];
+    bin_bytes[b.id] += c.slice;
+    pk.n += 1;
+    b.load += c.cost;
+    bin_load[b.id] = b.load;
+    if (pk.n < kPackTerms) {
+      heap.push_back(b);
+      std::push_heap(heap.begin(), heap.end(), worse);
+    }
+  }
+  for (const Cand &c : big) {
+    PackDev pk;
+    std::memset(&pk, 0, sizeof(pk));
+    pk.n = 1;
+    pk.inst[0] = c.inst;
+    pk.term[0] = c.term;
+    if (c.slice <= kLdsPerCU) {
+      pk.block = 1;
+    } else {
+      pk.block = 2;
+      pk.scratch_off = *scratch_bytes;
+      *scratch_bytes += ((int64_t)c.slice + 255) & ~(int64_t)255;
+    }
+    out->push_back(pk);
+  }
+  std::vector<int64_t> order((size_t)nbins);
+  for (int64_t i = 0; i < nbins; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t b) { return bin_load[a] > bin_load[b]; });
+  for (int64_t i : order) {
+    if (bins[i].n == 0) continue;
+    out->push_back(bins[i]);
+    lds = std::max(lds, bin_bytes[i]);
+  }
+  set->count = (int32_t)(out->size() - set->first);
+  set->lds_bytes = lds;
+}
+
+template <typename T>
+hipError_t ensure(T **ptr, int64_t *cap, int64_t n, int64_t *bytes_delta) {
+  if (n <= *cap && *ptr) return hipSuccess;
+  hipFree(*ptr);
+  *ptr = nullptr;
+  const int64_t m = std::max<int64_t>(n, 1);
+  hipError_t e = hipMalloc((void **)ptr, (size_t)m * sizeof(T));
+  if (e == hipSuccess) {
+    if (bytes_delta) *bytes_delta += (m - *cap) * (int64_t)sizeof(T);
+    *cap = m;
+  } else {
+    *cap = 0;
+  }
+  return e;
+}
+
+}  // namespace
+
+void inst_from_problem(const sg_problem *p, InstDev *d) {
+  std::memset(d, 0, sizeof(*d));
+  const Compiled &h = p->h;
+  d->terms = p->d_terms;
+  d->pairs = p->d_pairs;
+  d->mb = p->d_mb;
+  d->inv_ptr = p->d_inv_ptr;
+  d->inv_col = p->d_inv_col;
+  d->rows = p->d_rows;
+  d->h0 = p->d_h0;
+  d->tab64 = p->d_tables;
+  d->tab32 = p->d_tables32;
+  d->tab32r = p->d_tables32r;
+  d->tm = p->d_tm;
+  d->x0 = p->d_work;
+  d->x1 = p->d_work + h.ncs;
+  d->acc = p->d_work + 2 * h.ncs;
+  d->partials = p->d_partials;
+  d->result = p->d_result;
+  d->cheb_a = p->d_cheb_a;
+  d->ncs = h.ncs;
+  d->nlong = h.n_long_rows;
+  d->nitems = (int32_t)h.n_items;
+  d->std_maps = (h.nbA == 1 && h.nbB == 2 && h.nqA == 2 && h.nqB == 2) ? 1 : 0;
+  d->round32 = 0;
+  d->K = 0;
+  d->inv_half = 1.0;
+  d->phase_re = 1.0;
+  d->active = 1;
+}
+
+sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::string *err) {
+  pl->probs = probs;
+  pl->inst.assign(probs.size(), InstDev{});
+  pl->packs.clear();
+  pl->items.clear();
+  pl->scratch_bytes = 0;
+  pl->any32 = false;
+  std::vector<Cand> c64, m64, m32;
+  for (size_t i = 0; i < probs.size(); ++i) {
+    const sg_problem *p = probs[i];
+    const Compiled &h = p->h;
+    inst_from_problem(p, &pl->inst[i]);
+    bool inst32 = false;
+    for (int64_t t = 0; t < h.nterms; ++t) {
+      const int ng = h.terms[t].ngrid;
+      Cand c{(int32_t)i, (int32_t)t, h.cost[t], 2 * ng * 16, ng};
+      c64.push_back(c);
+      if (std::abs(h.coeff[t]) <= h.mixed_max_fp32_coeff) {
+        c.slice = 2 * ng * 8;
+        m32.push_back(c);
+        inst32 = true;
+      } else {
+        m64.push_back(c);
+      }
+    }
+    pl->inst[i].round32 = inst32 ? 1 : 0;
+    pl->any32 = pl->any32 || inst32;
+    for (int64_t q = 0; q < h.n_long_rows; ++q)
+      pl->items.push_back({(int32_t)i, (int32_t)q, (int32_t)q, 0});
+    const int64_t nshort = h.ncs - h.n_long_rows;
+    int32_t local = (int32_t)h.n_long_rows;
+    for (int64_t q = 0; q < nshort; q += kShortLanes)
+      pl->items.push_back({(int32_t)i, (int32_t)(h.n_long_rows + q), local++, 0});
+  }
+  pack_set(c64, &pl->packs, &pl->sets[0], &pl->scratch_bytes);
+  pack_set(m64, &pl->packs, &pl->sets[1], &pl->scratch_bytes);
+  pack_set(m32, &pl->packs, &pl->sets[2], &pl->scratch_bytes);
+  (void)err;
+  return SG_OK;
+}
+
+sg_status plan_upload(Plan *pl, hipStream_t s) {
+  hipError_t e;
+  if ((e = ensure(&pl->d_packs, &pl->packs_capacity, (int64_t)pl->packs.size(), nullptr)) != hipSuccess)
+    return fail(SG_ENOMEM, "device allocation of packs failed");
+  if ((e = ensure(&pl->d_items, &pl->items_capacity, (int64_t)pl->items.size(), nullptr)) != hipSuccess)
+    return fail(SG_ENOMEM, "device allocation of reduce items failed");
+  if ((e = ensure(&pl->d_scratch, &pl->scratch_capacity, pl->scratch_bytes, nullptr)) != hipSuccess)
+    return fail(SG_ENOMEM, "device allocation of sweep scratch failed");
+  if (!pl->packs.empty() &&
+      (e = hipMemcpyAsync(pl->d_packs, pl->packs.data(), pl->packs.size() * sizeof(PackDev),
+                          hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(e, "upload packs");
+  if (!pl->items.empty() &&
+      (e = hipMemcpyAsync(pl->d_items, pl->items.data(), pl->items.size() * sizeof(RedItem),
+                          hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(e, "upload reduce items");
+  return plan_upload_inst(pl, s);
+}
+
+sg_status plan_upload_inst(Plan *pl, hipStream_t s) {
+  hipError_t e;
+  if ((e = ensure(&pl->d_inst, &pl->inst_capacity, (int64_t)pl->inst.size(), nullptr)) != hipSuccess)
+    return fail(SG_ENOMEM, "device allocation of instance descriptors failed");
+  if (!pl->inst.empty() &&
+      (e = hipMemcpyAsync(pl->d_inst, pl->inst.data(), pl->inst.size() * sizeof(InstDev),
+                          hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(e, "upload instance descriptors");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "plan upload");
+  return SG_OK;
+}
+
+void plan_free(Plan *pl) {
+  if (!pl) return;
+  hipFree(pl->d_inst);
+  hipFree(pl->d_packs);
+  hipFree(pl->d_items);
+  hipFree(pl->d_scratch);
+  pl->d_inst = nullptr;
+  pl->d_packs = nullptr;
+  pl->d_items = nullptr;
+  pl->d_scratch = nullptr;
+  pl->inst_capacity = pl->packs_capacity = pl->items_capacity = pl->scratch_capacity = 0;
+}
+
+}  // namespace sg

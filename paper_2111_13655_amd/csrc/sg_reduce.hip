@@ -2,10 +2,12 @@
 // small vector kernels of the propagator, for gfx950 (MI355X).
 //
 // The scatter-add is done as a gather: every compact index sums its
-// term-major contributions through the inverse of M^B in a fixed order (lane
-// groups of 8 for short rows, a whole wavefront for long ones), so results
-// are bitwise reproducible.  The Chebyshev recurrence and the norm/energy
-// partial sums are fused into its epilogue.
+// term-major contributions through the inverse of M^B in a fixed order (a
+// whole wavefront for a long row, a group of 8 lanes for each of 8 short
+// rows), so results are bitwise reproducible and independent of which other
+// instances share the launch.  The exact FP64 diagonal part of the mixed
+// path, the Chebyshev recurrence, the series accumulation and the norm /
+// energy partial sums are fused into the epilogue.
 #include "sg_internal.h"
 
 namespace sg {
@@ -13,21 +15,16 @@ namespace sg {
 namespace {
 
 constexpr int kRedThreads = 256;
-constexpr int kShortLanes = 8;
 
 struct ReduceArgs {
-  const int32_t *ptr;
-  const int32_t *col;
-  const int32_t *rows;     // long rows first, then short rows
-  const double2 *tm;
-  const double *h0;
-  const double2 *vin;
-  double2 *out;
-  int64_t ncs;
-  int64_t nlong;
-  double *partials;
-  ChebArgs ca;
-  int cheb;
+  const InstDev *inst;
+  const RedItem *items;
+  int64_t nitems;
+  double2 *x0o, *x1o;
+  int mode;            // 0 apply, 1 Chebyshev
+  int k;               // Chebyshev term produced (1..K-1)
+  int want_partials;   // k == 1: norm / energy partial sums
+  int split;           // add the exact diagonal part
 };
 
 // Sum of tm[col[j]] for j = b + sub, b + sub + G, ... < e, in increasing j.
@@ -60,95 +57,123 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ void row_epilogue(const ReduceArgs &a, int64_t row, double sr,
-                                             double si, double *pn, double *pe) {
-  const double2 vk = a.vin[row];
-  if (a.ca.split) {
-    const double d = a.h0[row];
+// Row epilogue: (H psi)[row] = s (+ exact diagonal), then either the plain
+// output or one Chebyshev recurrence step phi_k = -2i Hs phi_{k-1} + phi_{k-2}
+// (phi_1 = -i Hs phi_0), acc += a_k phi_k, and on the last term
+// psi <- exp(-i Ebar dt) acc.
+__device__ __forceinline__ void row_epilogue(const ReduceArgs &a, const InstDev *I, int64_t row,
+                                             double sr, double si, double *pn, double *pe) {
+  double2 *x0 = a.x0o ? a.x0o : I->x0;
+  double2 *x1 = a.x1o ? a.x1o : I->x1;
+  const double2 *vin = (a.mode == 0) ? x0 : (((a.k - 1) & 1) ? x1 : x0);
+  const double2 vk = vin[row];
+  if (a.split) {
+    const double d = I->h0[row];
     sr = fma(d, vk.x, sr);
     si = fma(d, vk.y, si);
   }
-  if (!a.cheb) {
-    a.out[row] = make_double2(sr, si);
+  if (a.mode == 0) {
+    x1[row] = make_double2(sr, si);
     return;
   }
-  const ChebArgs &c = a.ca;
-  const double zr = (sr - c.ebar * vk.x) * c.inv_half;
-  const double zi = (si - c.ebar * vk.y) * c.inv_half;
+  double2 *prev = (a.k & 1) ? x1 : x0;   // phi_{k-2} in, phi_k out
+  const double zr = (sr - I->ebar * vk.x) * I->inv_half;
+  const double zi = (si - I->ebar * vk.y) * I->inv_half;
+  const double ak = I->cheb_a[a.k];
   double2 phi, accv;
-  if (c.first) {
+  if (a.k == 1) {
+    const double a0 = I->cheb_a[0];
     phi = make_double2(zi, -zr);  // -i z
-    accv = make_double2(c.a_0 * vk.x + c.a_k * phi.x, c.a_0 * vk.y + c.a_k * phi.y);
+    accv = make_double2(a0 * vk.x + ak * phi.x, a0 * vk.y + ak * phi.y);
     *pn = vk.x * vk.x + vk.y * vk.y;
     *pe = vk.x * sr + vk.y * si;  // Re(conj(psi) H psi)
   } else {
-    const double2 pr = c.prev[row];
-    phi = make_double2(2.0 * zi + pr.x, -2.0 * zr + pr.y);  // -2i z + phi_{k-1}
-    const double2 ac = c.acc[row];
-    accv = make_double2(ac.x + c.a_k * phi.x, ac.y + c.a_k * phi.y);
+    const double2 pr = prev[row];
+    phi = make_double2(2.0 * zi + pr.x, -2.0 * zr + pr.y);  // -2i z + phi_{k-2}
+    const double2 ac = I->acc[row];
+    accv = make_double2(ac.x + ak * phi.x, ac.y + ak * phi.y);
   }
-  if (c.last) {
-    c.final_out[row] = make_double2(c.phase_re * accv.x - c.phase_im * accv.y,
-                                    c.phase_re * accv.y + c.phase_im * accv.x);
+  if (a.k == I->K - 1) {
+    x0[row] = make_double2(I->phase_re * accv.x - I->phase_im * accv.y,
+                           I->phase_re * accv.y + I->phase_im * accv.x);
   } else {
-    c.prev[row] = phi;
-    c.acc[row] = accv;
+    prev[row] = phi;
+    I->acc[row] = accv;
   }
 }
 
 // step 5 (second half): compact[r] = sum of its term-major contributions
 __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
-  __shared__ double red[2][kRedThreads / 64];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * (kRedThreads / 64) + wave;
+  if (gw >= a.nitems) return;
+  const RedItem it = a.items[gw];
+  const InstDev *I = a.inst + it.inst;
+  if (!I->active || (a.mode == 1 && a.k > I->K - 1)) return;
   double pn = 0.0, pe = 0.0;
-  if (gw < a.nlong) {
-    const int64_t row = a.rows[gw];
-    const int b = a.ptr[row], e = a.ptr[row + 1];
+  if (it.first < I->nlong) {
+    const int64_t row = I->rows[it.first];
+    const int b = I->inv_ptr[row], e = I->inv_ptr[row + 1];
     double sr = 0.0, si = 0.0;
-    strided_sum<64>(a.col, a.tm, b, e, lane, &sr, &si);
+    strided_sum<64>(I->inv_col, I->tm, b, e, lane, &sr, &si);
     sr = group_sum<64>(sr);
     si = group_sum<64>(si);
-    if (lane == 0) row_epilogue(a, row, sr, si, &pn, &pe);
+    if (lane == 0) row_epilogue(a, I, row, sr, si, &pn, &pe);
   } else {
-    const int64_t sidx = (gw - a.nlong) * (64 / kShortLanes) + lane / kShortLanes;
+    const int64_t ri = (int64_t)it.first + lane / kShortLanes;
     const int sub = lane % kShortLanes;
-    const bool valid = a.nlong + sidx < a.ncs;
+    const bool valid = ri < I->ncs;
     double sr = 0.0, si = 0.0;
     int64_t row = 0;
     if (valid) {
-      row = a.rows[a.nlong + sidx];
-      const int b = a.ptr[row], e = a.ptr[row + 1];
-      strided_sum<kShortLanes>(a.col, a.tm, b, e, sub, &sr, &si);
+      row = I->rows[ri];
+      const int b = I->inv_ptr[row], e = I->inv_ptr[row + 1];
+      strided_sum<kShortLanes>(I->inv_col, I->tm, b, e, sub, &sr, &si);
     }
     sr = group_sum<kShortLanes>(sr);
     si = group_sum<kShortLanes>(si);
-    if (valid && sub == 0) row_epilogue(a, row, sr, si, &pn, &pe);
+    if (valid && sub == 0) row_epilogue(a, I, row, sr, si, &pn, &pe);
   }
-  if (a.cheb && a.ca.first && a.ca.want_partials) {
+  if (a.mode == 1 && a.k == 1 && a.want_partials) {
     pn = group_sum<64>(pn);
     pe = group_sum<64>(pe);
     if (lane == 0) {
-      red[0][wave] = pn;
-      red[1][wave] = pe;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double sn = 0.0, se = 0.0;
-      for (int w = 0; w < kRedThreads / 64; ++w) {
-        sn += red[0][w];
-        se += red[1][w];
-      }
-      a.partials[2 * blockIdx.x] = sn;
-      a.partials[2 * blockIdx.x + 1] = se;
+      I->partials[2 * it.local] = pn;
+      I->partials[2 * it.local + 1] = pe;
     }
   }
 }
 
-// Sums `n` pairs of partials in a fixed order; writes out[0..1].
-__global__ __launch_bounds__(256) void finalize_kernel(const double *partials, int n,
-                                                       double *out) {
+// One block per instance: sums its item partials in a fixed order.
+__global__ __launch_bounds__(256) void finalize_kernel(const InstDev *inst) {
+  __shared__ double s0[256], s1[256];
+  const InstDev *I = inst + blockIdx.x;
+  if (!I->active) return;
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < I->nitems; i += 256) {
+    a += I->partials[2 * i];
+    b += I->partials[2 * i + 1];
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) {
+      s0[threadIdx.x] += s0[threadIdx.x + w];
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    I->result[0] = s0[0];
+    I->result[1] = s1[0];
+  }
+}
+
+// Sums n pairs of partials in a fixed order; writes out[0..1].
+__global__ __launch_bounds__(256) void sum_pairs_kernel(const double *partials, int n,
+                                                        double *out) {
   __shared__ double s0[256], s1[256];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) {
@@ -207,42 +232,34 @@ __global__ __launch_bounds__(256) void axpby_kernel(int64_t n, double2 *y, const
 
 }  // namespace
 
-int64_t reduce_blocks(const sg_problem *p) {
-  const int64_t nshort = p->h.ncs - p->h.n_long_rows;
-  const int64_t waves = p->h.n_long_rows + (nshort + (64 / kShortLanes) - 1) / (64 / kShortLanes);
-  return (waves + (kRedThreads / 64) - 1) / (kRedThreads / 64);
-}
-
-hipError_t launch_reduce(const sg_problem *p, Epi epi, const double2 *psi_in, double2 *out,
-                         const ChebArgs *ca, hipStream_t s) {
+hipError_t launch_reduce(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   ReduceArgs a;
-  a.ptr = p->d_inv_ptr;
-  a.col = p->d_inv_col;
-  a.rows = p->d_rows;
-  a.tm = p->d_tm;
-  a.h0 = p->d_h0;
-  a.vin = psi_in;
-  a.out = out;
-  a.ncs = p->h.ncs;
-  a.nlong = p->h.n_long_rows;
-  a.partials = p->d_partials;
-  a.ca = ca ? *ca : ChebArgs{};
-  a.cheb = epi == Epi::Cheb ? 1 : 0;
-  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)reduce_blocks(p)), dim3(kRedThreads), 0, s, a);
+  a.inst = pl->d_inst;
+  a.items = pl->d_items;
+  a.nitems = (int64_t)pl->items.size();
+  a.x0o = c.x0o;
+  a.x1o = c.x1o;
+  a.mode = c.mode == Mode::Cheb ? 1 : 0;
+  a.k = c.k;
+  a.want_partials = c.want_partials;
+  a.split = c.prec == SG_MIXED ? 1 : 0;
+  const int64_t blocks = (a.nitems + (kRedThreads / 64) - 1) / (kRedThreads / 64);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)blocks), dim3(kRedThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize_partials(const sg_problem *p, hipStream_t s) {
-  const int n = (int)reduce_blocks(p);
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, (const double *)p->d_partials, n,
-                     p->d_result);
+hipError_t launch_finalize(const Plan *pl, hipStream_t s) {
+  if (pl->inst.empty()) return hipSuccess;
+  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)pl->inst.size()), dim3(256), 0, s,
+                     (const InstDev *)pl->d_inst);
   return hipGetLastError();
 }
 
 hipError_t launch_dot(const sg_problem *p, const double2 *x, const double2 *y, hipStream_t s) {
   const int blocks = 256;
   hipLaunchKernelGGL(dot_kernel, dim3(blocks), dim3(256), 0, s, x, y, p->h.ncs, p->d_partials);
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, (const double *)p->d_partials,
+  hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(256), 0, s, (const double *)p->d_partials,
                      blocks, p->d_result);
   return hipGetLastError();
 }

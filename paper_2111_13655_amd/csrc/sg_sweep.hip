@@ -31,17 +31,26 @@ namespace {
 
 constexpr int kThreads = 512;
 
-struct SweepArgs {
-  const TermDev *terms;
-  const PackDev *packs;
+// What one term's computation reads and writes (built per term slot).
+struct TermCtx {
   const int32_t *mb;
-  const double2 *psi;
+  const double2 *psi;    // the vector H is applied to
   double2 *tm;
   const void *tab;       // one-mode tables in the arithmetic type
-  const double *pairs;
+  const double *pc;      // the term's pair coefficients
   int std_maps;          // nb = 1 + 2l, nq = 2 + 2l
   int split;             // operator without the separable harmonic part
   int round32;           // FP64 arithmetic on FP32-rounded tables and coefficients
+};
+
+struct SweepArgs {
+  const InstDev *inst;
+  const PackDev *packs;
+  char *scratch;
+  double2 *x0o, *x1o;    // single-instance buffer overrides (nullable)
+  int mode;              // 0 apply, 1 Chebyshev
+  int k;                 // Chebyshev term being produced
+  int split;
 };
 
 template <typename R> struct Cx;
@@ -178,7 +187,7 @@ __device__ __forceinline__ void contract_level(int kind, int level, int std_maps
 // fiber through M^B and writes the nq transformed values to LDS.
 // ---------------------------------------------------------------------------
 template <typename G, typename R, int NI_, int NO_>
-__device__ __forceinline__ void gather_b2g_impl(const SweepArgs &a, int off, int nfib, int ni,
+__device__ __forceinline__ void gather_b2g_impl(const TermCtx &a, int off, int nfib, int ni,
                                                 int no, const R *__restrict__ M,
                                                 typename Cx<R>::T *__restrict__ out) {
   typedef typename Cx<R>::T C;
@@ -215,7 +224,7 @@ __device__ __forceinline__ void gather_b2g_impl(const SweepArgs &a, int off, int
 }
 
 template <typename G, typename R>
-__device__ __forceinline__ void gather_b2g(const SweepArgs &a, int level, int nb, int nq, int off,
+__device__ __forceinline__ void gather_b2g(const TermCtx &a, int level, int nb, int nq, int off,
                                            int nfib, const R *M, typename Cx<R>::T *out) {
   if (a.std_maps) {
     switch (level) {
@@ -293,7 +302,7 @@ __device__ __forceinline__ void g2b_store(int std_maps, int level, int nb, int n
 //       + sum_{p<q} (c_pq Q_p^2 Q_q^2 + k_pq Q_p^2 Q_q).
 // ---------------------------------------------------------------------------
 template <typename G, typename R, int NQ_, bool KIN>
-__device__ __forceinline__ void potential_impl(const SweepArgs &a, const TermDev *T,
+__device__ __forceinline__ void potential_impl(const TermCtx &a, const TermDev *T,
                                                const typename Cx<R>::T *__restrict__ src,
                                                typename Cx<R>::T *__restrict__ dst, int nfib) {
   typedef typename Cx<R>::T C;
@@ -310,7 +319,7 @@ __device__ __forceinline__ void potential_impl(const SweepArgs &a, const TermDev
   const R c0 = cv(split ? T->c0_split : T->c0_full);
   const R al0 = cv(split ? T->alpha_split[0] : T->alpha_full[0]);
   const R be0 = cv(T->beta[0]);
-  const double *pc = a.pairs + (size_t)(T - a.terms) * (2 * kMaxPairs);
+  const double *pc = a.pc;
   for (int f = G::tid(); f < nfib; f += G::N) {
     R xq[kMaxActive];
     int rem = f;
@@ -377,7 +386,7 @@ __device__ __forceinline__ void potential_impl(const SweepArgs &a, const TermDev
 }
 
 template <typename G, typename R>
-__device__ __forceinline__ void potential(const SweepArgs &a, const TermDev *T, int level0,
+__device__ __forceinline__ void potential(const TermCtx &a, const TermDev *T, int level0,
                                           const typename Cx<R>::T *src, typename Cx<R>::T *dst,
                                           int nfib) {
   const bool kin = a.split == 0;
@@ -406,7 +415,7 @@ __device__ __forceinline__ void potential(const SweepArgs &a, const TermDev *T, 
 // The whole of Alg. 1 for one term, by the threads of G, with two LDS
 // buffers of `buf` complex values each.
 template <typename G, typename R>
-__device__ __forceinline__ void run_term(const SweepArgs &a, const TermDev *T,
+__device__ __forceinline__ void run_term(const TermCtx &a, const TermDev *T,
                                          typename Cx<R>::T *lds, int buf) {
   typedef typename Cx<R>::T C;
   const R *tab = (const R *)a.tab;
@@ -480,20 +489,54 @@ __device__ __forceinline__ void run_term(const SweepArgs &a, const TermDev *T,
   }
 }
 
+// Is instance I part of this launch, and which vector does H act on?
+__device__ __forceinline__ bool live(const SweepArgs &a, const InstDev *I) {
+  return I->active && (a.mode == 0 || a.k <= I->K - 1);
+}
+__device__ __forceinline__ const double2 *input_of(const SweepArgs &a, const InstDev *I) {
+  double2 *x0 = a.x0o ? a.x0o : I->x0;
+  double2 *x1 = a.x1o ? a.x1o : I->x1;
+  if (a.mode == 0) return x0;
+  return ((a.k - 1) & 1) ? x1 : x0;   // phi_{k-1}
+}
+
+template <typename R>
+__device__ __forceinline__ TermCtx make_ctx(const SweepArgs &a, const InstDev *I, int t) {
+  TermCtx c;
+  c.mb = I->mb;
+  c.psi = input_of(a, I);
+  c.tm = I->tm;
+  c.pc = I->pairs + (size_t)t * (2 * kMaxPairs);
+  c.std_maps = I->std_maps;
+  c.split = a.split;
+  c.round32 = (a.split && I->round32) ? 1 : 0;
+  if (sizeof(R) == sizeof(float)) c.tab = I->tab32;
+  else c.tab = c.round32 ? (const void *)I->tab32r : (const void *)I->tab64;
+  return c;
+}
+
 template <typename R>
 __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
   extern __shared__ char lds_raw[];
   typedef typename Cx<R>::T C;
   const PackDev *P = a.packs + blockIdx.x;
   if (P->block) {
-    const TermDev *T = a.terms + P->term[0];
-    run_term<BlockGroup, R>(a, T, (C *)lds_raw, T->ngrid);
+    const InstDev *I = a.inst + P->inst[0];
+    if (!live(a, I)) return;
+    const int t = P->term[0];
+    const TermDev *T = I->terms + t;
+    const TermCtx c = make_ctx<R>(a, I, t);
+    if (P->block == 1) run_term<BlockGroup, R>(c, T, (C *)lds_raw, T->ngrid);
+    else run_term<BlockGroup, R>(c, T, (C *)(a.scratch + P->scratch_off), T->ngrid);
     return;
   }
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (w >= P->n) return;
-  const TermDev *T = a.terms + P->term[w];
-  run_term<WaveGroup, R>(a, T, (C *)(lds_raw + P->lds_off[w]), T->ngrid);
+  const InstDev *I = a.inst + P->inst[w];
+  if (!live(a, I)) return;
+  const int t = P->term[w];
+  const TermCtx c = make_ctx<R>(a, I, t);
+  run_term<WaveGroup, R>(c, I->terms + t, (C *)(lds_raw + P->lds_off[w]), I->terms[t].ngrid);
 }
 
 template <typename R>
@@ -511,41 +554,34 @@ hipError_t launch_packs(const SweepArgs &a, int npacks, int lds, hipStream_t s) 
 
 }  // namespace
 
-hipError_t launch_sweep(const sg_problem *p, const double2 *psi, sg_precision prec,
-                        hipStream_t s) {
+hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   SweepArgs a;
-  a.terms = p->d_terms;
-  a.mb = p->d_mb;
-  a.psi = psi;
-  a.tm = p->d_tm;
-  a.pairs = p->d_pairs;
-  a.std_maps = (p->h.nbA == 1 && p->h.nbB == 2 && p->h.nqA == 2 && p->h.nqB == 2) ? 1 : 0;
-  a.split = prec == SG_MIXED ? 1 : 0;
-  // FP64 terms of a mixed launch use the FP32-rounded tables, so that every
-  // term applies the same one-mode operators and the Smolyak combination
-  // cancels their rounding as it does when all terms run in FP32; with no
-  // FP32 term at all, the exact tables are used.
-  const bool any32 = p->h.sets[2].count > 0;
-  a.round32 = (prec == SG_MIXED && any32) ? 1 : 0;
+  a.inst = pl->d_inst;
+  a.scratch = pl->d_scratch;
+  a.x0o = c.x0o;
+  a.x1o = c.x1o;
+  a.mode = c.mode == Mode::Cheb ? 1 : 0;
+  a.k = c.k;
+  a.split = c.prec == SG_MIXED ? 1 : 0;
   hipError_t e = hipSuccess;
-  if (prec == SG_FP64) {
-    const PackSet &ps = p->h.sets[0];
+  if (c.prec == SG_FP64) {
+    const PackSet &ps = pl->sets[0];
     if (ps.count == 0) return hipSuccess;
-    a.packs = p->d_packs + ps.first;
-    a.tab = p->d_tables;
+    a.packs = pl->d_packs + ps.first;
     return launch_packs<double>(a, ps.count, ps.lds_bytes, s);
   }
-  // mixed: terms with large |D_l| in FP64, the rest in FP32
-  const PackSet &p64 = p->h.sets[1], &p32 = p->h.sets[2];
+  // mixed: terms with large |D_l| in FP64, the rest in FP32.  The FP64 terms
+  // of an instance that also has FP32 terms read the FP32-rounded tables, so
+  // that all its terms apply the same one-mode operators and the Smolyak
+  // combination cancels their rounding as it does when all run in FP32.
+  const PackSet &p64 = pl->sets[1], &p32 = pl->sets[2];
   if (p64.count > 0) {
-    a.packs = p->d_packs + p64.first;
-    a.tab = any32 ? p->d_tables32r : p->d_tables;
+    a.packs = pl->d_packs + p64.first;
     e = launch_packs<double>(a, p64.count, p64.lds_bytes, s);
     if (e != hipSuccess) return e;
   }
   if (p32.count > 0) {
-    a.packs = p->d_packs + p32.first;
-    a.tab = p->d_tables32;
+    a.packs = pl->d_packs + p32.first;
     e = launch_packs<float>(a, p32.count, p32.lds_bytes, s);
   }
   return e;

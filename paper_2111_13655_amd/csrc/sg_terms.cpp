@@ -37,10 +37,6 @@ namespace {
 
 inline int size_map(int A, int B, int l) { return A + B * l; }
 
-bool mul_overflows(int64_t a, int64_t b, int64_t limit) {
-  return a != 0 && b > limit / a;
-}
-
 }  // namespace
 
 sg_status count_sizes(int D, int L, int nbA, int nbB, int64_t out[3]) {
@@ -425,8 +421,10 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
   h.cost = cost;
   h.tables32.assign(h.tables.begin(), h.tables.end());
   h.tables32r.assign(h.tables32.begin(), h.tables32.end());
-  sg_status ps = build_pack_sets(&h, err);
-  if (ps != SG_OK) return ps;
+  if (h.max_grid > 65536) {
+    *err = "a term grid exceeds 65536 points";
+    return SG_EINVAL;
+  }
 
   // reduce rows: long rows (a wavefront each) first, then short rows
   h.rows.clear();
@@ -436,115 +434,8 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
   h.n_long_rows = (int64_t)h.rows.size();
   for (int64_t r = 0; r < h.ncs; ++r)
     if (h.inv_ptr[r + 1] - h.inv_ptr[r] <= kLongRow) h.rows.push_back((int32_t)r);
+  h.n_items = h.n_long_rows + (h.ncs - h.n_long_rows + kShortLanes - 1) / kShortLanes;
   return SG_OK;
-}
-
-namespace {
-
-// Packs the given terms for one sweep launch.  Terms above kWaveMaxGrid grid
-// points get a workgroup each; the others are dealt, longest first, to the
-// least loaded of B packs of at most kPackTerms terms (one wavefront each),
-// with B large enough to give every compute unit work.  Each term needs two
-// LDS buffers of ngrid complex values of elem_bytes each.
-sg_status pack_terms(const Compiled &h, const std::vector<int32_t> &ids, int elem_bytes,
-                     std::vector<PackDev> *out, PackSet *set, std::string *err) {
-  set->first = (int32_t)out->size();
-  set->count = 0;
-  set->lds_bytes = 0;
-  if (ids.empty()) return SG_OK;
-  auto slice = [&](int32_t t) {
-    const int b = 2 * h.terms[t].ngrid * elem_bytes;
-    return (b + 15) & ~15;
-  };
-  std::vector<int32_t> big, small;
-  for (int32_t t : ids) (h.terms[t].ngrid > kWaveMaxGrid ? big : small).push_back(t);
-  auto by_cost = [&](int32_t a, int32_t b) { return h.cost[a] > h.cost[b]; };
-  std::stable_sort(big.begin(), big.end(), by_cost);
-  std::stable_sort(small.begin(), small.end(), by_cost);
-  int lds = 0;
-  for (int32_t t : big) {
-    if (slice(t) > kLdsPerCU) {
-      *err = "a term grid exceeds the on-chip buffer";
-      return SG_EINVAL;
-    }
-    lds = std::max(lds, slice(t));
-  }
-  // packs of small terms: enough of them to occupy every compute unit
-  const int64_t nsmall = (int64_t)small.size();
-  int64_t nbins = (nsmall + kPackTerms - 1) / kPackTerms;
-  const int small_lds = kPackTerms * ((2 * kWaveMaxGrid * elem_bytes + 15) & ~15);
-  const int per_cu = std::max(1, kLdsPerCU / std::max(lds, small_lds));
-  const int64_t want = (int64_t)kComputeUnits * per_cu - (int64_t)big.size();
-  nbins = std::max<int64_t>(nbins, std::min<int64_t>(nsmall, want));
-  struct Bin {
-    double load;
-    int64_t id;
-  };
-  auto worse = [](const Bin &a, const Bin &b) {
-    return a.load > b.load || (a.load == b.load && a.id > b.id);
-  };
-  std::vector<Bin> heap;
-  std::vector<PackDev> bins((size_t)nbins);
-  std::vector<int> bin_bytes((size_t)nbins, 0);
-  for (int64_t i = 0; i < nbins; ++i) {
-    std::memset(&bins[i], 0, sizeof(PackDev));
-    heap.push_back({0.0, i});
-  }
-  std::make_heap(heap.begin(), heap.end(), worse);
-  for (int32_t t : small) {
-    std::pop_heap(heap.begin(), heap.end(), worse);
-    Bin b = heap.back();
-    heap.pop_back();
-    PackDev &pk = bins[b.id];
-    pk.term[pk.n] = t;
-    pk.lds_off[pk.n] = bin_bytes[b.id];
-    bin_bytes[b.id] += slice(t);
-    pk.n += 1;
-    b.load += h.cost[t];
-    if (pk.n < kPackTerms) {
-      heap.push_back(b);
-      std::push_heap(heap.begin(), heap.end(), worse);
-    }
-  }
-  for (int32_t t : big) {
-    PackDev pk;
-    std::memset(&pk, 0, sizeof(pk));
-    pk.n = 1;
-    pk.block = 1;
-    pk.term[0] = t;
-    out->push_back(pk);
-  }
-  // small packs, most loaded first
-  std::vector<int64_t> order((size_t)nbins);
-  std::vector<double> load((size_t)nbins, 0.0);
-  for (int64_t i = 0; i < nbins; ++i) {
-    order[i] = i;
-    for (int j = 0; j < bins[i].n; ++j) load[i] += h.cost[bins[i].term[j]];
-  }
-  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return load[a] > load[b]; });
-  for (int64_t i : order) {
-    if (bins[i].n == 0) continue;
-    out->push_back(bins[i]);
-    lds = std::max(lds, bin_bytes[i]);
-  }
-  set->count = (int32_t)(out->size() - set->first);
-  set->lds_bytes = lds;
-  return SG_OK;
-}
-
-}  // namespace
-
-sg_status build_pack_sets(Compiled *h, std::string *err) {
-  h->packs.clear();
-  std::vector<int32_t> all, mix64, mix32;
-  for (int64_t t = 0; t < h->nterms; ++t) {
-    all.push_back((int32_t)t);
-    (std::abs(h->coeff[t]) <= h->mixed_max_fp32_coeff ? mix32 : mix64).push_back((int32_t)t);
-  }
-  sg_status st = pack_terms(*h, all, (int)sizeof(double2), &h->packs, &h->sets[0], err);
-  if (st == SG_OK) st = pack_terms(*h, mix64, (int)sizeof(double2), &h->packs, &h->sets[1], err);
-  if (st == SG_OK) st = pack_terms(*h, mix32, (int)sizeof(float2), &h->packs, &h->sets[2], err);
-  return st;
 }
 
 }  // namespace sg
