@@ -28,6 +28,9 @@ if ROOT not in sys.path:
 
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
+# Sources whose change invalidates recorded HBM counters of the sweep kernel.
+KERNEL_SOURCES = ["paper_2111_13655_amd/csrc/sg_sweep.hip", "paper_2111_13655_amd/csrc/sg_internal.h",
+                  "paper_2111_13655_amd/csrc/sg_plan.cpp"]
 
 WORKLOADS = {
     "d6_l6_fp64": dict(D=6, L=6, dt=0.05, check_every=100, precision="fp64",
@@ -47,6 +50,34 @@ def instance_for(name):
     import sg_inputs
     return {"d6_l6_fp64": sg_inputs.config1, "d2_l4_fp64": sg_inputs.config0,
             "d12_l6_mixed": sg_inputs.config2}[name]()
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the rocprofv3 counter summaries
+    under profiles/ (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or None when
+    none was recorded for this workload or the kernel sources changed since."""
+    import glob
+    want = kernel_sources_sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("traffic-data:"):
+                    continue
+                kv = dict(tok.split("=", 1) for tok in line.split()[1:] if "=" in tok)
+                if kv.get("workload") == workload and kv.get("kernel") == kernel:
+                    if kv.get("sources_sha256") != want:
+                        return None
+                    return float(kv["bytes_per_launch"])
+    return None
 
 
 def cpu_baseline(inst, info, budget_s: float):
@@ -88,6 +119,9 @@ def main():
     ap.add_argument("--latency-samples", type=int, default=1000)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (the "
+                         "reference kernel for scaling HBM byte counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -97,6 +131,16 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes,
+                          "launches": 3}), flush=True)
+        return
     import paper_2111_13655_amd as sg
 
     wl = WORKLOADS[args.workload]
@@ -193,7 +237,9 @@ def main():
         "status": int(status),
         "kernel_avg_us": {"term_sweep": sweep_avg_s * 1e6, "reduce": reduce_avg_s * 1e6},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved_tflops / peak,
+                     "traffic": recorded_traffic(f"{args.workload}/{prec_name}",
+                                                 "sweep_kernel<double>"),
                      "kernel": "sweep_kernel",
                      "flops_per_launch": sweep_flops},
     }

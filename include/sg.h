@@ -281,9 +281,10 @@ sg_status sg_tune_mixed(sg_problem *p, const void *psi, double tol, int32_t reps
                         int32_t *chosen, double *chosen_error, void *stream);
 
 /* Per-kernel timing for measurement.  sg_set_timing(p, 1) resets the
- * counters and brackets every term-sweep and reduce launch made through this
- * handle with a pair of HIP events on the launch stream (the events add a
- * small gap between kernels; leave timing off for throughput runs).
+ * counters and attaches a pair of HIP events to every term-sweep and reduce
+ * launch made through this handle (hipExtLaunchKernel: the events take the
+ * start and end timestamps of the kernel dispatches themselves, so the
+ * durations are the kernels' and no marker packet enters the stream).
  * sg_get_timing waits for the recorded events and returns the summed kernel
  * durations. */
 typedef struct {

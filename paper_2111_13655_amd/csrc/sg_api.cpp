@@ -51,19 +51,20 @@ hipError_t flush_timing(sg_problem *p) {
   return hipSuccess;
 }
 
+// The events are attached to the kernel dispatches (start of the first,
+// end of the last), so a pair measures the kernels and no event packets.
 template <typename F>
-hipError_t timed(sg_problem *p, int kind, hipStream_t s, F launch) {
+hipError_t timed(sg_problem *p, int kind, hipStream_t s, const LaunchCtl &c, F launch) {
   auto &T = p->timing;
-  if (!T.on) return launch();
+  if (!T.on) return launch(c);
   if (T.used == kTimingPairs) {
     hipError_t e = flush_timing(p);
     if (e != hipSuccess) return e;
   }
-  hipError_t e = hipEventRecord(T.ev[2 * T.used], s);
-  if (e != hipSuccess) return e;
-  e = launch();
-  if (e != hipSuccess) return e;
-  e = hipEventRecord(T.ev[2 * T.used + 1], s);
+  LaunchCtl ct = c;
+  ct.ev0 = T.ev[2 * T.used];
+  ct.ev1 = T.ev[2 * T.used + 1];
+  hipError_t e = launch(ct);
   if (e != hipSuccess) return e;
   T.kind[T.used] = kind;
   T.used += 1;
@@ -105,12 +106,12 @@ void release(sg_problem *p) {
 
 hipError_t run_sweep(sg_problem *owner, const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   if (!owner) return launch_sweep(pl, c, s);
-  return timed(owner, 0, s, [&] { return launch_sweep(pl, c, s); });
+  return timed(owner, 0, s, c, [&](const LaunchCtl &ct) { return launch_sweep(pl, ct, s); });
 }
 
 hipError_t run_reduce(sg_problem *owner, const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   if (!owner) return launch_reduce(pl, c, s);
-  return timed(owner, 1, s, [&] { return launch_reduce(pl, c, s); });
+  return timed(owner, 1, s, c, [&](const LaunchCtl &ct) { return launch_reduce(pl, ct, s); });
 }
 
 }  // namespace sg

@@ -43,13 +43,18 @@ struct alignas(16) TermDev {
   int32_t xo[kMaxActive];
   float rcp_nq[kMaxActive]; //   1/nq for fast index division
   double coeff;             // D_l
-  double c0_full;           // constant part of the effective potential, FP64 path
-  double c0_split;          // ... without the harmonic part (mixed path)
-  double alpha_full[kMaxActive];   // coefficient of Q_p^2, FP64 path
-  double alpha_split[kMaxActive];  // ... without 1/2 omega_p (mixed path)
-  double beta[kMaxActive];         // coefficient of Q_p
+  // Effective-potential coefficients in three variants (kPot*): the FP64
+  // path; the mixed path (no separable harmonic part); the mixed path's
+  // values rounded to FP32 (held in FP64), for instances whose FP64 terms
+  // must apply the same rounded operator as their FP32 terms.
+  double c0[3];                    // constant part
+  double alpha[3][kMaxActive];     // coefficient of Q_p^2
+  double beta[2][kMaxActive];      // coefficient of Q_p: exact, rounded
   double kin[kMaxActive];          // -1/2 omega_p (kinetic prefactor)
 };
+constexpr int kPotFull = 0, kPotSplit = 1, kPotSplitRounded = 2;
+// Pair coefficients per term: [2 variants: exact, FP32-rounded][kMaxPairs][c, k].
+constexpr int kPairStride = 4 * kMaxPairs;
 
 // Offsets of the one-mode tables of a level inside the packed table array.
 struct LevelDev {
@@ -203,7 +208,7 @@ struct sg_problem {
   int32_t *d_inv_col = nullptr;
   int32_t *d_rows = nullptr;
   double *d_tables = nullptr;
-  double *d_pairs = nullptr;       // [nterms][kMaxPairs][2]
+  double *d_pairs = nullptr;       // [nterms][kPairStride]
   double *d_h0 = nullptr;
   // work buffers
   double2 *d_tm = nullptr;         // term-major results [N_s]
@@ -266,6 +271,10 @@ struct LaunchCtl {
   int want_partials = 0;
   double2 *x0o = nullptr;
   double2 *x1o = nullptr;
+  // Optional timing events attached to the dispatches themselves (start of
+  // the first kernel of the launch, end of the last one).
+  hipEvent_t ev0 = nullptr;
+  hipEvent_t ev1 = nullptr;
 };
 hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s);
 hipError_t launch_reduce(const Plan *pl, const LaunchCtl &c, hipStream_t s);

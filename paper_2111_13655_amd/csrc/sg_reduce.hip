@@ -8,6 +8,8 @@
 // instances share the launch.  The exact FP64 diagonal part of the mixed
 // path, the Chebyshev recurrence, the series accumulation and the norm /
 // energy partial sums are fused into the epilogue.
+#include <hip/hip_ext.h>
+
 #include "sg_internal.h"
 
 namespace sg {
@@ -245,7 +247,11 @@ hipError_t launch_reduce(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   a.split = c.prec == SG_MIXED ? 1 : 0;
   const int64_t blocks = (a.nitems + (kRedThreads / 64) - 1) / (kRedThreads / 64);
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)blocks), dim3(kRedThreads), 0, s, a);
+  if (c.ev0 || c.ev1)
+    hipExtLaunchKernelGGL(reduce_kernel, dim3((unsigned)blocks), dim3(kRedThreads), 0, s, c.ev0,
+                          c.ev1, 0, a);
+  else
+    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)blocks), dim3(kRedThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -23,6 +23,8 @@
 // of the term record, so a wave issues independent scalar loads.
 // The arithmetic type R is double (FP64 path, and the high-|D_l| terms of the
 // mixed path) or float (the other terms of the mixed path).
+#include <hip/hip_ext.h>
+
 #include "sg_internal.h"
 
 namespace sg {
@@ -31,21 +33,33 @@ namespace {
 
 constexpr int kThreads = 512;
 
-// What one term's computation reads and writes (built per term slot).
+// Address-space-qualified pointers.  Grid buffers live in LDS (or, for terms
+// too large for LDS, in global scratch); HBM data are global; per-term
+// records, coefficient blocks and one-mode matrices are wave-uniform and are
+// read through the constant address space, i.e. with scalar loads.
+template <typename T> using lds_p = __attribute__((address_space(3))) T *;
+template <typename T> using glb_p = __attribute__((address_space(1))) T *;
+template <typename T> using cptr = const __attribute__((address_space(4))) T *;
+
+// Plain complex values (trivially copyable across address spaces; the
+// layout of double2 / float2).
+struct alignas(16) Z64 { double x, y; };
+struct alignas(8) Z32 { float x, y; };
+// What one term's computation reads and writes.
 struct TermCtx {
-  const int32_t *mb;
-  const double2 *psi;    // the vector H is applied to
-  double2 *tm;
-  const void *tab;       // one-mode tables in the arithmetic type
-  const double *pc;      // the term's pair coefficients
-  int std_maps;          // nb = 1 + 2l, nq = 2 + 2l
-  int split;             // operator without the separable harmonic part
-  int round32;           // FP64 arithmetic on FP32-rounded tables and coefficients
+  glb_p<const int32_t> mb;
+  glb_p<const Z64> psi;      // the vector H is applied to
+  glb_p<Z64> tm;
+  const void *tab;           // one-mode tables in the arithmetic type
+  cptr<double> pc;           // the term's pair coefficients (variant chosen)
+  int std_maps;              // nb = 1 + 2l, nq = 2 + 2l
+  int split;                 // operator without the separable harmonic part
+  int pot;                   // kPotFull / kPotSplit / kPotSplitRounded
 };
 
 struct SweepArgs {
-  const InstDev *inst;
-  const PackDev *packs;
+  cptr<InstDev> inst;
+  cptr<PackDev> packs;
   char *scratch;
   double2 *x0o, *x1o;    // single-instance buffer overrides (nullable)
   int mode;              // 0 apply, 1 Chebyshev
@@ -53,14 +67,29 @@ struct SweepArgs {
   int split;
 };
 
+// Element access through address-space-qualified pointers (member-wise: the
+// implicit copy of a struct binds a generic reference).
+template <typename C, typename P>
+__device__ __forceinline__ C ldc(P p) {
+  C v;
+  v.x = p->x;
+  v.y = p->y;
+  return v;
+}
+template <typename P, typename C>
+__device__ __forceinline__ void stc(P p, const C &v) {
+  p->x = v.x;
+  p->y = v.y;
+}
+
 template <typename R> struct Cx;
 template <> struct Cx<double> {
-  typedef double2 T;
-  static __device__ __forceinline__ double2 make(double a, double b) { return make_double2(a, b); }
+  typedef Z64 T;
+  static __device__ __forceinline__ Z64 make(double a, double b) { return Z64{a, b}; }
 };
 template <> struct Cx<float> {
-  typedef float2 T;
-  static __device__ __forceinline__ float2 make(float a, float b) { return make_float2(a, b); }
+  typedef Z32 T;
+  static __device__ __forceinline__ Z32 make(float a, float b) { return Z32{a, b}; }
 };
 
 // Threads of one term: a single wavefront, or the whole workgroup.
@@ -85,18 +114,20 @@ __device__ __forceinline__ int fdiv(int f, float rcp) {
   return __float2int_rz(((float)f + 0.5f) * rcp);
 }
 
-// A wave-uniform pointer re-derived inside a divergent loop, in the constant
-// (read-only global) address space.  readfirstlane is convergent, so it and
-// the scalar loads through the pointer stay in the loop body; hoisting all
-// matrix entries out of the fiber loop would spill them.
-template <typename R>
-using cptr = const __attribute__((address_space(4))) R *;
-template <typename R>
-__device__ __forceinline__ cptr<R> in_loop_uniform(const R *p) {
+// A wave-uniform pointer re-derived inside a divergent loop.  readfirstlane
+// is convergent, so it and the scalar loads through the pointer stay in the
+// loop body; hoisting every matrix entry or coefficient out of the fiber loop
+// would exhaust the scalar registers and spill.
+template <typename T>
+__device__ __forceinline__ cptr<T> in_loop_uniform(const T *p) {
   const uint64_t v = (uint64_t)p;
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return (cptr<R>)(((uint64_t)hi << 32) | lo);
+  return (cptr<T>)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ cptr<T> in_loop_uniform(cptr<T> p) {
+  return in_loop_uniform((const T *)p);
 }
 
 // Compile-time size when N_ > 0, run-time size n otherwise (loops are then
@@ -107,11 +138,10 @@ __device__ __forceinline__ cptr<R> in_loop_uniform(const R *p) {
 // ---------------------------------------------------------------------------
 // One-mode contraction over fibers.  Layout: out[lo + stride*(u + NO*hi)]
 // (+)= scale * sum_k M[u*NI + k] in[lo + stride*(k + NI*hi)].
+// P is the buffer pointer type (LDS or global scratch).
 // ---------------------------------------------------------------------------
-template <typename G, typename R, int NI_, int NO_, bool ACC>
-__device__ __forceinline__ void contract(const typename Cx<R>::T *__restrict__ in,
-                                         typename Cx<R>::T *__restrict__ out,
-                                         const R *__restrict__ M, R scale, int ni, int no,
+template <typename G, typename R, typename P, int NI_, int NO_, bool ACC>
+__device__ __forceinline__ void contract(P in, P out, const R *M, R scale, int ni, int no,
                                          int stride, int nouter) {
   typedef typename Cx<R>::T C;
   const int NI = NI_ > 0 ? NI_ : ni;
@@ -121,12 +151,12 @@ __device__ __forceinline__ void contract(const typename Cx<R>::T *__restrict__ i
   for (int f = G::tid(); f < F; f += G::N) {
     const int hi = fdiv(f, rcp);
     const int lo = f - hi * stride;
-    const C *src = in + lo + hi * (stride * NI);
-    C *dst = out + lo + hi * (stride * NO);
+    P src = in + lo + hi * (stride * NI);
+    P dst = out + lo + hi * (stride * NO);
     const cptr<R> Mw = in_loop_uniform(M);
     C x[SG_CN(NI_)];
 #pragma unroll
-    for (int k = 0; k < SG_CN(NI_); ++k) x[k] = SG_IN(NI_, k, NI) ? src[k * stride] : Cx<R>::make(0, 0);
+    for (int k = 0; k < SG_CN(NI_); ++k) x[k] = SG_IN(NI_, k, NI) ? ldc<C>(src + k * stride) : Cx<R>::make(0, 0);
 #pragma unroll 1
     for (int u = 0; u < NO; ++u) {
       R re = 0, im = 0;
@@ -139,12 +169,12 @@ __device__ __forceinline__ void contract(const typename Cx<R>::T *__restrict__ i
         }
       }
       if (ACC) {
-        C o = dst[u * stride];
+        C o = ldc<C>(dst + u * stride);
         o.x = fma(scale, re, o.x);
         o.y = fma(scale, im, o.y);
-        dst[u * stride] = o;
+        stc(dst + u * stride, o);
       } else {
-        dst[u * stride] = Cx<R>::make(re, im);
+        stc(dst + u * stride, Cx<R>::make(re, im));
       }
     }
   }
@@ -152,17 +182,16 @@ __device__ __forceinline__ void contract(const typename Cx<R>::T *__restrict__ i
 
 // kind 0: basis -> grid (NI = nb, NO = nq); 1: kinetic on the grid
 // (NI = NO = nq); 2: grid -> basis (NI = nq, NO = nb)
-template <typename G, typename R, bool ACC>
+template <typename G, typename R, typename P, bool ACC>
 __device__ __forceinline__ void contract_level(int kind, int level, int std_maps, int nb, int nq,
-                                               const typename Cx<R>::T *in,
-                                               typename Cx<R>::T *out, const R *M, R scale,
-                                               int stride, int nouter) {
+                                               P in, P out, const R *M, R scale, int stride,
+                                               int nouter) {
   if (std_maps) {
-#define SG_CASE(L_, NB_, NQ_)                                                                    \
-  case L_:                                                                                       \
-    if (kind == 0) contract<G, R, NB_, NQ_, ACC>(in, out, M, scale, nb, nq, stride, nouter);    \
-    else if (kind == 1) contract<G, R, NQ_, NQ_, ACC>(in, out, M, scale, nq, nq, stride, nouter); \
-    else contract<G, R, NQ_, NB_, ACC>(in, out, M, scale, nq, nb, stride, nouter);              \
+#define SG_CASE(L_, NB_, NQ_)                                                                       \
+  case L_:                                                                                          \
+    if (kind == 0) contract<G, R, P, NB_, NQ_, ACC>(in, out, M, scale, nb, nq, stride, nouter);    \
+    else if (kind == 1) contract<G, R, P, NQ_, NQ_, ACC>(in, out, M, scale, nq, nq, stride, nouter); \
+    else contract<G, R, P, NQ_, NB_, ACC>(in, out, M, scale, nq, nb, stride, nouter);              \
     return;
     switch (level) {
       SG_CASE(1, 3, 4)
@@ -178,35 +207,34 @@ __device__ __forceinline__ void contract_level(int kind, int level, int std_maps
   }
   const int NI = kind == 0 ? nb : nq;
   const int NO = kind == 2 ? nb : nq;
-  contract<G, R, 0, 0, ACC>(in, out, M, scale, NI, NO, stride, nouter);
+  contract<G, R, P, 0, 0, ACC>(in, out, M, scale, NI, NO, stride, nouter);
 }
 
 // ---------------------------------------------------------------------------
 // Step 1 fused with the first basis -> grid contraction: fibers along mode 0
 // are contiguous runs of the term-major layout, so each thread gathers its
-// fiber through M^B and writes the nq transformed values to LDS.
+// fiber through M^B and writes the nq transformed values to the buffer.
 // ---------------------------------------------------------------------------
-template <typename G, typename R, int NI_, int NO_>
+template <typename G, typename R, typename P, int NI_, int NO_>
 __device__ __forceinline__ void gather_b2g_impl(const TermCtx &a, int off, int nfib, int ni,
-                                                int no, const R *__restrict__ M,
-                                                typename Cx<R>::T *__restrict__ out) {
+                                                int no, const R *M, P out) {
   typedef typename Cx<R>::T C;
   const int NI = NI_ > 0 ? NI_ : ni;
   const int NO = NO_ > 0 ? NO_ : no;
   for (int f = G::tid(); f < nfib; f += G::N) {
-    const int32_t *mb = a.mb + off + f * NI;
+    glb_p<const int32_t> mb = a.mb + off + f * NI;
     const cptr<R> Mw = in_loop_uniform(M);
     C x[SG_CN(NI_)];
 #pragma unroll
     for (int k = 0; k < SG_CN(NI_); ++k) {
       if (SG_IN(NI_, k, NI)) {
-        const double2 v = a.psi[mb[k]];
+        const Z64 v = ldc<Z64>(a.psi + mb[k]);
         x[k] = Cx<R>::make((R)v.x, (R)v.y);
       } else {
         x[k] = Cx<R>::make(0, 0);
       }
     }
-    C *dst = out + f * NO;
+    P dst = out + f * NO;
 #pragma unroll 1
     for (int u = 0; u < NO; ++u) {
       R re = 0, im = 0;
@@ -218,38 +246,36 @@ __device__ __forceinline__ void gather_b2g_impl(const TermCtx &a, int off, int n
           im = fma(m, x[k].y, im);
         }
       }
-      dst[u] = Cx<R>::make(re, im);
+      stc(dst + u, Cx<R>::make(re, im));
     }
   }
 }
 
-template <typename G, typename R>
+template <typename G, typename R, typename P>
 __device__ __forceinline__ void gather_b2g(const TermCtx &a, int level, int nb, int nq, int off,
-                                           int nfib, const R *M, typename Cx<R>::T *out) {
+                                           int nfib, const R *M, P out) {
   if (a.std_maps) {
     switch (level) {
-      case 1: gather_b2g_impl<G, R, 3, 4>(a, off, nfib, nb, nq, M, out); return;
-      case 2: gather_b2g_impl<G, R, 5, 6>(a, off, nfib, nb, nq, M, out); return;
-      case 3: gather_b2g_impl<G, R, 7, 8>(a, off, nfib, nb, nq, M, out); return;
-      case 4: gather_b2g_impl<G, R, 9, 10>(a, off, nfib, nb, nq, M, out); return;
-      case 5: gather_b2g_impl<G, R, 11, 12>(a, off, nfib, nb, nq, M, out); return;
-      case 6: gather_b2g_impl<G, R, 13, 14>(a, off, nfib, nb, nq, M, out); return;
-      case 7: gather_b2g_impl<G, R, 15, 16>(a, off, nfib, nb, nq, M, out); return;
+      case 1: gather_b2g_impl<G, R, P, 3, 4>(a, off, nfib, nb, nq, M, out); return;
+      case 2: gather_b2g_impl<G, R, P, 5, 6>(a, off, nfib, nb, nq, M, out); return;
+      case 3: gather_b2g_impl<G, R, P, 7, 8>(a, off, nfib, nb, nq, M, out); return;
+      case 4: gather_b2g_impl<G, R, P, 9, 10>(a, off, nfib, nb, nq, M, out); return;
+      case 5: gather_b2g_impl<G, R, P, 11, 12>(a, off, nfib, nb, nq, M, out); return;
+      case 6: gather_b2g_impl<G, R, P, 13, 14>(a, off, nfib, nb, nq, M, out); return;
+      case 7: gather_b2g_impl<G, R, P, 15, 16>(a, off, nfib, nb, nq, M, out); return;
       default: break;
     }
   }
-  gather_b2g_impl<G, R, 0, 0>(a, off, nfib, nb, nq, M, out);
+  gather_b2g_impl<G, R, P, 0, 0>(a, off, nfib, nb, nq, M, out);
 }
 
 // ---------------------------------------------------------------------------
 // Step 4's last contraction: grid -> basis along the slowest active mode
 // (nouter = 1), written as D_l * result in FP64 to the term-major buffer.
 // ---------------------------------------------------------------------------
-template <typename G, typename R, int NI_, int NO_>
-__device__ __forceinline__ void g2b_store_impl(const typename Cx<R>::T *__restrict__ in,
-                                               double2 *__restrict__ tm,
-                                               const R *__restrict__ M, double cf, int ni,
-                                               int no, int stride) {
+template <typename G, typename R, typename P, int NI_, int NO_>
+__device__ __forceinline__ void g2b_store_impl(P in, glb_p<Z64> tm, const R *M, double cf,
+                                               int ni, int no, int stride) {
   typedef typename Cx<R>::T C;
   const int NI = NI_ > 0 ? NI_ : ni;
   const int NO = NO_ > 0 ? NO_ : no;
@@ -258,7 +284,7 @@ __device__ __forceinline__ void g2b_store_impl(const typename Cx<R>::T *__restri
     C x[SG_CN(NI_)];
 #pragma unroll
     for (int k = 0; k < SG_CN(NI_); ++k)
-      x[k] = SG_IN(NI_, k, NI) ? in[lo + k * stride] : Cx<R>::make(0, 0);
+      x[k] = SG_IN(NI_, k, NI) ? ldc<C>(in + lo + k * stride) : Cx<R>::make(0, 0);
 #pragma unroll 1
     for (int u = 0; u < NO; ++u) {
       R re = 0, im = 0;
@@ -270,28 +296,27 @@ __device__ __forceinline__ void g2b_store_impl(const typename Cx<R>::T *__restri
           im = fma(m, x[k].y, im);
         }
       }
-      tm[lo + u * stride] = make_double2(cf * (double)re, cf * (double)im);
+      stc(tm + lo + u * stride, Z64{cf * (double)re, cf * (double)im});
     }
   }
 }
 
-template <typename G, typename R>
-__device__ __forceinline__ void g2b_store(int std_maps, int level, int nb, int nq,
-                                          const typename Cx<R>::T *in, double2 *tm, const R *M,
-                                          double cf, int stride) {
+template <typename G, typename R, typename P>
+__device__ __forceinline__ void g2b_store(int std_maps, int level, int nb, int nq, P in,
+                                          glb_p<Z64> tm, const R *M, double cf, int stride) {
   if (std_maps) {
     switch (level) {
-      case 1: g2b_store_impl<G, R, 4, 3>(in, tm, M, cf, nq, nb, stride); return;
-      case 2: g2b_store_impl<G, R, 6, 5>(in, tm, M, cf, nq, nb, stride); return;
-      case 3: g2b_store_impl<G, R, 8, 7>(in, tm, M, cf, nq, nb, stride); return;
-      case 4: g2b_store_impl<G, R, 10, 9>(in, tm, M, cf, nq, nb, stride); return;
-      case 5: g2b_store_impl<G, R, 12, 11>(in, tm, M, cf, nq, nb, stride); return;
-      case 6: g2b_store_impl<G, R, 14, 13>(in, tm, M, cf, nq, nb, stride); return;
-      case 7: g2b_store_impl<G, R, 16, 15>(in, tm, M, cf, nq, nb, stride); return;
+      case 1: g2b_store_impl<G, R, P, 4, 3>(in, tm, M, cf, nq, nb, stride); return;
+      case 2: g2b_store_impl<G, R, P, 6, 5>(in, tm, M, cf, nq, nb, stride); return;
+      case 3: g2b_store_impl<G, R, P, 8, 7>(in, tm, M, cf, nq, nb, stride); return;
+      case 4: g2b_store_impl<G, R, P, 10, 9>(in, tm, M, cf, nq, nb, stride); return;
+      case 5: g2b_store_impl<G, R, P, 12, 11>(in, tm, M, cf, nq, nb, stride); return;
+      case 6: g2b_store_impl<G, R, P, 14, 13>(in, tm, M, cf, nq, nb, stride); return;
+      case 7: g2b_store_impl<G, R, P, 16, 15>(in, tm, M, cf, nq, nb, stride); return;
       default: break;
     }
   }
-  g2b_store_impl<G, R, 0, 0>(in, tm, M, cf, nq, nb, stride);
+  g2b_store_impl<G, R, P, 0, 0>(in, tm, M, cf, nq, nb, stride);
 }
 
 // ---------------------------------------------------------------------------
@@ -300,26 +325,25 @@ __device__ __forceinline__ void g2b_store(int std_maps, int level, int nb, int n
 // potential is A + B Q_0^2 + C Q_0 with A, B, C computed once per fiber from
 // V_eff = c0 + sum_p (alpha_p Q_p^2 + beta_p Q_p)
 //       + sum_{p<q} (c_pq Q_p^2 Q_q^2 + k_pq Q_p^2 Q_q).
+// The coefficients are read with scalar loads from the term record and the
+// term's pair block, in the variant the context selects.
 // ---------------------------------------------------------------------------
-template <typename G, typename R, int NQ_, bool KIN>
-__device__ __forceinline__ void potential_impl(const TermCtx &a, const TermDev *T,
-                                               const typename Cx<R>::T *__restrict__ src,
-                                               typename Cx<R>::T *__restrict__ dst, int nfib) {
+template <typename G, typename R, typename P, int NQ_, bool KIN>
+__device__ __forceinline__ void potential_impl(const TermCtx &a, cptr<TermDev> T, P src, P dst,
+                                               int nfib) {
   typedef typename Cx<R>::T C;
   const R *tab = (const R *)a.tab;
+  const glb_p<const R> tg = (glb_p<const R>)tab;   // per-lane node reads
   const int na = T->na;
   const int NQ = NQ_ > 0 ? NQ_ : T->nq[0];
   const R *x0 = tab + T->xo[0];
   const R *K0 = tab + T->kg[0];
   const R kin0 = (R)T->kin[0];
-  const bool split = a.split != 0;
-  // mixed-path FP64 terms round coefficients as the FP32 terms do
-  const bool r32 = a.round32 != 0;
-  auto cv = [r32](double v) -> R { return (R)(r32 ? (double)(float)v : v); };
-  const R c0 = cv(split ? T->c0_split : T->c0_full);
-  const R al0 = cv(split ? T->alpha_split[0] : T->alpha_full[0]);
-  const R be0 = cv(T->beta[0]);
-  const double *pc = a.pc;
+  const int pot = a.pot;
+  const int bv = pot == kPotSplitRounded ? 1 : 0;
+  const R c0 = (R)T->c0[pot];
+  const R al0 = (R)T->alpha[pot][0];
+  const R be0 = (R)T->beta[bv][0];
   for (int f = G::tid(); f < nfib; f += G::N) {
     R xq[kMaxActive];
     int rem = f;
@@ -330,42 +354,44 @@ __device__ __forceinline__ void potential_impl(const TermCtx &a, const TermDev *
         const int hi = fdiv(rem, T->rcp_nq[q]);
         const int u = rem - hi * T->nq[q];
         rem = hi;
-        xq[q] = tab[T->xo[q] + u];
+        xq[q] = tg[T->xo[q] + u];
       }
     }
+    const cptr<double> al = in_loop_uniform(&T->alpha[pot][0]);
+    const cptr<double> be = in_loop_uniform(&T->beta[bv][0]);
+    const cptr<double> pc = in_loop_uniform(a.pc);
     R A = c0, B = al0, Cc = be0;
 #pragma unroll
     for (int q = 1; q < kMaxActive; ++q) {
       if (q < na) {
         const R x2 = xq[q] * xq[q];
-        const R alq = cv(split ? T->alpha_split[q] : T->alpha_full[q]);
-        A = fma(alq, x2, A);
-        A = fma(cv(T->beta[q]), xq[q], A);
-        B = fma(cv(pc[2 * pair_index(0, q)]), x2, B);
-        B = fma(cv(pc[2 * pair_index(0, q) + 1]), xq[q], B);
+        A = fma((R)al[q], x2, A);
+        A = fma((R)be[q], xq[q], A);
+        B = fma((R)pc[2 * pair_index(0, q)], x2, B);
+        B = fma((R)pc[2 * pair_index(0, q) + 1], xq[q], B);
 #pragma unroll
         for (int r = q + 1; r < kMaxActive; ++r) {
           if (r < na) {
-            A = fma(cv(pc[2 * pair_index(q, r)]) * x2, xq[r] * xq[r], A);
-            A = fma(cv(pc[2 * pair_index(q, r) + 1]) * x2, xq[r], A);
+            A = fma((R)pc[2 * pair_index(q, r)] * x2, xq[r] * xq[r], A);
+            A = fma((R)pc[2 * pair_index(q, r) + 1] * x2, xq[r], A);
           }
         }
       }
     }
-    const C *s = src + f * NQ;
-    C *d = dst + f * NQ;
+    P s = src + f * NQ;
+    P d = dst + f * NQ;
     const cptr<R> Kw = in_loop_uniform(K0);
     const cptr<R> xw = in_loop_uniform(x0);
     C x[SG_CN(NQ_)];
     if (KIN) {
 #pragma unroll
-      for (int u = 0; u < SG_CN(NQ_); ++u) x[u] = SG_IN(NQ_, u, NQ) ? s[u] : Cx<R>::make(0, 0);
+      for (int u = 0; u < SG_CN(NQ_); ++u) x[u] = SG_IN(NQ_, u, NQ) ? ldc<C>(s + u) : Cx<R>::make(0, 0);
     }
 #pragma unroll 1
     for (int u = 0; u < NQ; ++u) {
       const R xv = xw[u];
       const R V = fma(fma(B, xv, Cc), xv, A);
-      const C xu = s[u];
+      const C xu = ldc<C>(s + u);
       R re = V * xu.x, im = V * xu.y;
       if (KIN) {
         R kr = 0, ki = 0;
@@ -380,21 +406,20 @@ __device__ __forceinline__ void potential_impl(const TermCtx &a, const TermDev *
         re = fma(kin0, kr, re);
         im = fma(kin0, ki, im);
       }
-      d[u] = Cx<R>::make(re, im);
+      stc(d + u, Cx<R>::make(re, im));
     }
   }
 }
 
-template <typename G, typename R>
-__device__ __forceinline__ void potential(const TermCtx &a, const TermDev *T, int level0,
-                                          const typename Cx<R>::T *src, typename Cx<R>::T *dst,
-                                          int nfib) {
+template <typename G, typename R, typename P>
+__device__ __forceinline__ void potential(const TermCtx &a, cptr<TermDev> T, int level0, P src,
+                                          P dst, int nfib) {
   const bool kin = a.split == 0;
   if (a.std_maps) {
-#define SG_PCASE(L_, NQ_)                                                   \
-  case L_:                                                                  \
-    if (kin) potential_impl<G, R, NQ_, true>(a, T, src, dst, nfib);         \
-    else potential_impl<G, R, NQ_, false>(a, T, src, dst, nfib);            \
+#define SG_PCASE(L_, NQ_)                                                     \
+  case L_:                                                                    \
+    if (kin) potential_impl<G, R, P, NQ_, true>(a, T, src, dst, nfib);        \
+    else potential_impl<G, R, P, NQ_, false>(a, T, src, dst, nfib);           \
     return;
     switch (level0) {
       SG_PCASE(1, 4)
@@ -408,16 +433,14 @@ __device__ __forceinline__ void potential(const TermCtx &a, const TermDev *T, in
     }
 #undef SG_PCASE
   }
-  if (kin) potential_impl<G, R, 0, true>(a, T, src, dst, nfib);
-  else potential_impl<G, R, 0, false>(a, T, src, dst, nfib);
+  if (kin) potential_impl<G, R, P, 0, true>(a, T, src, dst, nfib);
+  else potential_impl<G, R, P, 0, false>(a, T, src, dst, nfib);
 }
 
-// The whole of Alg. 1 for one term, by the threads of G, with two LDS
-// buffers of `buf` complex values each.
-template <typename G, typename R>
-__device__ __forceinline__ void run_term(const TermCtx &a, const TermDev *T,
-                                         typename Cx<R>::T *lds, int buf) {
-  typedef typename Cx<R>::T C;
+// The whole of Alg. 1 for one term, by the threads of G, with two buffers of
+// `buf` complex values each starting at `base`.
+template <typename G, typename R, typename P>
+__device__ __forceinline__ void run_term(const TermCtx &a, cptr<TermDev> T, P base, int buf) {
   const R *tab = (const R *)a.tab;
   const int na = T->na;
   const int nbasis = T->nbasis;
@@ -426,35 +449,35 @@ __device__ __forceinline__ void run_term(const TermCtx &a, const TermDev *T,
   const double cf = T->coeff;
   if (na == 0) {  // every mode at a one-function level: a scalar term
     if (G::tid() == 0) {
-      const double c0 = a.split ? T->c0_split : T->c0_full;
-      const double2 x = a.psi[a.mb[off]];
-      a.tm[off] = make_double2(cf * c0 * x.x, cf * c0 * x.y);
+      const double c0 = T->c0[a.split ? kPotSplit : kPotFull];
+      const Z64 x = ldc<Z64>(a.psi + a.mb[off]);
+      stc(a.tm + off, Z64{cf * c0 * x.x, cf * c0 * x.y});
     }
     return;
   }
-  C *src = lds, *dst = lds + buf;
+  P src = base, dst = base + buf;
 
   // steps 1-2: gather + basis -> grid along mode 0, then the other modes
   {
     const int nb0 = T->nb[0], nq0 = T->nq[0];
-    gather_b2g<G, R>(a, T->lev[0], nb0, nq0, off, nbasis / nb0, tab + T->bt[0], src);
+    gather_b2g<G, R, P>(a, T->lev[0], nb0, nq0, off, nbasis / nb0, tab + T->bt[0], src);
     G::sync();
     int stride = nq0;
     int nouter = nbasis / nb0;
     for (int p = 1; p < na; ++p) {
       const int nb = T->nb[p], nq = T->nq[p];
       nouter /= nb;
-      contract_level<G, R, false>(0, T->lev[p], a.std_maps, nb, nq, src, dst, tab + T->bt[p],
-                                  (R)1, stride, nouter);
+      contract_level<G, R, P, false>(0, T->lev[p], a.std_maps, nb, nq, src, dst, tab + T->bt[p],
+                                     (R)1, stride, nouter);
       G::sync();
-      C *tmp = src; src = dst; dst = tmp;
+      P tmp = src; src = dst; dst = tmp;
       stride *= nq;
     }
   }
   // step 3: potential (+ mode-0 kinetic), then the other modes' kinetic
   {
     const int nq0 = T->nq[0];
-    potential<G, R>(a, T, T->lev[0], src, dst, ngrid / nq0);
+    potential<G, R, P>(a, T, T->lev[0], src, dst, ngrid / nq0);
     G::sync();
     if (!a.split) {
       int stride = nq0;
@@ -462,13 +485,13 @@ __device__ __forceinline__ void run_term(const TermCtx &a, const TermDev *T,
       for (int p = 1; p < na; ++p) {
         const int nb = T->nb[p], nq = T->nq[p];
         nouter /= nq;
-        contract_level<G, R, true>(1, T->lev[p], a.std_maps, nb, nq, src, dst, tab + T->kg[p],
-                                   (R)T->kin[p], stride, nouter);
+        contract_level<G, R, P, true>(1, T->lev[p], a.std_maps, nb, nq, src, dst, tab + T->kg[p],
+                                      (R)T->kin[p], stride, nouter);
         G::sync();
         stride *= nq;
       }
     }
-    C *tmp = src; src = dst; dst = tmp;
+    P tmp = src; src = dst; dst = tmp;
   }
   // step 4: grid -> basis; the last mode writes D_l * result to HBM
   {
@@ -477,23 +500,23 @@ __device__ __forceinline__ void run_term(const TermCtx &a, const TermDev *T,
     for (int p = 0; p < na - 1; ++p) {
       const int nb = T->nb[p], nq = T->nq[p];
       nouter /= nq;
-      contract_level<G, R, false>(2, T->lev[p], a.std_maps, nb, nq, src, dst, tab + T->wt[p],
-                                  (R)1, stride, nouter);
+      contract_level<G, R, P, false>(2, T->lev[p], a.std_maps, nb, nq, src, dst, tab + T->wt[p],
+                                     (R)1, stride, nouter);
       G::sync();
-      C *tmp = src; src = dst; dst = tmp;
+      P tmp = src; src = dst; dst = tmp;
       stride *= nb;
     }
     const int p = na - 1;
-    g2b_store<G, R>(a.std_maps, T->lev[p], T->nb[p], T->nq[p], src, a.tm + off, tab + T->wt[p],
-                    cf, stride);
+    g2b_store<G, R, P>(a.std_maps, T->lev[p], T->nb[p], T->nq[p], src, a.tm + off,
+                       tab + T->wt[p], cf, stride);
   }
 }
 
 // Is instance I part of this launch, and which vector does H act on?
-__device__ __forceinline__ bool live(const SweepArgs &a, const InstDev *I) {
+__device__ __forceinline__ bool live(const SweepArgs &a, cptr<InstDev> I) {
   return I->active && (a.mode == 0 || a.k <= I->K - 1);
 }
-__device__ __forceinline__ const double2 *input_of(const SweepArgs &a, const InstDev *I) {
+__device__ __forceinline__ const double2 *input_of(const SweepArgs &a, cptr<InstDev> I) {
   double2 *x0 = a.x0o ? a.x0o : I->x0;
   double2 *x1 = a.x1o ? a.x1o : I->x1;
   if (a.mode == 0) return x0;
@@ -501,17 +524,18 @@ __device__ __forceinline__ const double2 *input_of(const SweepArgs &a, const Ins
 }
 
 template <typename R>
-__device__ __forceinline__ TermCtx make_ctx(const SweepArgs &a, const InstDev *I, int t) {
+__device__ __forceinline__ TermCtx make_ctx(const SweepArgs &a, cptr<InstDev> I, int t) {
   TermCtx c;
-  c.mb = I->mb;
-  c.psi = input_of(a, I);
-  c.tm = I->tm;
-  c.pc = I->pairs + (size_t)t * (2 * kMaxPairs);
+  c.mb = (glb_p<const int32_t>)I->mb;
+  c.psi = (glb_p<const Z64>)input_of(a, I);
+  c.tm = (glb_p<Z64>)I->tm;
   c.std_maps = I->std_maps;
   c.split = a.split;
-  c.round32 = (a.split && I->round32) ? 1 : 0;
+  const bool r32 = a.split && I->round32;
+  c.pot = a.split ? (r32 ? kPotSplitRounded : kPotSplit) : kPotFull;
+  c.pc = (cptr<double>)(I->pairs + (size_t)t * kPairStride + (r32 ? 2 * kMaxPairs : 0));
   if (sizeof(R) == sizeof(float)) c.tab = I->tab32;
-  else c.tab = c.round32 ? (const void *)I->tab32r : (const void *)I->tab64;
+  else c.tab = r32 ? (const void *)I->tab32r : (const void *)I->tab64;
   return c;
 }
 
@@ -519,28 +543,32 @@ template <typename R>
 __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
   extern __shared__ char lds_raw[];
   typedef typename Cx<R>::T C;
-  const PackDev *P = a.packs + blockIdx.x;
+  const cptr<PackDev> P = a.packs + blockIdx.x;
   if (P->block) {
-    const InstDev *I = a.inst + P->inst[0];
+    const cptr<InstDev> I = a.inst + P->inst[0];
     if (!live(a, I)) return;
     const int t = P->term[0];
-    const TermDev *T = I->terms + t;
+    const cptr<TermDev> T = (cptr<TermDev>)(I->terms + t);
     const TermCtx c = make_ctx<R>(a, I, t);
-    if (P->block == 1) run_term<BlockGroup, R>(c, T, (C *)lds_raw, T->ngrid);
-    else run_term<BlockGroup, R>(c, T, (C *)(a.scratch + P->scratch_off), T->ngrid);
+    if (P->block == 1)
+      run_term<BlockGroup, R, lds_p<C>>(c, T, (lds_p<C>)lds_raw, T->ngrid);
+    else
+      run_term<BlockGroup, R, glb_p<C>>(c, T, (glb_p<C>)(a.scratch + P->scratch_off), T->ngrid);
     return;
   }
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (w >= P->n) return;
-  const InstDev *I = a.inst + P->inst[w];
+  const cptr<InstDev> I = a.inst + P->inst[w];
   if (!live(a, I)) return;
   const int t = P->term[w];
+  const cptr<TermDev> T = (cptr<TermDev>)(I->terms + t);
   const TermCtx c = make_ctx<R>(a, I, t);
-  run_term<WaveGroup, R>(c, I->terms + t, (C *)(lds_raw + P->lds_off[w]), I->terms[t].ngrid);
+  run_term<WaveGroup, R, lds_p<C>>(c, T, (lds_p<C>)(lds_raw + P->lds_off[w]), T->ngrid);
 }
 
 template <typename R>
-hipError_t launch_packs(const SweepArgs &a, int npacks, int lds, hipStream_t s) {
+hipError_t launch_packs(const SweepArgs &a, int npacks, int lds, hipStream_t s,
+                        hipEvent_t ev0, hipEvent_t ev1) {
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)sweep_kernel<R>,
@@ -548,7 +576,11 @@ hipError_t launch_packs(const SweepArgs &a, int npacks, int lds, hipStream_t s) 
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(sweep_kernel<R>, dim3((unsigned)npacks), dim3(kThreads), lds, s, a);
+  if (ev0 || ev1)
+    hipExtLaunchKernelGGL(sweep_kernel<R>, dim3((unsigned)npacks), dim3(kThreads), lds, s, ev0,
+                          ev1, 0, a);
+  else
+    hipLaunchKernelGGL(sweep_kernel<R>, dim3((unsigned)npacks), dim3(kThreads), lds, s, a);
   return hipGetLastError();
 }
 
@@ -556,7 +588,7 @@ hipError_t launch_packs(const SweepArgs &a, int npacks, int lds, hipStream_t s) 
 
 hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   SweepArgs a;
-  a.inst = pl->d_inst;
+  a.inst = (cptr<InstDev>)pl->d_inst;
   a.scratch = pl->d_scratch;
   a.x0o = c.x0o;
   a.x1o = c.x1o;
@@ -567,8 +599,8 @@ hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   if (c.prec == SG_FP64) {
     const PackSet &ps = pl->sets[0];
     if (ps.count == 0) return hipSuccess;
-    a.packs = pl->d_packs + ps.first;
-    return launch_packs<double>(a, ps.count, ps.lds_bytes, s);
+    a.packs = (cptr<PackDev>)(pl->d_packs + ps.first);
+    return launch_packs<double>(a, ps.count, ps.lds_bytes, s, c.ev0, c.ev1);
   }
   // mixed: terms with large |D_l| in FP64, the rest in FP32.  The FP64 terms
   // of an instance that also has FP32 terms read the FP32-rounded tables, so
@@ -576,13 +608,15 @@ hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   // combination cancels their rounding as it does when all run in FP32.
   const PackSet &p64 = pl->sets[1], &p32 = pl->sets[2];
   if (p64.count > 0) {
-    a.packs = pl->d_packs + p64.first;
-    e = launch_packs<double>(a, p64.count, p64.lds_bytes, s);
+    a.packs = (cptr<PackDev>)(pl->d_packs + p64.first);
+    e = launch_packs<double>(a, p64.count, p64.lds_bytes, s, c.ev0,
+                             p32.count > 0 ? nullptr : c.ev1);
     if (e != hipSuccess) return e;
   }
   if (p32.count > 0) {
-    a.packs = pl->d_packs + p32.first;
-    e = launch_packs<float>(a, p32.count, p32.lds_bytes, s);
+    a.packs = (cptr<PackDev>)(pl->d_packs + p32.first);
+    e = launch_packs<float>(a, p32.count, p32.lds_bytes, s, p64.count > 0 ? nullptr : c.ev0,
+                            c.ev1);
   }
   return e;
 }

@@ -317,7 +317,7 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
 
   // ---- per-term operator coefficients -------------------------------------
   h.terms.resize(h.nterms);
-  h.pairs.assign((size_t)h.nterms * kMaxPairs * 2, 0.0);
+  h.pairs.assign((size_t)h.nterms * kPairStride, 0.0);
   h.grid_literal = h.grid_active = h.max_basis = h.max_grid = 0;
   h.flops_fp64 = h.flops_mixed = 0.0;
   std::vector<double> cost(h.nterms);
@@ -354,11 +354,16 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
       T.nb[p] = T.nq[p] = 1;
       T.rcp_nq[p] = 1.0f;
     }
-    double *pr = &h.pairs[(size_t)t * kMaxPairs * 2];
+    auto r32 = [](double v) { return (double)(float)v; };
+    double *pr = &h.pairs[(size_t)t * kPairStride];
+    double *prr = pr + 2 * kMaxPairs;
     for (size_t q = 0; q < act.size(); ++q)
       for (size_t r = q + 1; r < act.size(); ++r) {
-        pr[2 * pair_index((int)q, (int)r)] = h.c[(size_t)act[q] * D + act[r]];
-        pr[2 * pair_index((int)q, (int)r) + 1] = h.k[(size_t)act[q] * D + act[r]];
+        const int pi = pair_index((int)q, (int)r);
+        pr[2 * pi] = h.c[(size_t)act[q] * D + act[r]];
+        pr[2 * pi + 1] = h.k[(size_t)act[q] * D + act[r]];
+        prr[2 * pi] = r32(pr[2 * pi]);
+        prr[2 * pi + 1] = r32(pr[2 * pi + 1]);
       }
     T.nbasis = (int32_t)nbas;
     T.ngrid = (int32_t)ngr;
@@ -373,8 +378,9 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
         c0s += C(z, z2) * m2[lz] * m2[lz2] + K(z, z2) * m2[lz] * m1[lz2];
       }
     }
-    T.c0_split = c0s;
-    T.c0_full = c0s + c0h;
+    T.c0[kPotFull] = c0s + c0h;
+    T.c0[kPotSplit] = c0s;
+    T.c0[kPotSplitRounded] = r32(c0s);
     for (size_t p = 0; p < act.size(); ++p) {
       int m = act[p];
       double al = 0.0, be = 0.0;
@@ -384,9 +390,11 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
         if (m < z) al += K(m, z) * m1[lz];
         else be += K(z, m) * m2[lz];
       }
-      T.alpha_split[p] = al;
-      T.alpha_full[p] = al + 0.5 * h.omega[m];
-      T.beta[p] = be;
+      T.alpha[kPotFull][p] = al + 0.5 * h.omega[m];
+      T.alpha[kPotSplit][p] = al;
+      T.alpha[kPotSplitRounded][p] = r32(al);
+      T.beta[0][p] = be;
+      T.beta[1][p] = r32(be);
       T.kin[p] = -0.5 * h.omega[m];
     }
     // sizes and algorithmic flops (4 per complex x real multiply-add)
