@@ -119,6 +119,9 @@ def main():
     ap.add_argument("--latency-samples", type=int, default=1000)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--grid-kinetic", action="store_true",
+                    help="SG_FP64 in the literal form (kinetic matrices on every term grid) "
+                         "instead of the default exact diagonal split")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the "
                          "reference kernel for scaling HBM byte counters) and exit")
@@ -151,7 +154,9 @@ def main():
     torch.cuda.set_device(dev)
     log(f"[bench] build {args.workload} D={inst.D} L={inst.L}")
     P = sg.Problem.from_instance(inst)
-    info = P.info
+    if args.grid_kinetic:
+        sg.sg_set_operator_form(P.handle, True)
+    info = sg.sg_problem_info(P.handle)
     n = P.n_cs
     psi0 = torch.empty(n, dtype=torch.complex128, device=dev)
     sg.sg_init_gaussian(P.handle, inst.shift, psi0)
@@ -187,8 +192,8 @@ def main():
     sg.sg_set_timing(P.handle, False)
     sweep_avg_s = tim["sweep_ms"] / max(tim["sweep_launches"], 1) * 1e-3
     reduce_avg_s = tim["reduce_ms"] / max(tim["reduce_launches"], 1) * 1e-3
-    flops_apply = info["flops_fp64"] if prec == sg.SG_FP64 else info["flops_mixed"]
-    sweep_flops = flops_apply - 2.0 * info["n_s"] - (4.0 * n if prec == sg.SG_MIXED else 0.0)
+    info = sg.sg_problem_info(P.handle)
+    sweep_flops = info["sweep_flops_fp64"] if prec == sg.SG_FP64 else info["sweep_flops_mixed"]
     achieved_tflops = sweep_flops / sweep_avg_s / 1e12
     peak = FP64_VALU_PEAK_TFLOPS
     log(f"[bench] sweep avg {sweep_avg_s * 1e6:.2f} us, reduce avg {reduce_avg_s * 1e6:.2f} us")
@@ -227,7 +232,9 @@ def main():
         "config": {"workload": wl["desc"], "D": inst.D, "L": inst.L, "dt": wl["dt"],
                    "precision": prec_name, "n_terms": info["n_terms"], "n_cs": n,
                    "n_s": info["n_s"], "chebyshev_terms": stats["cheb_terms"],
-                   "check_every": wl["check_every"], "parallelism": "single GPU"},
+                   "check_every": wl["check_every"], "parallelism": "single GPU",
+                   "operator_form": ("split" if (prec == sg.SG_MIXED or info["fp64_split"])
+                                     else "grid_kinetic")},
         "grid_pts_per_s_literal": value * info["grid_literal"],
         "grid_pts_per_s_active": value * info["grid_active"],
         "latency_us_p50": float(np.percentile(lat, 50)),

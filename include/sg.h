@@ -103,10 +103,15 @@ typedef struct {
   int64_t grid_active;     /* sum_l prod_{l_i>0} nq(l_i): points evaluated     */
   int64_t max_term_basis;  /* largest prod_{l_i>0} nb(l_i)                     */
   int64_t max_term_grid;   /* largest prod_{l_i>0} nq(l_i)                     */
-  double flops_fp64;       /* algorithmic flops of one SG_FP64 apply           */
+  double flops_fp64;       /* algorithmic flops of one SG_FP64 apply, in the
+                              operator form it uses (sg_set_operator_form)     */
   double flops_mixed;      /* algorithmic flops of one SG_MIXED apply          */
+  double sweep_flops_fp64; /* the term-sweep kernels' share of flops_fp64     */
+  double sweep_flops_mixed;/* ... of flops_mixed                               */
   double bytes_fp64;       /* algorithmic HBM bytes of one apply (both modes)  */
   int64_t device_bytes;    /* device memory held by the handle                 */
+  int32_t fp64_split;      /* 1: SG_FP64 applies the split form                */
+  int32_t pad;
 } sg_info;
 
 /* Sizes of a problem without building it: out[0] = N_st, out[1] = N_s,
@@ -268,6 +273,19 @@ sg_status sg_serve_destroy(sg_server *s);
  * by |D_l|) run in FP64.  The default is 16.  Synchronous; also valid on a
  * host-only handle. */
 sg_status sg_set_mixed_threshold(sg_problem *p, int32_t max_fp32_coeff);
+
+/* Operator form of SG_FP64 applies.  Alg. 1 evaluates, per term, the whole
+ * operator on the term's grid: the potential times the grid values plus the
+ * kinetic second-derivative matrix of every active mode (grid_kinetic = 1).
+ * When nq(l) > nb(l) at every level, each term's rule integrates the
+ * separable part sum_i 1/2 omega_i (-d^2/dQ_i^2 + Q_i^2) exactly, so its
+ * Smolyak sum is exactly the diagonal sum_i omega_i (n_i + 1/2); the default
+ * (grid_kinetic = 0) then applies that diagonal in FP64 in the reduce and
+ * only the coupling potential on the grids (same operator, fewer
+ * contractions; results agree to rounding).  Without that condition SG_FP64
+ * always uses the grid form.  SG_MIXED always uses the split form.
+ * Synchronous; also valid on a host-only handle. */
+sg_status sg_set_operator_form(sg_problem *p, int32_t grid_kinetic);
 
 /* Precision autotuner.  Tries every threshold from "all terms in FP32" down
  * to 0 (no FP32 term: the exact FP64 split) on the device vector psi

@@ -24,7 +24,7 @@ __all__ = [
     "sg_free", "sg_problem_info", "sg_basis_indices", "sg_term_levels",
     "sg_mapping_table", "sg_init_gaussian", "sg_apply_H", "sg_spectral_bounds",
     "sg_propagate_chebyshev", "sg_set_timing", "sg_get_timing", "sg_set_mixed_threshold",
-    "sg_tune_mixed", "sg_batch_create", "sg_batch_propagate", "sg_batch_free",
+    "sg_tune_mixed", "sg_set_operator_form", "sg_batch_create", "sg_batch_propagate", "sg_batch_free",
     "ServeConfig", "sg_serve_create", "sg_serve_submit", "sg_serve_poll", "sg_serve_cancel",
     "sg_serve_counters", "sg_serve_destroy", "Problem",
 ]
@@ -62,8 +62,10 @@ class Info(ctypes.Structure):
                 ("n_s", ctypes.c_int64), ("grid_literal", ctypes.c_int64),
                 ("grid_active", ctypes.c_int64), ("max_term_basis", ctypes.c_int64),
                 ("max_term_grid", ctypes.c_int64), ("flops_fp64", ctypes.c_double),
-                ("flops_mixed", ctypes.c_double), ("bytes_fp64", ctypes.c_double),
-                ("device_bytes", ctypes.c_int64)]
+                ("flops_mixed", ctypes.c_double), ("sweep_flops_fp64", ctypes.c_double),
+                ("sweep_flops_mixed", ctypes.c_double), ("bytes_fp64", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64), ("fp64_split", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -107,6 +109,7 @@ class Result(ctypes.Structure):
 
 _SIGNATURES = {
     "sg_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "sg_set_operator_form": (ctypes.c_int, [_P, ctypes.c_int32]),
     "sg_set_mixed_threshold": (ctypes.c_int, [_P, ctypes.c_int32]),
     "sg_tune_mixed": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int32),
@@ -329,6 +332,10 @@ def sg_tune_mixed(h, psi, tol: float = 1e-6, reps: int = 3, stream=None):
     _check(lib().sg_tune_mixed(h, _vec_ptr(psi, n_cs, "psi"), float(tol), int(reps),
                                ctypes.byref(ch), ctypes.byref(er), _stream_ptr(stream)))
     return ch.value, er.value
+
+
+def sg_set_operator_form(h, grid_kinetic: bool) -> None:
+    _check(lib().sg_set_operator_form(h, int(grid_kinetic)))
 
 
 def sg_set_timing(h, enable: bool) -> None:

@@ -271,10 +271,18 @@ sg_status sg_problem_info(const sg_problem *p, sg_info *out) {
   out->grid_active = h.grid_active;
   out->max_term_basis = h.max_basis;
   out->max_term_grid = h.max_grid;
-  out->flops_fp64 = h.flops_fp64;
+  const bool split = p->host_only ? (h.split_exact && !p->grid_kinetic)
+                                   : (p->plan && p->plan->fp64_split);
+  const double red_grid = 2.0 * (double)h.MB.size();
+  const double red_split = 2.0 * (double)h.MB.size() + 4.0 * (double)h.ncs;
+  out->flops_fp64 = split ? h.flops_mixed : h.flops_fp64;
   out->flops_mixed = h.flops_mixed;
+  out->sweep_flops_fp64 = split ? h.flops_mixed - red_split : h.flops_fp64 - red_grid;
+  out->sweep_flops_mixed = h.flops_mixed - red_split;
   out->bytes_fp64 = h.bytes_apply;
   out->device_bytes = p->device_bytes;
+  out->fp64_split = split ? 1 : 0;
+  out->pad = 0;
   return SG_OK;
 }
 
@@ -357,6 +365,17 @@ sg_status sg_set_mixed_threshold(sg_problem *p, int32_t max_fp32_coeff) {
   if (!p) return fail(SG_EINVAL, "NULL problem");
   if (max_fp32_coeff < 0) return fail(SG_EINVAL, "threshold must be >= 0");
   p->h.mixed_max_fp32_coeff = max_fp32_coeff;
+  if (p->host_only) return SG_OK;
+  std::string err;
+  sg_status st = plan_build(p->plan, {p}, &err);
+  if (st != SG_OK) return fail(st, err);
+  return plan_upload(p->plan, nullptr);
+}
+
+sg_status sg_set_operator_form(sg_problem *p, int32_t grid_kinetic) {
+  if (!p) return fail(SG_EINVAL, "NULL problem");
+  if (grid_kinetic != 0 && grid_kinetic != 1) return fail(SG_EINVAL, "grid_kinetic must be 0 or 1");
+  p->grid_kinetic = grid_kinetic;
   if (p->host_only) return SG_OK;
   std::string err;
   sg_status st = plan_build(p->plan, {p}, &err);

@@ -101,30 +101,41 @@ struct InstDev {
   int32_t pad;
 };
 
-// Term-sweep packing.  A workgroup (512 threads) runs one pack: one term with
-// more than kWaveMaxGrid grid points on all its wavefronts, or up to
-// kPackTerms smaller terms, one per wavefront.  A term whose two grid buffers
-// do not fit in LDS runs on a whole workgroup with its buffers in a global
-// scratch region (L2-resident).
-constexpr int kPackTerms = 8;
-constexpr int kWaveMaxGrid = 512;
+// Term-sweep packing.  A workgroup (kSweepThreads threads, four wavefronts)
+// runs one pack: up to kPackTerms terms, one per wavefront, or one term on
+// all four wavefronts, its buffers in LDS or (too large for LDS) in a global
+// scratch region.  A term runs "in place" (one grid buffer: each contraction
+// holds all its input fibers in registers before writing) or "ping-pong"
+// (two buffers).  The host picks, per term, the smallest group whose
+// registers hold every in-place contraction (inplace_fpt below), and packs
+// wave terms under an LDS cap so that two workgroups share a compute unit.
+constexpr int kSweepThreads = 256;
+constexpr int kPackTerms = 4;
 constexpr int kLdsPerCU = 160 * 1024;
 constexpr int kComputeUnits = 256;   // MI355X; used to size the packing only
+constexpr int kPingPongWaveMaxGrid = 512;
+// Fibers of NI values one thread holds in an in-place contraction.
+__host__ __device__ constexpr int inplace_fpt(int ni) { return ni <= 18 ? 18 / ni : 1; }
+enum PackKind : int32_t { kPackWaves = 0, kPackBlockLds = 1, kPackBlockScratch = 2 };
 struct PackDev {
   int32_t n;                    // terms in the pack
-  int32_t block;                // 1: term[0] on the whole workgroup, 2: same in scratch
+  int32_t block;                // PackKind
   int32_t inst[kPackTerms];
   int32_t term[kPackTerms];
   int32_t lds_off[kPackTerms];  // byte offset of each wavefront's LDS slice
-  int64_t scratch_off;          // block == 2: byte offset in the plan's scratch
+  int32_t inplace[kPackTerms];  // 1: in place (one buffer), 0: ping-pong
+  int64_t scratch_off;          // kPackBlockScratch: byte offset in the plan's scratch
 };
 struct PackSet {
   int32_t first = 0;            // index of the first pack
   int32_t count = 0;
   int32_t lds_bytes = 0;        // dynamic LDS of the launch
 };
-// Pack sets: FP64 path (all terms), mixed path FP64 terms, mixed path FP32 terms.
-constexpr int kPackSets = 3;
+// Pack sets: FP64 with the kinetic matrices on the grid (all terms); FP64
+// with the separable part split off (all terms); the mixed path's FP64 terms;
+// its FP32 terms.
+constexpr int kPackSets = 4;
+enum PackSetId { kSetGrid64 = 0, kSetSplit64 = 1, kSetMixed64 = 2, kSetMixed32 = 3 };
 // Rows of the inverse mapping longer than this are reduced by a whole
 // wavefront, shorter ones by a group of 8 lanes.
 constexpr int kLongRow = 64;
@@ -165,6 +176,9 @@ struct Compiled {
                                      // FP64 terms: same operator as the FP32 terms)
   std::vector<double> cost;          // estimated work per term
   int32_t mixed_max_fp32_coeff = 16; // mixed path: |D_l| at most this -> FP32
+  // nq(l) > nb(l) at every level used: every term's rule then integrates the
+  // separable harmonic part exactly, so it can be split off as the diagonal.
+  bool split_exact = false;
   std::vector<int32_t> rows;         // compact rows, long rows first
   int64_t n_long_rows = 0;
   int64_t n_items = 0;               // reduce work items
@@ -215,6 +229,7 @@ struct sg_problem {
   double2 *d_work = nullptr;       // 4 * N_cs: Chebyshev phi, ACC, spares
   double *d_partials = nullptr;    // [2 * n_items] reduction partials
   double *d_cheb_a = nullptr;      // [kMaxChebTerms] series coefficients
+  int grid_kinetic = 0;            // 1: SG_FP64 applies the kinetic matrices on the grid
   double *d_result = nullptr;      // 8 doubles
   double *h_result = nullptr;      // pinned host mirror of d_result
   int64_t device_bytes = 0;
@@ -250,6 +265,7 @@ struct Plan {
   int64_t scratch_bytes = 0;
   int64_t packs_capacity = 0, items_capacity = 0, inst_capacity = 0, scratch_capacity = 0;
   bool any32 = false;              // some term of some instance runs in FP32
+  bool fp64_split = false;         // SG_FP64 launches use the split form
 };
 
 // Plans (sg_plan.cpp)
@@ -276,6 +292,11 @@ struct LaunchCtl {
   hipEvent_t ev0 = nullptr;
   hipEvent_t ev1 = nullptr;
 };
+// Does a launch of this precision apply the split operator (separable
+// harmonic part as the exact FP64 diagonal in the reduce)?
+inline bool split_form(const Plan *pl, sg_precision prec) {
+  return prec == SG_MIXED || pl->fp64_split;
+}
 hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s);
 hipError_t launch_reduce(const Plan *pl, const LaunchCtl &c, hipStream_t s);
 hipError_t launch_finalize(const Plan *pl, hipStream_t s);  // per-instance partials

@@ -1,12 +1,17 @@
 // Launch plans: the instances one term-sweep / reduce launch covers.
 //
-// Packing (the term -> workgroup schedule).  Terms above kWaveMaxGrid grid
-// points get a workgroup each (in global scratch when their two grid buffers
-// exceed the LDS of a compute unit); the others are dealt, most expensive
-// first, to the least loaded of B packs of at most kPackTerms terms (one
-// wavefront each), with B large enough to give every compute unit work.
-// Terms of different instances mix freely: every term is computed by the
-// same code whatever its pack, so results do not depend on the mix.
+// Packing (the term -> workgroup schedule).  Each term gets the smallest
+// group that runs it well:
+//   * one wavefront, when every contraction of the term has at most
+//     inplace_fpt(NI) fibers per lane (in-place form) or the term is small
+//     (ping-pong form);
+//   * the four wavefronts of a workgroup otherwise, with its buffer in LDS
+//     when it fits under the per-workgroup cap, else in global scratch.
+// Wave terms are dealt, most expensive first, to the least loaded of enough
+// packs (at most kPackTerms terms and the LDS cap each) to give every compute
+// unit work.  Terms of different instances mix freely: every term is
+// computed by the same code whatever its pack, so results do not depend on
+// the mix.
 //
 // Reduce items: one wavefront per long row, one per eight short rows, in each
 // instance's row order; an item's partial sums go to its own slot so that the
@@ -25,28 +30,67 @@ struct Cand {
   int32_t inst;
   int32_t term;
   double cost;
-  int slice;   // bytes of the two grid buffers
-  int ngrid;
+  int64_t slice;   // bytes of the term's buffer(s)
+  int inplace;     // 1: one buffer, contractions in place
+  int wave;        // 1: one wavefront can run it
+  int64_t ngrid;
 };
 
-void pack_set(const std::vector<Cand> &cands, std::vector<PackDev> *out, PackSet *set,
-              int64_t *scratch_bytes) {
+// Does every in-place contraction of term T fit the registers of a group of
+// n lanes?  B->G along modes 1.. and G->B along modes ..na-2 run in place
+// (the first and last contractions read or write HBM).
+bool inplace_fits(const TermDev &T, int n) {
+  const int na = T.na;
+  for (int p = 1; p < na; ++p) {           // basis -> grid along mode p
+    int64_t s = 1;
+    for (int q = 0; q < na; ++q) s *= q < p ? T.nq[q] : T.nb[q];
+    const int ni = T.nb[p];
+    if (s / ni > (int64_t)inplace_fpt(ni) * n) return false;
+  }
+  for (int p = 0; p + 1 < na; ++p) {       // grid -> basis along mode p
+    int64_t s = 1;
+    for (int q = 0; q < na; ++q) s *= q < p ? T.nb[q] : T.nq[q];
+    const int ni = T.nq[p];
+    if (s / ni > (int64_t)inplace_fpt(ni) * n) return false;
+  }
+  return true;
+}
+
+// One candidate per term of a pack set.  split: the set applies the split
+// operator (no kinetic contractions, so the in-place form applies to the
+// standard size maps); elem: bytes of one complex value.
+Cand make_cand(int32_t inst, int32_t term, const Compiled &h, bool split, int elem) {
+  const TermDev &T = h.terms[term];
+  Cand c{inst, term, h.cost[term], 0, 0, 0, T.ngrid};
+  const bool std_maps = h.nbA == 1 && h.nbB == 2 && h.nqA == 2 && h.nqB == 2;
+  const int64_t one = (int64_t)T.ngrid * elem;
+  if (split && std_maps && T.na > 0 && inplace_fits(T, kSweepThreads)) {
+    c.inplace = 1;
+    c.slice = one;
+    c.wave = inplace_fits(T, 64) ? 1 : 0;
+  } else {
+    c.inplace = 0;
+    c.slice = 2 * one;
+    c.wave = T.ngrid <= kPingPongWaveMaxGrid ? 1 : 0;
+  }
+  return c;
+}
+
+void pack_set(const std::vector<Cand> &cands, int elem, std::vector<PackDev> *out,
+              PackSet *set, int64_t *scratch_bytes) {
   set->first = (int32_t)out->size();
   set->count = 0;
   set->lds_bytes = 0;
   if (cands.empty()) return;
+  // two workgroups per compute unit (FP64), four (FP32)
+  const int cap = elem >= 16 ? kLdsPerCU / 2 : kLdsPerCU / 4;
+  const int per_cu = kLdsPerCU / cap;
   std::vector<Cand> big, small;
-  for (const Cand &c : cands) (c.ngrid > kWaveMaxGrid ? big : small).push_back(c);
+  for (const Cand &c : cands) (c.wave && c.slice <= cap ? small : big).push_back(c);
   auto by_cost = [](const Cand &a, const Cand &b) { return a.cost > b.cost; };
   std::stable_sort(big.begin(), big.end(), by_cost);
   std::stable_sort(small.begin(), small.end(), by_cost);
   int lds = 0;
-  for (const Cand &c : big)
-    if (c.slice <= kLdsPerCU) lds = std::max(lds, c.slice);
-  int small_slice = 0;
-  for (const Cand &c : small) small_slice = std::max(small_slice, c.slice);
-  const int small_lds = kPackTerms * small_slice;
-  const int per_cu = std::max(1, kLdsPerCU / std::max(1, std::max(lds, small_lds)));
   const int64_t nsmall = (int64_t)small.size();
   int64_t nbins = (nsmall + kPackTerms - 1) / kPackTerms;
   const int64_t want = (int64_t)kComputeUnits * per_cu - (int64_t)big.size();
@@ -59,22 +103,50 @@ void pack_set(const std::vector<Cand> &cands, std::vector<PackDev> *out, PackSet
     return a.load > b.load || (a.load == b.load && a.id > b.id);
   };
   std::vector<Bin> heap;
-  std::vector<PackDev> bins((size_t)nbins);
-  std::vector<int> bin_bytes((size_t)nbins, 0);
-  std::vector<double> bin_load((size_t)nbins, 0.0);
-  for (int64_t i = 0; i < nbins; ++i) {
-    std::memset(&bins[i], 0, sizeof(PackDev));
-    heap.push_back({0.0, i});
-  }
-  std::make_heap(heap.begin(), heap.end(), worse);
+  std::vector<PackDev> bins;
+  std::vector<int64_t> bin_bytes;
+  std::vector<double> bin_load;
+  auto new_bin = [&]() {
+    PackDev pk;
+    std::memset(&pk, 0, sizeof(pk));
+    pk.block = kPackWaves;
+    bins.push_back(pk);
+    bin_bytes.push_back(0);
+    bin_load.push_back(0.0);
+    heap.push_back({0.0, (int64_t)bins.size() - 1});
+    std::push_heap(heap.begin(), heap.end(), worse);
+  };
+  for (int64_t i = 0; i < nbins; ++i) new_bin();
   for (const Cand &c : small) {
-    std::pop_heap(heap.begin(), heap.end(), worse);
-    Bin b = heap.back();
-    heap.pop_back();
+    // least loaded bin with room (bins without room leave the heap for good
+    // once full; bins short of LDS are set aside for this term only)
+    std::vector<Bin> aside;
+    Bin b{0.0, -1};
+    while (!heap.empty()) {
+      std::pop_heap(heap.begin(), heap.end(), worse);
+      Bin t = heap.back();
+      heap.pop_back();
+      if (bin_bytes[t.id] + c.slice <= cap) {
+        b = t;
+        break;
+      }
+      aside.push_back(t);
+    }
+    for (const Bin &t : aside) {
+      heap.push_back(t);
+      std::push_heap(heap.begin(), heap.end(), worse);
+    }
+    if (b.id < 0) {
+      new_bin();
+      std::pop_heap(heap.begin(), heap.end(), worse);
+      b = heap.back();
+      heap.pop_back();
+    }
     PackDev &pk = bins[b.id];
     pk.inst[pk.n] = c.inst;
     pk.term[pk.n] = c.term;
-    pk.lds_off[pk.n] = bin_bytes[b.id];
+    pk.lds_off[pk.n] = (int32_t)bin_bytes[b.id];
+    pk.inplace[pk.n] = c.inplace;
     bin_bytes[b.id] += c.slice;
     pk.n += 1;
     b.load += c.cost;
@@ -90,23 +162,27 @@ void pack_set(const std::vector<Cand> &cands, std::vector<PackDev> *out, PackSet
     pk.n = 1;
     pk.inst[0] = c.inst;
     pk.term[0] = c.term;
-    if (c.slice <= kLdsPerCU) {
-      pk.block = 1;
+    pk.inplace[0] = c.inplace;
+    if (c.slice <= cap) {
+      pk.block = kPackBlockLds;
+      lds = std::max<int>(lds, (int)c.slice);
     } else {
-      pk.block = 2;
+      // global scratch holds the two ping-pong buffers
+      pk.block = kPackBlockScratch;
+      pk.inplace[0] = 0;
       pk.scratch_off = *scratch_bytes;
-      *scratch_bytes += ((int64_t)c.slice + 255) & ~(int64_t)255;
+      *scratch_bytes += (2 * c.ngrid * elem + 255) & ~(int64_t)255;
     }
     out->push_back(pk);
   }
-  std::vector<int64_t> order((size_t)nbins);
-  for (int64_t i = 0; i < nbins; ++i) order[i] = i;
+  std::vector<int64_t> order(bins.size());
+  for (size_t i = 0; i < bins.size(); ++i) order[i] = (int64_t)i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int64_t a, int64_t b) { return bin_load[a] > bin_load[b]; });
   for (int64_t i : order) {
     if (bins[i].n == 0) continue;
     out->push_back(bins[i]);
-    lds = std::max(lds, bin_bytes[i]);
+    lds = std::max<int>(lds, (int)bin_bytes[i]);
   }
   set->count = (int32_t)(out->size() - set->first);
   set->lds_bytes = lds;
@@ -168,22 +244,23 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
   pl->items.clear();
   pl->scratch_bytes = 0;
   pl->any32 = false;
-  std::vector<Cand> c64, m64, m32;
+  pl->fp64_split = false;
+  std::vector<Cand> cg64, cs64, m64, m32;
+  bool split_all = true;
   for (size_t i = 0; i < probs.size(); ++i) {
     const sg_problem *p = probs[i];
     const Compiled &h = p->h;
     inst_from_problem(p, &pl->inst[i]);
+    split_all = split_all && h.split_exact && !p->grid_kinetic;
     bool inst32 = false;
     for (int64_t t = 0; t < h.nterms; ++t) {
-      const int ng = h.terms[t].ngrid;
-      Cand c{(int32_t)i, (int32_t)t, h.cost[t], 2 * ng * 16, ng};
-      c64.push_back(c);
+      cg64.push_back(make_cand((int32_t)i, (int32_t)t, h, false, 16));
+      cs64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16));
       if (std::abs(h.coeff[t]) <= h.mixed_max_fp32_coeff) {
-        c.slice = 2 * ng * 8;
-        m32.push_back(c);
+        m32.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 8));
         inst32 = true;
       } else {
-        m64.push_back(c);
+        m64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16));
       }
     }
     pl->inst[i].round32 = inst32 ? 1 : 0;
@@ -195,9 +272,13 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
     for (int64_t q = 0; q < nshort; q += kShortLanes)
       pl->items.push_back({(int32_t)i, (int32_t)(h.n_long_rows + q), local++, 0});
   }
-  pack_set(c64, &pl->packs, &pl->sets[0], &pl->scratch_bytes);
-  pack_set(m64, &pl->packs, &pl->sets[1], &pl->scratch_bytes);
-  pack_set(m32, &pl->packs, &pl->sets[2], &pl->scratch_bytes);
+  pl->fp64_split = split_all;
+  // the set SG_FP64 launches do not use stays empty
+  if (split_all) cg64.clear(); else cs64.clear();
+  pack_set(cg64, 16, &pl->packs, &pl->sets[kSetGrid64], &pl->scratch_bytes);
+  pack_set(cs64, 16, &pl->packs, &pl->sets[kSetSplit64], &pl->scratch_bytes);
+  pack_set(m64, 16, &pl->packs, &pl->sets[kSetMixed64], &pl->scratch_bytes);
+  pack_set(m32, 8, &pl->packs, &pl->sets[kSetMixed32], &pl->scratch_bytes);
   (void)err;
   return SG_OK;
 }

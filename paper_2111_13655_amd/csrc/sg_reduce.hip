@@ -244,7 +244,7 @@ hipError_t launch_reduce(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   a.mode = c.mode == Mode::Cheb ? 1 : 0;
   a.k = c.k;
   a.want_partials = c.want_partials;
-  a.split = c.prec == SG_MIXED ? 1 : 0;
+  a.split = split_form(pl, c.prec) ? 1 : 0;
   const int64_t blocks = (a.nitems + (kRedThreads / 64) - 1) / (kRedThreads / 64);
   if (blocks == 0) return hipSuccess;
   if (c.ev0 || c.ev1)

@@ -31,7 +31,7 @@ namespace sg {
 
 namespace {
 
-constexpr int kThreads = 512;
+constexpr int kThreads = kSweepThreads;
 
 // Address-space-qualified pointers.  Grid buffers live in LDS (or, for terms
 // too large for LDS, in global scratch); HBM data are global; per-term
@@ -64,7 +64,8 @@ struct SweepArgs {
   double2 *x0o, *x1o;    // single-instance buffer overrides (nullable)
   int mode;              // 0 apply, 1 Chebyshev
   int k;                 // Chebyshev term being produced
-  int split;
+  int split;             // split operator (no kinetic or harmonic part on the grids)
+  int mixed;             // SG_MIXED launch (instances with FP32 terms use rounded tables)
 };
 
 // Element access through address-space-qualified pointers (member-wise: the
@@ -180,6 +181,154 @@ __device__ __forceinline__ void contract(P in, P out, const R *M, R scale, int n
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fixed-size contractions (standard size maps), processed in rounds: in one
+// round a thread takes FPT fibers (f = f0 + tid + j*N), issues all their
+// loads together, then forms each output row for all FPT fibers from one
+// row of the one-mode matrix.  Outputs are the same FMA chains, in the same
+// order, as one fiber at a time.
+// ---------------------------------------------------------------------------
+template <int NI>
+struct Fpt {
+  static constexpr int value = NI <= 4 ? 4 : NI == 5 ? 3 : NI <= 8 ? 2 : 1;
+};
+
+template <typename G, typename R, typename P, int NI, int NO, bool ACC>
+__device__ __forceinline__ void contract_fixed(P in, P out, const R *M, R scale, int stride,
+                                               int nouter) {
+  typedef typename Cx<R>::T C;
+  constexpr int FPT = Fpt<NI>::value;
+  const int F = stride * nouter;
+  const float rcp = 1.0f / (float)stride;
+  const int sNI = stride * NI, sNO = stride * NO;
+  for (int f0 = 0; f0 < F; f0 += FPT * G::N) {
+    int ib[FPT], ob[FPT];
+    bool ok[FPT];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      int f = f0 + G::tid() + j * G::N;
+      ok[j] = f < F;
+      f = ok[j] ? f : 0;
+      const int hi = fdiv(f, rcp);
+      const int lo = f - hi * stride;
+      ib[j] = lo + hi * sNI;
+      ob[j] = lo + hi * sNO;
+    }
+    C x[FPT][NI];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j)
+#pragma unroll
+      for (int k = 0; k < NI; ++k) x[j][k] = ldc<C>(in + ib[j] + k * stride);
+    const cptr<R> Mw = in_loop_uniform(M);
+#pragma unroll 1
+    for (int u = 0; u < NO; ++u) {
+#pragma unroll
+      for (int j = 0; j < FPT; ++j) {
+        R re = 0, im = 0;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+          const R m = Mw[u * NI + k];
+          re = fma(m, x[j][k].x, re);
+          im = fma(m, x[j][k].y, im);
+        }
+        if (ok[j]) {
+          P d = out + ob[j] + u * stride;
+          if (ACC) {
+            C o = ldc<C>(d);
+            o.x = fma(scale, re, o.x);
+            o.y = fma(scale, im, o.y);
+            stc(d, o);
+          } else {
+            stc(d, Cx<R>::make(re, im));
+          }
+        }
+      }
+    }
+  }
+}
+
+template <typename G, typename R, typename P, int NI, int NO>
+__device__ __forceinline__ void gather_fixed(const TermCtx &a, int off, int nfib, const R *M,
+                                             P out) {
+  typedef typename Cx<R>::T C;
+  constexpr int FPT = Fpt<NI>::value;
+  for (int f0 = 0; f0 < nfib; f0 += FPT * G::N) {
+    int idx[FPT][NI];
+    bool ok[FPT];
+    int fb[FPT];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      const int f = f0 + G::tid() + j * G::N;
+      ok[j] = f < nfib;
+      fb[j] = ok[j] ? f : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < FPT; ++j)
+#pragma unroll
+      for (int k = 0; k < NI; ++k) idx[j][k] = a.mb[off + fb[j] * NI + k];
+    C x[FPT][NI];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j)
+#pragma unroll
+      for (int k = 0; k < NI; ++k) {
+        const Z64 v = ldc<Z64>(a.psi + idx[j][k]);
+        x[j][k] = Cx<R>::make((R)v.x, (R)v.y);
+      }
+    const cptr<R> Mw = in_loop_uniform(M);
+#pragma unroll 1
+    for (int u = 0; u < NO; ++u) {
+#pragma unroll
+      for (int j = 0; j < FPT; ++j) {
+        R re = 0, im = 0;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+          const R m = Mw[u * NI + k];
+          re = fma(m, x[j][k].x, re);
+          im = fma(m, x[j][k].y, im);
+        }
+        if (ok[j]) stc(out + fb[j] * NO + u, Cx<R>::make(re, im));
+      }
+    }
+  }
+}
+
+template <typename G, typename R, typename P, int NI, int NO>
+__device__ __forceinline__ void g2b_fixed(P in, glb_p<Z64> tm, const R *M, double cf,
+                                          int stride) {
+  typedef typename Cx<R>::T C;
+  constexpr int FPT = Fpt<NI>::value;
+  for (int f0 = 0; f0 < stride; f0 += FPT * G::N) {
+    bool ok[FPT];
+    int lo[FPT];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      const int f = f0 + G::tid() + j * G::N;
+      ok[j] = f < stride;
+      lo[j] = ok[j] ? f : 0;
+    }
+    C x[FPT][NI];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j)
+#pragma unroll
+      for (int k = 0; k < NI; ++k) x[j][k] = ldc<C>(in + lo[j] + k * stride);
+    const cptr<R> Mw = in_loop_uniform(M);
+#pragma unroll 1
+    for (int u = 0; u < NO; ++u) {
+#pragma unroll
+      for (int j = 0; j < FPT; ++j) {
+        R re = 0, im = 0;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+          const R m = Mw[u * NI + k];
+          re = fma(m, x[j][k].x, re);
+          im = fma(m, x[j][k].y, im);
+        }
+        if (ok[j]) stc(tm + lo[j] + u * stride, Z64{cf * (double)re, cf * (double)im});
+      }
+    }
+  }
+}
+
 // kind 0: basis -> grid (NI = nb, NO = nq); 1: kinetic on the grid
 // (NI = NO = nq); 2: grid -> basis (NI = nq, NO = nb)
 template <typename G, typename R, typename P, bool ACC>
@@ -189,9 +338,9 @@ __device__ __forceinline__ void contract_level(int kind, int level, int std_maps
   if (std_maps) {
 #define SG_CASE(L_, NB_, NQ_)                                                                       \
   case L_:                                                                                          \
-    if (kind == 0) contract<G, R, P, NB_, NQ_, ACC>(in, out, M, scale, nb, nq, stride, nouter);    \
-    else if (kind == 1) contract<G, R, P, NQ_, NQ_, ACC>(in, out, M, scale, nq, nq, stride, nouter); \
-    else contract<G, R, P, NQ_, NB_, ACC>(in, out, M, scale, nq, nb, stride, nouter);              \
+    if (kind == 0) contract_fixed<G, R, P, NB_, NQ_, ACC>(in, out, M, scale, stride, nouter);      \
+    else if (kind == 1) contract_fixed<G, R, P, NQ_, NQ_, ACC>(in, out, M, scale, stride, nouter); \
+    else contract_fixed<G, R, P, NQ_, NB_, ACC>(in, out, M, scale, stride, nouter);                \
     return;
     switch (level) {
       SG_CASE(1, 3, 4)
@@ -256,13 +405,13 @@ __device__ __forceinline__ void gather_b2g(const TermCtx &a, int level, int nb, 
                                            int nfib, const R *M, P out) {
   if (a.std_maps) {
     switch (level) {
-      case 1: gather_b2g_impl<G, R, P, 3, 4>(a, off, nfib, nb, nq, M, out); return;
-      case 2: gather_b2g_impl<G, R, P, 5, 6>(a, off, nfib, nb, nq, M, out); return;
-      case 3: gather_b2g_impl<G, R, P, 7, 8>(a, off, nfib, nb, nq, M, out); return;
-      case 4: gather_b2g_impl<G, R, P, 9, 10>(a, off, nfib, nb, nq, M, out); return;
-      case 5: gather_b2g_impl<G, R, P, 11, 12>(a, off, nfib, nb, nq, M, out); return;
-      case 6: gather_b2g_impl<G, R, P, 13, 14>(a, off, nfib, nb, nq, M, out); return;
-      case 7: gather_b2g_impl<G, R, P, 15, 16>(a, off, nfib, nb, nq, M, out); return;
+      case 1: gather_fixed<G, R, P, 3, 4>(a, off, nfib, M, out); return;
+      case 2: gather_fixed<G, R, P, 5, 6>(a, off, nfib, M, out); return;
+      case 3: gather_fixed<G, R, P, 7, 8>(a, off, nfib, M, out); return;
+      case 4: gather_fixed<G, R, P, 9, 10>(a, off, nfib, M, out); return;
+      case 5: gather_fixed<G, R, P, 11, 12>(a, off, nfib, M, out); return;
+      case 6: gather_fixed<G, R, P, 13, 14>(a, off, nfib, M, out); return;
+      case 7: gather_fixed<G, R, P, 15, 16>(a, off, nfib, M, out); return;
       default: break;
     }
   }
@@ -306,13 +455,13 @@ __device__ __forceinline__ void g2b_store(int std_maps, int level, int nb, int n
                                           glb_p<Z64> tm, const R *M, double cf, int stride) {
   if (std_maps) {
     switch (level) {
-      case 1: g2b_store_impl<G, R, P, 4, 3>(in, tm, M, cf, nq, nb, stride); return;
-      case 2: g2b_store_impl<G, R, P, 6, 5>(in, tm, M, cf, nq, nb, stride); return;
-      case 3: g2b_store_impl<G, R, P, 8, 7>(in, tm, M, cf, nq, nb, stride); return;
-      case 4: g2b_store_impl<G, R, P, 10, 9>(in, tm, M, cf, nq, nb, stride); return;
-      case 5: g2b_store_impl<G, R, P, 12, 11>(in, tm, M, cf, nq, nb, stride); return;
-      case 6: g2b_store_impl<G, R, P, 14, 13>(in, tm, M, cf, nq, nb, stride); return;
-      case 7: g2b_store_impl<G, R, P, 16, 15>(in, tm, M, cf, nq, nb, stride); return;
+      case 1: g2b_fixed<G, R, P, 4, 3>(in, tm, M, cf, stride); return;
+      case 2: g2b_fixed<G, R, P, 6, 5>(in, tm, M, cf, stride); return;
+      case 3: g2b_fixed<G, R, P, 8, 7>(in, tm, M, cf, stride); return;
+      case 4: g2b_fixed<G, R, P, 10, 9>(in, tm, M, cf, stride); return;
+      case 5: g2b_fixed<G, R, P, 12, 11>(in, tm, M, cf, stride); return;
+      case 6: g2b_fixed<G, R, P, 14, 13>(in, tm, M, cf, stride); return;
+      case 7: g2b_fixed<G, R, P, 16, 15>(in, tm, M, cf, stride); return;
       default: break;
     }
   }
@@ -411,6 +560,126 @@ __device__ __forceinline__ void potential_impl(const TermCtx &a, cptr<TermDev> T
   }
 }
 
+// Fixed-size potential step (standard maps), in rounds of FPT fibers: each
+// coefficient read with a scalar load updates all FPT fibers of the round.
+template <typename G, typename R, typename P, int NQ, bool KIN>
+__device__ __forceinline__ void potential_fixed(const TermCtx &a, cptr<TermDev> T, P src, P dst,
+                                                int nfib) {
+  typedef typename Cx<R>::T C;
+  constexpr int FPT = NQ <= 8 ? 2 : 1;
+  const R *tab = (const R *)a.tab;
+  const glb_p<const R> tg = (glb_p<const R>)tab;   // per-lane node reads
+  const int na = T->na;
+  const R *x0 = tab + T->xo[0];
+  const R *K0 = tab + T->kg[0];
+  const R kin0 = (R)T->kin[0];
+  const int pot = a.pot;
+  const int bv = pot == kPotSplitRounded ? 1 : 0;
+  const R c0 = (R)T->c0[pot];
+  const R al0 = (R)T->alpha[pot][0];
+  const R be0 = (R)T->beta[bv][0];
+  for (int f0 = 0; f0 < nfib; f0 += FPT * G::N) {
+    bool ok[FPT];
+    int fb[FPT];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      const int f = f0 + G::tid() + j * G::N;
+      ok[j] = f < nfib;
+      fb[j] = ok[j] ? f : 0;
+    }
+    // the fibers (held only for the fused kinetic contraction)
+    C x[FPT][KIN ? NQ : 1];
+    if (KIN) {
+#pragma unroll
+      for (int j = 0; j < FPT; ++j)
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) x[j][u] = ldc<C>(src + fb[j] * NQ + u);
+    }
+    R xq[FPT][kMaxActive];
+    int rem[FPT];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) rem[j] = fb[j];
+#pragma unroll
+    for (int q = 1; q < kMaxActive; ++q) {
+      if (q < na) {
+        const float rq = T->rcp_nq[q];
+        const int nq = T->nq[q];
+        const int xo = T->xo[q];
+#pragma unroll
+        for (int j = 0; j < FPT; ++j) {
+          const int hi = fdiv(rem[j], rq);
+          const int uq = rem[j] - hi * nq;
+          rem[j] = hi;
+          xq[j][q] = tg[xo + uq];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < FPT; ++j) xq[j][q] = 0;
+      }
+    }
+    const cptr<double> al = in_loop_uniform(&T->alpha[pot][0]);
+    const cptr<double> be = in_loop_uniform(&T->beta[bv][0]);
+    const cptr<double> pc = in_loop_uniform(a.pc);
+    R A[FPT], B[FPT];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      A[j] = c0;
+      B[j] = al0;
+    }
+#pragma unroll
+    for (int q = 1; q < kMaxActive; ++q) {
+      if (q < na) {
+        const R alq = (R)al[q], beq = (R)be[q];
+        const R c0q = (R)pc[2 * pair_index(0, q)], k0q = (R)pc[2 * pair_index(0, q) + 1];
+#pragma unroll
+        for (int j = 0; j < FPT; ++j) {
+          const R x2 = xq[j][q] * xq[j][q];
+          A[j] = fma(alq, x2, A[j]);
+          A[j] = fma(beq, xq[j][q], A[j]);
+          B[j] = fma(c0q, x2, B[j]);
+          B[j] = fma(k0q, xq[j][q], B[j]);
+        }
+#pragma unroll
+        for (int r = q + 1; r < kMaxActive; ++r) {
+          if (r < na) {
+            const R cqr = (R)pc[2 * pair_index(q, r)], kqr = (R)pc[2 * pair_index(q, r) + 1];
+#pragma unroll
+            for (int j = 0; j < FPT; ++j) {
+              const R x2 = xq[j][q] * xq[j][q];
+              A[j] = fma(cqr * x2, xq[j][r] * xq[j][r], A[j]);
+              A[j] = fma(kqr * x2, xq[j][r], A[j]);
+            }
+          }
+        }
+      }
+    }
+    const cptr<R> Kw = in_loop_uniform(K0);
+    const cptr<R> xw = in_loop_uniform(x0);
+#pragma unroll 1
+    for (int u = 0; u < NQ; ++u) {
+      const R xv = xw[u];
+#pragma unroll
+      for (int j = 0; j < FPT; ++j) {
+        const R V = fma(fma(B[j], xv, be0), xv, A[j]);
+        const C xu = ldc<C>(src + fb[j] * NQ + u);
+        R re = V * xu.x, im = V * xu.y;
+        if (KIN) {
+          R kr = 0, ki = 0;
+#pragma unroll
+          for (int k = 0; k < NQ; ++k) {
+            const R m = Kw[u * NQ + k];
+            kr = fma(m, x[j][k].x, kr);
+            ki = fma(m, x[j][k].y, ki);
+          }
+          re = fma(kin0, kr, re);
+          im = fma(kin0, ki, im);
+        }
+        if (ok[j]) stc(dst + fb[j] * NQ + u, Cx<R>::make(re, im));
+      }
+    }
+  }
+}
+
 template <typename G, typename R, typename P>
 __device__ __forceinline__ void potential(const TermCtx &a, cptr<TermDev> T, int level0, P src,
                                           P dst, int nfib) {
@@ -418,8 +687,8 @@ __device__ __forceinline__ void potential(const TermCtx &a, cptr<TermDev> T, int
   if (a.std_maps) {
 #define SG_PCASE(L_, NQ_)                                                     \
   case L_:                                                                    \
-    if (kin) potential_impl<G, R, P, NQ_, true>(a, T, src, dst, nfib);        \
-    else potential_impl<G, R, P, NQ_, false>(a, T, src, dst, nfib);           \
+    if (kin) potential_fixed<G, R, P, NQ_, true>(a, T, src, dst, nfib);       \
+    else potential_fixed<G, R, P, NQ_, false>(a, T, src, dst, nfib);          \
     return;
     switch (level0) {
       SG_PCASE(1, 4)
@@ -512,6 +781,134 @@ __device__ __forceinline__ void run_term(const TermCtx &a, cptr<TermDev> T, P ba
   }
 }
 
+// ---------------------------------------------------------------------------
+// In-place form (split operator, standard size maps): one buffer per term.
+// A contraction first loads every input fiber of the group into registers
+// (the host guarantees at most inplace_fpt(NI) fibers per thread), syncs the
+// group, then writes the outputs over the inputs.  Outputs are the same FMA
+// chains, in the same order, as in the ping-pong form.
+// ---------------------------------------------------------------------------
+template <typename G, typename R, int NI, int NO>
+__device__ __forceinline__ void contract_ip(lds_p<typename Cx<R>::T> buf, const R *M, int stride,
+                                            int nouter) {
+  typedef typename Cx<R>::T C;
+  constexpr int FPT = inplace_fpt(NI);
+  const int F = stride * nouter;
+  const float rcp = 1.0f / (float)stride;
+  const int sNI = stride * NI, sNO = stride * NO;
+  int ob[FPT];
+  bool ok[FPT];
+  C x[FPT][NI];
+#pragma unroll
+  for (int j = 0; j < FPT; ++j) {
+    int f = G::tid() + j * G::N;
+    ok[j] = f < F;
+    f = ok[j] ? f : 0;
+    const int hi = fdiv(f, rcp);
+    const int lo = f - hi * stride;
+    const int ib = lo + hi * sNI;
+    ob[j] = lo + hi * sNO;
+#pragma unroll
+    for (int k = 0; k < NI; ++k) x[j][k] = ldc<C>(buf + ib + k * stride);
+  }
+  G::sync();
+  const cptr<R> Mw = in_loop_uniform(M);
+#pragma unroll 1
+  for (int u = 0; u < NO; ++u) {
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      R re = 0, im = 0;
+#pragma unroll
+      for (int k = 0; k < NI; ++k) {
+        const R m = Mw[u * NI + k];
+        re = fma(m, x[j][k].x, re);
+        im = fma(m, x[j][k].y, im);
+      }
+      if (ok[j]) stc(buf + ob[j] + u * stride, Cx<R>::make(re, im));
+    }
+  }
+}
+
+// kind 0: basis -> grid (NI = nb, NO = nq); 2: grid -> basis (NI = nq, NO = nb)
+template <typename G, typename R>
+__device__ __forceinline__ void contract_ip_level(int kind, int level,
+                                                  lds_p<typename Cx<R>::T> buf, const R *M,
+                                                  int stride, int nouter) {
+#define SG_IPCASE(L_, NB_, NQ_)                                               \
+  case L_:                                                                   \
+    if (kind == 0) contract_ip<G, R, NB_, NQ_>(buf, M, stride, nouter);       \
+    else contract_ip<G, R, NQ_, NB_>(buf, M, stride, nouter);                 \
+    return;
+  switch (level) {
+    SG_IPCASE(1, 3, 4)
+    SG_IPCASE(2, 5, 6)
+    SG_IPCASE(3, 7, 8)
+    SG_IPCASE(4, 9, 10)
+    SG_IPCASE(5, 11, 12)
+    SG_IPCASE(6, 13, 14)
+    SG_IPCASE(7, 15, 16)
+    default: break;
+  }
+#undef SG_IPCASE
+}
+
+// Alg. 1 for one term of the split operator in place: gather + basis -> grid,
+// the coupling potential pointwise, grid -> basis, D_l * result to HBM.
+template <typename G, typename R>
+__device__ __forceinline__ void run_term_inplace(const TermCtx &a, cptr<TermDev> T,
+                                                 lds_p<typename Cx<R>::T> buf) {
+  typedef lds_p<typename Cx<R>::T> P;
+  const R *tab = (const R *)a.tab;
+  const int na = T->na;
+  const int nbasis = T->nbasis;
+  const int ngrid = T->ngrid;
+  const int off = T->off;
+  const double cf = T->coeff;
+  {
+    const int nb0 = T->nb[0], nq0 = T->nq[0];
+    gather_b2g<G, R, P>(a, T->lev[0], nb0, nq0, off, nbasis / nb0, tab + T->bt[0], buf);
+    G::sync();
+    int stride = nq0;
+    int nouter = nbasis / nb0;
+    for (int p = 1; p < na; ++p) {
+      nouter /= T->nb[p];
+      contract_ip_level<G, R>(0, T->lev[p], buf, tab + T->bt[p], stride, nouter);
+      G::sync();
+      stride *= T->nq[p];
+    }
+  }
+  potential<G, R, P>(a, T, T->lev[0], buf, buf, ngrid / T->nq[0]);
+  G::sync();
+  {
+    int stride = 1;
+    int nouter = ngrid;
+    for (int p = 0; p < na - 1; ++p) {
+      nouter /= T->nq[p];
+      contract_ip_level<G, R>(2, T->lev[p], buf, tab + T->wt[p], stride, nouter);
+      G::sync();
+      stride *= T->nb[p];
+    }
+    const int p = na - 1;
+    g2b_store<G, R, P>(a.std_maps, T->lev[p], T->nb[p], T->nq[p], buf, a.tm + off,
+                       tab + T->wt[p], cf, stride);
+  }
+}
+
+// One term: the scalar case, then the in-place or the ping-pong form.
+template <typename G, typename R, typename P>
+__device__ __forceinline__ void run_any(const TermCtx &a, cptr<TermDev> T, P base, int inplace) {
+  if (T->na == 0) {
+    if (G::tid() == 0) {
+      const double c0 = T->c0[a.split ? kPotSplit : kPotFull];
+      const Z64 x = ldc<Z64>(a.psi + a.mb[T->off]);
+      stc(a.tm + T->off, Z64{T->coeff * c0 * x.x, T->coeff * c0 * x.y});
+    }
+    return;
+  }
+  if (inplace) run_term_inplace<G, R>(a, T, (lds_p<typename Cx<R>::T>)base);
+  else run_term<G, R, P>(a, T, base, T->ngrid);
+}
+
 // Is instance I part of this launch, and which vector does H act on?
 __device__ __forceinline__ bool live(const SweepArgs &a, cptr<InstDev> I) {
   return I->active && (a.mode == 0 || a.k <= I->K - 1);
@@ -531,7 +928,7 @@ __device__ __forceinline__ TermCtx make_ctx(const SweepArgs &a, cptr<InstDev> I,
   c.tm = (glb_p<Z64>)I->tm;
   c.std_maps = I->std_maps;
   c.split = a.split;
-  const bool r32 = a.split && I->round32;
+  const bool r32 = a.mixed && I->round32;
   c.pot = a.split ? (r32 ? kPotSplitRounded : kPotSplit) : kPotFull;
   c.pc = (cptr<double>)(I->pairs + (size_t)t * kPairStride + (r32 ? 2 * kMaxPairs : 0));
   if (sizeof(R) == sizeof(float)) c.tab = I->tab32;
@@ -544,16 +941,17 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
   extern __shared__ char lds_raw[];
   typedef typename Cx<R>::T C;
   const cptr<PackDev> P = a.packs + blockIdx.x;
-  if (P->block) {
+  const int kind = P->block;
+  if (kind != kPackWaves) {
     const cptr<InstDev> I = a.inst + P->inst[0];
     if (!live(a, I)) return;
     const int t = P->term[0];
     const cptr<TermDev> T = (cptr<TermDev>)(I->terms + t);
     const TermCtx c = make_ctx<R>(a, I, t);
-    if (P->block == 1)
-      run_term<BlockGroup, R, lds_p<C>>(c, T, (lds_p<C>)lds_raw, T->ngrid);
+    if (kind == kPackBlockLds)
+      run_any<BlockGroup, R, lds_p<C>>(c, T, (lds_p<C>)lds_raw, P->inplace[0]);
     else
-      run_term<BlockGroup, R, glb_p<C>>(c, T, (glb_p<C>)(a.scratch + P->scratch_off), T->ngrid);
+      run_any<BlockGroup, R, glb_p<C>>(c, T, (glb_p<C>)(a.scratch + P->scratch_off), 0);
     return;
   }
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -563,7 +961,7 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
   const int t = P->term[w];
   const cptr<TermDev> T = (cptr<TermDev>)(I->terms + t);
   const TermCtx c = make_ctx<R>(a, I, t);
-  run_term<WaveGroup, R, lds_p<C>>(c, T, (lds_p<C>)(lds_raw + P->lds_off[w]), T->ngrid);
+  run_any<WaveGroup, R, lds_p<C>>(c, T, (lds_p<C>)(lds_raw + P->lds_off[w]), P->inplace[w]);
 }
 
 template <typename R>
@@ -594,10 +992,11 @@ hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   a.x1o = c.x1o;
   a.mode = c.mode == Mode::Cheb ? 1 : 0;
   a.k = c.k;
-  a.split = c.prec == SG_MIXED ? 1 : 0;
+  a.split = split_form(pl, c.prec) ? 1 : 0;
+  a.mixed = c.prec == SG_MIXED ? 1 : 0;
   hipError_t e = hipSuccess;
   if (c.prec == SG_FP64) {
-    const PackSet &ps = pl->sets[0];
+    const PackSet &ps = pl->sets[pl->fp64_split ? kSetSplit64 : kSetGrid64];
     if (ps.count == 0) return hipSuccess;
     a.packs = (cptr<PackDev>)(pl->d_packs + ps.first);
     return launch_packs<double>(a, ps.count, ps.lds_bytes, s, c.ev0, c.ev1);
@@ -606,7 +1005,7 @@ hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   // of an instance that also has FP32 terms read the FP32-rounded tables, so
   // that all its terms apply the same one-mode operators and the Smolyak
   // combination cancels their rounding as it does when all run in FP32.
-  const PackSet &p64 = pl->sets[1], &p32 = pl->sets[2];
+  const PackSet &p64 = pl->sets[kSetMixed64], &p32 = pl->sets[kSetMixed32];
   if (p64.count > 0) {
     a.packs = (cptr<PackDev>)(pl->d_packs + p64.first);
     e = launch_packs<double>(a, p64.count, p64.lds_bytes, s, c.ev0,

@@ -426,6 +426,9 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
   h.bytes_apply = 32.0 * (double)h.ncs + 8.0 * (double)h.MB.size() + 4.0 * (double)h.ncs +
                   32.0 * (double)h.MB.size() + (double)sizeof(TermDev) * (double)h.nterms;
 
+  h.split_exact = true;
+  for (int l = 0; l <= L; ++l)
+    if (size_map(h.nqA, h.nqB, l) <= size_map(h.nbA, h.nbB, l)) h.split_exact = false;
   h.cost = cost;
   h.tables32.assign(h.tables.begin(), h.tables.end());
   h.tables32r.assign(h.tables32.begin(), h.tables32.end());

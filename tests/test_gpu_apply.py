@@ -112,6 +112,43 @@ def test_apply_config2_sampled_rows_and_hermiticity():
     assert abs(lhs - rhs) < 1e-12 * abs(lhs)
 
 
+@pytest.mark.parametrize("D,L", [(2, 4), (4, 4), (3, 5), (1, 7)])
+def test_apply_grid_kinetic_form_vs_route1(D, L):
+    """SG_FP64 with the kinetic matrices on every term grid (the literal
+    Alg. 1 form) against Route 1, and against the default split form."""
+    sg = _sg()
+    inst = sg_inputs.small_instance(D, L, seed=300 + 10 * D + L)
+    O = Oracle(inst)
+    psi = rand_state(O.S.n_cs, 17)
+    ref = O.apply_literal(psi)
+    with sg.Problem.from_instance(inst) as P:
+        x, y = to_dev(psi), empty(P.n_cs)
+        assert sg.sg_problem_info(P.handle)["fp64_split"] == 1
+        P.apply(x, y, sg.SG_FP64)
+        split = to_host(y)
+        sg.sg_set_operator_form(P.handle, True)
+        assert sg.sg_problem_info(P.handle)["fp64_split"] == 0
+        P.apply(x, y, sg.SG_FP64)
+        grid = to_host(y)
+    assert max_rel(grid, ref) < TOL_FP64
+    assert max_rel(split, ref) < TOL_FP64
+    assert max_rel(grid, split) < TOL_FP64
+
+
+def test_apply_config1_grid_kinetic_form():
+    sg = _sg()
+    inst = sg_inputs.config1()
+    say("apply config1 grid-kinetic form")
+    H = galerkin_masked_matrix(inst)
+    with sg.Problem.from_instance(inst) as P:
+        psi = rand_state(P.n_cs, 23)
+        x, y = to_dev(psi), empty(P.n_cs)
+        sg.sg_set_operator_form(P.handle, True)
+        P.apply(x, y, sg.SG_FP64)
+        out = to_host(y)
+    assert max_rel(out, H @ psi) < TOL_FP64
+
+
 def test_apply_uncoupled_is_diagonal():
     sg = _sg()
     inst = sg_inputs.small_instance(5, 4, seed=9)

@@ -87,6 +87,32 @@ def test_config_sizes():
             sg.sg_free(h)
 
 
+def test_operator_form_selection_host_only():
+    import paper_2111_13655_amd as sg
+    inst = sg_inputs.config0()
+    P = sg.Problem.from_instance(inst, host_only=True)
+    try:
+        info = sg.sg_problem_info(P.handle)
+        assert info["fp64_split"] == 1          # nq(l) = 2l+2 > nb(l) = 2l+1
+        assert info["flops_fp64"] == info["flops_mixed"]
+        assert info["sweep_flops_fp64"] < info["flops_fp64"]
+        sg.sg_set_operator_form(P.handle, True)
+        info2 = sg.sg_problem_info(P.handle)
+        assert info2["fp64_split"] == 0
+        assert info2["flops_fp64"] > info["flops_fp64"]   # kinetic contractions
+        with pytest.raises(sg.SgError):
+            sg.sg_set_operator_form(P.handle, 2)
+    finally:
+        P.close()
+    # nq = nb at some level: the split is not exact, SG_FP64 keeps the grid form
+    inst2 = sg_inputs.small_instance(2, 2, seed=5, nb=(1, 2), nq=(1, 2))
+    P2 = sg.Problem.from_instance(inst2, host_only=True)
+    try:
+        assert sg.sg_problem_info(P2.handle)["fp64_split"] == 0
+    finally:
+        P2.close()
+
+
 def test_invalid_descriptions_rejected():
     sg = _sg()
     with pytest.raises(sg.SgError) as e:
