@@ -92,6 +92,7 @@ void release(sg_problem *p) {
   hipFree(p->d_rows);
   hipFree(p->d_tables);
   hipFree(p->d_pairs);
+  hipFree(p->d_potc);
   hipFree(p->d_h0);
   hipFree(p->d_tm);
   hipFree(p->d_work);
@@ -155,7 +156,7 @@ namespace sg {
 
 int64_t estimate_device_bytes(const Compiled &h) {
   const int64_t ns = (int64_t)h.MB.size();
-  return (int64_t)h.terms.size() * (int64_t)sizeof(TermDev) + (int64_t)h.pairs.size() * 8 +
+  return (int64_t)h.terms.size() * (int64_t)sizeof(TermDev) + (int64_t)h.pairs.size() * 8 + (int64_t)h.potc.size() * 8 +
          ns * 4 * 2 + (h.ncs + 1) * 4 + h.ncs * 4 + h.ncs * 8 + ns * 16 + 4 * h.ncs * 16 +
          2 * std::max<int64_t>(h.n_items, 256) * 8 + (int64_t)h.tables.size() * 20 +
          (int64_t)sizeof(double) * (kMaxChebTerms + 8);
@@ -183,6 +184,7 @@ sg_status upload_problem(sg_problem *p, sg_problem **out) {
   SG_UP(d_rows, h.rows)
   SG_UP(d_tables, h.tables)
   SG_UP(d_pairs, h.pairs)
+  SG_UP(d_potc, h.potc)
   SG_UP(d_h0, h.h0)
 #undef SG_UP
   size_t tm_bytes = (size_t)ns * sizeof(double2);

@@ -33,8 +33,8 @@ struct alignas(16) TermDev {
   int32_t nbasis;    // prod over active modes of nb
   int32_t ngrid;     // prod over active modes of nq
   int32_t na;        // number of active modes
-  int8_t lev[kMaxActive];   // levels of the active modes, increasing mode id
-  int8_t mode[kMaxActive];  // their mode ids
+  int32_t lev[kMaxActive];  // levels of the active modes, increasing mode id
+  int32_t mode[kMaxActive]; // their mode ids (32-bit: read with scalar loads)
   int32_t nb[kMaxActive];   // per active mode: basis size
   int32_t nq[kMaxActive];   //   grid size
   int32_t bt[kMaxActive];   //   offsets of its level's tables in the table array
@@ -53,6 +53,15 @@ struct alignas(16) TermDev {
   double kin[kMaxActive];          // -1/2 omega_p (kinetic prefactor)
 };
 constexpr int kPotFull = 0, kPotSplit = 1, kPotSplitRounded = 2;
+// Per-term coefficient block of the split coupling potential (exact and
+// FP32-rounded variants), which an in-place term copies into LDS next to its
+// grid buffer:  [0] c0, [1] alpha_0, [2] beta_0, [2+q] alpha_q, [9+q] beta_q,
+// [16+q] c_0q, [23+q] k_0q (q = 1..7), [31 + 2 (pair_index(q,r) - 7)] c_qr,
+// k_qr (1 <= q < r <= 7).
+constexpr int kCoefUsed = 73;
+constexpr int kCoefStride = 80;          // doubles per variant
+constexpr int kCoefLdsBytes = 640;       // LDS reserved per in-place term
+__host__ __device__ constexpr int coef_pair(int q, int r) { return 31 + 2 * (q * (2 * 8 - q - 1) / 2 + (r - q - 1) - 7); }
 // Pair coefficients per term: [2 variants: exact, FP32-rounded][kMaxPairs][c, k].
 constexpr int kPairStride = 4 * kMaxPairs;
 
@@ -76,6 +85,7 @@ struct DeviceTables {
 struct InstDev {
   const TermDev *terms;
   const double *pairs;
+  const double *potc;       // [nterms][2][kCoefStride] split coefficient blocks
   const int32_t *mb;
   const int32_t *inv_ptr;
   const int32_t *inv_col;
@@ -101,16 +111,16 @@ struct InstDev {
   int32_t pad;
 };
 
-// Term-sweep packing.  A workgroup (kSweepThreads threads, four wavefronts)
+// Term-sweep packing.  A workgroup (kSweepThreads threads, eight wavefronts)
 // runs one pack: up to kPackTerms terms, one per wavefront, or one term on
-// all four wavefronts, its buffers in LDS or (too large for LDS) in a global
+// all eight wavefronts, its buffers in LDS or (too large for LDS) in a global
 // scratch region.  A term runs "in place" (one grid buffer: each contraction
 // holds all its input fibers in registers before writing) or "ping-pong"
 // (two buffers).  The host picks, per term, the smallest group whose
 // registers hold every in-place contraction (inplace_fpt below), and packs
 // wave terms under an LDS cap so that two workgroups share a compute unit.
-constexpr int kSweepThreads = 256;
-constexpr int kPackTerms = 4;
+constexpr int kSweepThreads = 512;
+constexpr int kPackTerms = 8;
 constexpr int kLdsPerCU = 160 * 1024;
 constexpr int kComputeUnits = 256;   // MI355X; used to size the packing only
 constexpr int kPingPongWaveMaxGrid = 512;
@@ -129,8 +139,16 @@ struct PackDev {
 struct PackSet {
   int32_t first = 0;            // index of the first pack
   int32_t count = 0;
-  int32_t lds_bytes = 0;        // dynamic LDS of the launch
+  int32_t lds_bytes = 0;        // dynamic LDS of the launch (tables + largest pack)
+  int32_t tab_bytes = 0;        // LDS at offset 0 holding the standard-map tables
 };
+// The one-mode tables of the standard size maps (nb = 2l+1, nq = 2l+2) are
+// the same for every instance; a launch copies them into LDS once per
+// workgroup.  Compact layout per level l: b (nq x nb), wt b^T (nb x nq),
+// nodes (nq), at element offset std_table_base(l).
+__host__ __device__ constexpr int std_table_base(int l) {
+  return 8 * ((l - 1) * l * (2 * l - 1) / 6) + 7 * l * (l - 1) + 6 * l;
+}
 // Pack sets: FP64 with the kinetic matrices on the grid (all terms); FP64
 // with the separable part split off (all terms); the mixed path's FP64 terms;
 // its FP32 terms.
@@ -171,6 +189,7 @@ struct Compiled {
   DeviceTables tdesc;
   std::vector<TermDev> terms;        // [nterms]
   std::vector<double> pairs;         // [nterms][kMaxPairs][2]: c_pq, k_pq of active pairs
+  std::vector<double> potc;          // [nterms][2][kCoefStride]: split coefficient blocks
   std::vector<float> tables32;       // the same tables in FP32 (mixed path)
   std::vector<double> tables32r;     // FP32-rounded tables held in FP64 (mixed-path
                                      // FP64 terms: same operator as the FP32 terms)
@@ -223,6 +242,7 @@ struct sg_problem {
   int32_t *d_rows = nullptr;
   double *d_tables = nullptr;
   double *d_pairs = nullptr;       // [nterms][kPairStride]
+  double *d_potc = nullptr;        // [nterms][2][kCoefStride]
   double *d_h0 = nullptr;
   // work buffers
   double2 *d_tm = nullptr;         // term-major results [N_s]
@@ -266,6 +286,14 @@ struct Plan {
   int64_t packs_capacity = 0, items_capacity = 0, inst_capacity = 0, scratch_capacity = 0;
   bool any32 = false;              // some term of some instance runs in FP32
   bool fp64_split = false;         // SG_FP64 launches use the split form
+  bool any_round32 = false;        // some instance's FP64 terms use rounded tables
+  // standard-map tables for levels 0..stab_L (stab_L < 0: no standard-map instance)
+  int stab_L = -1;
+  std::vector<double> stab64, stab32r;
+  std::vector<float> stab32;
+  double *d_stab64 = nullptr, *d_stab32r = nullptr;
+  float *d_stab32 = nullptr;
+  int64_t stab_capacity = 0;
 };
 
 // Plans (sg_plan.cpp)

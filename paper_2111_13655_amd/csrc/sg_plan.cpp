@@ -66,7 +66,7 @@ Cand make_cand(int32_t inst, int32_t term, const Compiled &h, bool split, int el
   const int64_t one = (int64_t)T.ngrid * elem;
   if (split && std_maps && T.na > 0 && inplace_fits(T, kSweepThreads)) {
     c.inplace = 1;
-    c.slice = one;
+    c.slice = one + kCoefLdsBytes;
     c.wave = inplace_fits(T, 64) ? 1 : 0;
   } else {
     c.inplace = 0;
@@ -76,15 +76,17 @@ Cand make_cand(int32_t inst, int32_t term, const Compiled &h, bool split, int el
   return c;
 }
 
-void pack_set(const std::vector<Cand> &cands, int elem, std::vector<PackDev> *out,
+void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vector<PackDev> *out,
               PackSet *set, int64_t *scratch_bytes) {
   set->first = (int32_t)out->size();
   set->count = 0;
   set->lds_bytes = 0;
+  set->tab_bytes = 0;
   if (cands.empty()) return;
-  // two workgroups per compute unit (FP64), four (FP32)
-  const int cap = elem >= 16 ? kLdsPerCU / 2 : kLdsPerCU / 4;
-  const int per_cu = kLdsPerCU / cap;
+  // two workgroups per compute unit (FP64), four (FP32); the tables come first
+  const int cap_total = elem >= 16 ? kLdsPerCU / 2 : kLdsPerCU / 4;
+  const int per_cu = kLdsPerCU / cap_total;
+  const int cap = cap_total - tab_bytes;
   std::vector<Cand> big, small;
   for (const Cand &c : cands) (c.wave && c.slice <= cap ? small : big).push_back(c);
   auto by_cost = [](const Cand &a, const Cand &b) { return a.cost > b.cost; };
@@ -185,7 +187,8 @@ void pack_set(const std::vector<Cand> &cands, int elem, std::vector<PackDev> *ou
     lds = std::max<int>(lds, (int)bin_bytes[i]);
   }
   set->count = (int32_t)(out->size() - set->first);
-  set->lds_bytes = lds;
+  set->tab_bytes = tab_bytes;
+  set->lds_bytes = tab_bytes + lds;
 }
 
 template <typename T>
@@ -211,6 +214,7 @@ void inst_from_problem(const sg_problem *p, InstDev *d) {
   const Compiled &h = p->h;
   d->terms = p->d_terms;
   d->pairs = p->d_pairs;
+  d->potc = p->d_potc;
   d->mb = p->d_mb;
   d->inv_ptr = p->d_inv_ptr;
   d->inv_col = p->d_inv_col;
@@ -273,12 +277,52 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
       pl->items.push_back({(int32_t)i, (int32_t)(h.n_long_rows + q), local++, 0});
   }
   pl->fp64_split = split_all;
+  // standard-map tables (identical for every such instance) for LDS
+  pl->stab_L = -1;
+  pl->any_round32 = false;
+  const sg_problem *src = nullptr;
+  for (size_t i = 0; i < probs.size(); ++i) {
+    if (!pl->inst[i].std_maps) continue;
+    pl->any_round32 = pl->any_round32 || pl->inst[i].round32;
+    if (probs[i]->h.L > pl->stab_L) {
+      pl->stab_L = probs[i]->h.L;
+      src = probs[i];
+    }
+  }
+  pl->stab64.clear();
+  pl->stab32.clear();
+  pl->stab32r.clear();
+  if (src) {
+    const Compiled &h = src->h;
+    for (int l = 0; l <= pl->stab_L; ++l) {
+      const LevelDev &ld = h.tdesc.lev[l];
+      const int nb = 2 * l + 1, nq = 2 * l + 2;
+      if ((int)pl->stab64.size() != std_table_base(l)) {
+        *err = "standard table layout mismatch";
+        return SG_EINVAL;
+      }
+      auto take = [&](int off, int n) {
+        for (int i = 0; i < n; ++i) {
+          pl->stab64.push_back(h.tables[off + i]);
+          pl->stab32.push_back(h.tables32[off + i]);
+          pl->stab32r.push_back(h.tables32r[off + i]);
+        }
+      };
+      take(ld.bt, nq * nb);
+      take(ld.wt, nb * nq);
+      take(ld.x, nq);
+    }
+  }
+  const int64_t E = (int64_t)pl->stab64.size();
+  const int t64 = (int)((E * 8 + 15) & ~(int64_t)15);
+  const int t32 = (int)((E * 4 + 15) & ~(int64_t)15);
   // the set SG_FP64 launches do not use stays empty
   if (split_all) cg64.clear(); else cs64.clear();
-  pack_set(cg64, 16, &pl->packs, &pl->sets[kSetGrid64], &pl->scratch_bytes);
-  pack_set(cs64, 16, &pl->packs, &pl->sets[kSetSplit64], &pl->scratch_bytes);
-  pack_set(m64, 16, &pl->packs, &pl->sets[kSetMixed64], &pl->scratch_bytes);
-  pack_set(m32, 8, &pl->packs, &pl->sets[kSetMixed32], &pl->scratch_bytes);
+  pack_set(cg64, 16, 0, &pl->packs, &pl->sets[kSetGrid64], &pl->scratch_bytes);
+  pack_set(cs64, 16, t64, &pl->packs, &pl->sets[kSetSplit64], &pl->scratch_bytes);
+  pack_set(m64, 16, pl->any_round32 ? 2 * t64 : t64, &pl->packs, &pl->sets[kSetMixed64],
+           &pl->scratch_bytes);
+  pack_set(m32, 8, t32, &pl->packs, &pl->sets[kSetMixed32], &pl->scratch_bytes);
   (void)err;
   return SG_OK;
 }
@@ -299,6 +343,28 @@ sg_status plan_upload(Plan *pl, hipStream_t s) {
       (e = hipMemcpyAsync(pl->d_items, pl->items.data(), pl->items.size() * sizeof(RedItem),
                           hipMemcpyHostToDevice, s)) != hipSuccess)
     return hip_fail(e, "upload reduce items");
+  const int64_t E = (int64_t)pl->stab64.size();
+  if (E > pl->stab_capacity) {
+    hipFree(pl->d_stab64);
+    hipFree(pl->d_stab32r);
+    hipFree(pl->d_stab32);
+    pl->d_stab64 = pl->d_stab32r = nullptr;
+    pl->d_stab32 = nullptr;
+    pl->stab_capacity = 0;
+    if (hipMalloc((void **)&pl->d_stab64, E * 8) != hipSuccess ||
+        hipMalloc((void **)&pl->d_stab32r, E * 8) != hipSuccess ||
+        hipMalloc((void **)&pl->d_stab32, E * 4) != hipSuccess)
+      return fail(SG_ENOMEM, "device allocation of the standard tables failed");
+    pl->stab_capacity = E;
+  }
+  if (E > 0 &&
+      ((e = hipMemcpyAsync(pl->d_stab64, pl->stab64.data(), E * 8, hipMemcpyHostToDevice, s)) !=
+           hipSuccess ||
+       (e = hipMemcpyAsync(pl->d_stab32r, pl->stab32r.data(), E * 8, hipMemcpyHostToDevice, s)) !=
+           hipSuccess ||
+       (e = hipMemcpyAsync(pl->d_stab32, pl->stab32.data(), E * 4, hipMemcpyHostToDevice, s)) !=
+           hipSuccess))
+    return hip_fail(e, "upload standard tables");
   return plan_upload_inst(pl, s);
 }
 
@@ -320,6 +386,12 @@ void plan_free(Plan *pl) {
   hipFree(pl->d_packs);
   hipFree(pl->d_items);
   hipFree(pl->d_scratch);
+  hipFree(pl->d_stab64);
+  hipFree(pl->d_stab32r);
+  hipFree(pl->d_stab32);
+  pl->d_stab64 = pl->d_stab32r = nullptr;
+  pl->d_stab32 = nullptr;
+  pl->stab_capacity = 0;
   pl->d_inst = nullptr;
   pl->d_packs = nullptr;
   pl->d_items = nullptr;

@@ -55,6 +55,8 @@ struct TermCtx {
   int std_maps;              // nb = 1 + 2l, nq = 2 + 2l
   int split;                 // operator without the separable harmonic part
   int pot;                   // kPotFull / kPotSplit / kPotSplitRounded
+  int lt_off;                // byte offset of this term's tables in LDS
+  glb_p<const double> pcoef; // the term's split coefficient block (variant chosen)
 };
 
 struct SweepArgs {
@@ -66,6 +68,9 @@ struct SweepArgs {
   int k;                 // Chebyshev term being produced
   int split;             // split operator (no kinetic or harmonic part on the grids)
   int mixed;             // SG_MIXED launch (instances with FP32 terms use rounded tables)
+  const void *stab;      // standard-map tables (launch precision) copied to LDS at 0
+  const void *stab_r;    // FP32-rounded FP64 tables, copied after them (or null)
+  int tab_a, tab_b;      // their LDS bytes (multiples of 16)
 };
 
 // Element access through address-space-qualified pointers (member-wise: the
@@ -782,25 +787,38 @@ __device__ __forceinline__ void run_term(const TermCtx &a, cptr<TermDev> T, P ba
 }
 
 // ---------------------------------------------------------------------------
-// In-place form (split operator, standard size maps): one buffer per term.
-// A contraction first loads every input fiber of the group into registers
-// (the host guarantees at most inplace_fpt(NI) fibers per thread), syncs the
-// group, then writes the outputs over the inputs.  Outputs are the same FMA
-// chains, in the same order, as in the ping-pong form.
+// In-place form (split operator, standard size maps): one buffer per term,
+// one-mode tables read from the workgroup's LDS copy.  A contraction first
+// loads every input fiber of the group into registers (the host guarantees
+// at most inplace_fpt(NI) fibers per thread), syncs the group, then writes
+// the outputs over the inputs.  Matrix rows are read one row ahead.  Outputs
+// are the same FMA chains, in the same order, as in the ping-pong form.
 // ---------------------------------------------------------------------------
+template <typename R, int NI>
+__device__ __forceinline__ void ld_row(lds_p<const R> M, int u, R (&r)[NI]) {
+#pragma unroll
+  for (int k = 0; k < NI; ++k) r[k] = M[u * NI + k];
+}
+// Rows are prefetched one ahead for short rows only (long rows would cost
+// more registers than the latency they hide).
+template <int NI> struct RowAhead { static constexpr bool value = NI <= 8; };
+
 template <typename G, typename R, int NI, int NO>
-__device__ __forceinline__ void contract_ip(lds_p<typename Cx<R>::T> buf, const R *M, int stride,
-                                            int nouter) {
+__device__ __forceinline__ void contract_ip(lds_p<typename Cx<R>::T> buf, lds_p<const R> M,
+                                            int stride, int nouter) {
   typedef typename Cx<R>::T C;
   constexpr int FPT = inplace_fpt(NI);
   const int F = stride * nouter;
   const float rcp = 1.0f / (float)stride;
   const int sNI = stride * NI, sNO = stride * NO;
+  // fiber slots this contraction needs (wave-uniform)
+  const int nj = min(FPT, (F + G::N - 1) / G::N);
   int ob[FPT];
   bool ok[FPT];
   C x[FPT][NI];
 #pragma unroll
   for (int j = 0; j < FPT; ++j) {
+    if (j >= nj) break;
     int f = G::tid() + j * G::N;
     ok[j] = f < F;
     f = ok[j] ? f : 0;
@@ -811,44 +829,245 @@ __device__ __forceinline__ void contract_ip(lds_p<typename Cx<R>::T> buf, const 
 #pragma unroll
     for (int k = 0; k < NI; ++k) x[j][k] = ldc<C>(buf + ib + k * stride);
   }
+  R cur[NI], nxt[NI];
+  ld_row<R, NI>(M, 0, cur);
   G::sync();
-  const cptr<R> Mw = in_loop_uniform(M);
 #pragma unroll 1
   for (int u = 0; u < NO; ++u) {
+    if (!RowAhead<NI>::value) ld_row<R, NI>(M, u, cur);
+    else if (u + 1 < NO) ld_row<R, NI>(M, u + 1, nxt);
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
+      if (j >= nj) break;
       R re = 0, im = 0;
 #pragma unroll
       for (int k = 0; k < NI; ++k) {
-        const R m = Mw[u * NI + k];
-        re = fma(m, x[j][k].x, re);
-        im = fma(m, x[j][k].y, im);
+        re = fma(cur[k], x[j][k].x, re);
+        im = fma(cur[k], x[j][k].y, im);
       }
       if (ok[j]) stc(buf + ob[j] + u * stride, Cx<R>::make(re, im));
+    }
+    if (RowAhead<NI>::value) {
+      if (RowAhead<NI>::value) {
+#pragma unroll
+        for (int k = 0; k < NI; ++k) cur[k] = nxt[k];
+      }
     }
   }
 }
 
-// kind 0: basis -> grid (NI = nb, NO = nq); 2: grid -> basis (NI = nq, NO = nb)
+template <typename G, typename R, int NI, int NO>
+__device__ __forceinline__ void gather_ip(const TermCtx &a, int off, int nfib, lds_p<const R> M,
+                                          lds_p<typename Cx<R>::T> out) {
+  typedef typename Cx<R>::T C;
+  constexpr int FPT = Fpt<NI>::value;
+  for (int f0 = 0; f0 < nfib; f0 += FPT * G::N) {
+    const int nj = min(FPT, (nfib - f0 + G::N - 1) / G::N);
+    int idx[FPT][NI];
+    bool ok[FPT];
+    int fb[FPT];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      const int f = f0 + G::tid() + j * G::N;
+      ok[j] = f < nfib;
+      fb[j] = ok[j] ? f : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      if (j >= nj) break;
+#pragma unroll
+      for (int k = 0; k < NI; ++k) idx[j][k] = a.mb[off + fb[j] * NI + k];
+    }
+    C x[FPT][NI];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      if (j >= nj) break;
+#pragma unroll
+      for (int k = 0; k < NI; ++k) {
+        const Z64 v = ldc<Z64>(a.psi + idx[j][k]);
+        x[j][k] = Cx<R>::make((R)v.x, (R)v.y);
+      }
+    }
+    R cur[NI], nxt[NI];
+    ld_row<R, NI>(M, 0, cur);
+#pragma unroll 1
+    for (int u = 0; u < NO; ++u) {
+      if (!RowAhead<NI>::value) ld_row<R, NI>(M, u, cur);
+      else if (u + 1 < NO) ld_row<R, NI>(M, u + 1, nxt);
+#pragma unroll
+      for (int j = 0; j < FPT; ++j) {
+        if (j >= nj) break;
+        R re = 0, im = 0;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+          re = fma(cur[k], x[j][k].x, re);
+          im = fma(cur[k], x[j][k].y, im);
+        }
+        if (ok[j]) stc(out + fb[j] * NO + u, Cx<R>::make(re, im));
+      }
+      if (RowAhead<NI>::value) {
+#pragma unroll
+        for (int k = 0; k < NI; ++k) cur[k] = nxt[k];
+      }
+    }
+  }
+}
+
+template <typename G, typename R, int NI, int NO>
+__device__ __forceinline__ void g2b_ip(lds_p<typename Cx<R>::T> in, glb_p<Z64> tm,
+                                       lds_p<const R> M, double cf, int stride) {
+  typedef typename Cx<R>::T C;
+  constexpr int FPT = Fpt<NI>::value;
+  for (int f0 = 0; f0 < stride; f0 += FPT * G::N) {
+    const int nj = min(FPT, (stride - f0 + G::N - 1) / G::N);
+    bool ok[FPT];
+    int lo[FPT];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      const int f = f0 + G::tid() + j * G::N;
+      ok[j] = f < stride;
+      lo[j] = ok[j] ? f : 0;
+    }
+    C x[FPT][NI];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      if (j >= nj) break;
+#pragma unroll
+      for (int k = 0; k < NI; ++k) x[j][k] = ldc<C>(in + lo[j] + k * stride);
+    }
+    R cur[NI], nxt[NI];
+    ld_row<R, NI>(M, 0, cur);
+#pragma unroll 1
+    for (int u = 0; u < NO; ++u) {
+      if (!RowAhead<NI>::value) ld_row<R, NI>(M, u, cur);
+      else if (u + 1 < NO) ld_row<R, NI>(M, u + 1, nxt);
+#pragma unroll
+      for (int j = 0; j < FPT; ++j) {
+        if (j >= nj) break;
+        R re = 0, im = 0;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+          re = fma(cur[k], x[j][k].x, re);
+          im = fma(cur[k], x[j][k].y, im);
+        }
+        if (ok[j]) stc(tm + lo[j] + u * stride, Z64{cf * (double)re, cf * (double)im});
+      }
+      if (RowAhead<NI>::value) {
+#pragma unroll
+        for (int k = 0; k < NI; ++k) cur[k] = nxt[k];
+      }
+    }
+  }
+}
+
+// The split coupling potential in place (fibers along mode 0; nodes from the
+// LDS tables).  Same arithmetic as potential_fixed without the kinetic part.
+template <typename G, typename R, int NQ>
+__device__ __forceinline__ void potential_ip(const TermCtx &a, cptr<TermDev> T,
+                                             lds_p<typename Cx<R>::T> buf, int nfib,
+                                             lds_p<const R> lt, lds_p<const R> cf) {
+  typedef typename Cx<R>::T C;
+  constexpr int FPT = NQ <= 8 ? 2 : 1;
+  const int na = T->na;
+  const int l0 = T->lev[0];
+  const lds_p<const R> x0 = lt + std_table_base(l0) + 2 * (2 * l0 + 1) * (2 * l0 + 2);
+  const R c0 = cf[0];
+  const R al0 = cf[1];
+  const R be0 = cf[2];
+  for (int f0 = 0; f0 < nfib; f0 += FPT * G::N) {
+    const int nj = min(FPT, (nfib - f0 + G::N - 1) / G::N);
+    bool ok[FPT];
+    int fb[FPT];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      const int f = f0 + G::tid() + j * G::N;
+      ok[j] = f < nfib && j < nj;
+      fb[j] = ok[j] ? f : 0;
+    }
+    R xq[FPT][kMaxActive];
+    int rem[FPT];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) rem[j] = fb[j];
+#pragma unroll
+    for (int q = 1; q < kMaxActive; ++q) {
+      if (q < na) {
+        const float rq = T->rcp_nq[q];
+        const int nq = T->nq[q];
+        const int lq = T->lev[q];
+        const lds_p<const R> xn = lt + std_table_base(lq) + 2 * (2 * lq + 1) * (2 * lq + 2);
+#pragma unroll
+        for (int j = 0; j < FPT; ++j) {
+          const int hi = fdiv(rem[j], rq);
+          const int uq = rem[j] - hi * nq;
+          rem[j] = hi;
+          xq[j][q] = xn[uq];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < FPT; ++j) xq[j][q] = 0;
+      }
+    }
+    R A[FPT], B[FPT];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      A[j] = c0;
+      B[j] = al0;
+    }
+#pragma unroll
+    for (int q = 1; q < kMaxActive; ++q) {
+      if (q < na) {
+        const R alq = cf[2 + q], beq = cf[9 + q];
+        const R c0q = cf[16 + q], k0q = cf[23 + q];
+#pragma unroll
+        for (int j = 0; j < FPT; ++j) {
+          const R x2 = xq[j][q] * xq[j][q];
+          A[j] = fma(alq, x2, A[j]);
+          A[j] = fma(beq, xq[j][q], A[j]);
+          B[j] = fma(c0q, x2, B[j]);
+          B[j] = fma(k0q, xq[j][q], B[j]);
+        }
+#pragma unroll
+        for (int r = q + 1; r < kMaxActive; ++r) {
+          if (r < na) {
+            const R cqr = cf[coef_pair(q, r)], kqr = cf[coef_pair(q, r) + 1];
+#pragma unroll
+            for (int j = 0; j < FPT; ++j) {
+              const R x2 = xq[j][q] * xq[j][q];
+              A[j] = fma(cqr * x2, xq[j][r] * xq[j][r], A[j]);
+              A[j] = fma(kqr * x2, xq[j][r], A[j]);
+            }
+          }
+        }
+      }
+    }
+#pragma unroll 1
+    for (int u = 0; u < NQ; ++u) {
+      const R xv = x0[u];
+#pragma unroll
+      for (int j = 0; j < FPT; ++j) {
+        if (j >= nj) break;
+        const R V = fma(fma(B[j], xv, be0), xv, A[j]);
+        const C xu = ldc<C>(buf + fb[j] * NQ + u);
+        if (ok[j]) stc(buf + fb[j] * NQ + u, Cx<R>::make(V * xu.x, V * xu.y));
+      }
+    }
+  }
+}
+
+// Level dispatch of the in-place steps (standard maps: nb = 2l+1, nq = 2l+2).
+#define SG_LEVELS(X) X(1, 3, 4) X(2, 5, 6) X(3, 7, 8) X(4, 9, 10) X(5, 11, 12) X(6, 13, 14) X(7, 15, 16)
+
 template <typename G, typename R>
 __device__ __forceinline__ void contract_ip_level(int kind, int level,
-                                                  lds_p<typename Cx<R>::T> buf, const R *M,
-                                                  int stride, int nouter) {
-#define SG_IPCASE(L_, NB_, NQ_)                                               \
-  case L_:                                                                   \
-    if (kind == 0) contract_ip<G, R, NB_, NQ_>(buf, M, stride, nouter);       \
-    else contract_ip<G, R, NQ_, NB_>(buf, M, stride, nouter);                 \
+                                                  lds_p<typename Cx<R>::T> buf,
+                                                  lds_p<const R> lt, int stride, int nouter) {
+  const lds_p<const R> base = lt + std_table_base(level);
+#define SG_IPCASE(L_, NB_, NQ_)                                                          \
+  case L_:                                                                              \
+    if (kind == 0) contract_ip<G, R, NB_, NQ_>(buf, base, stride, nouter);               \
+    else contract_ip<G, R, NQ_, NB_>(buf, base + NB_ * NQ_, stride, nouter);             \
     return;
-  switch (level) {
-    SG_IPCASE(1, 3, 4)
-    SG_IPCASE(2, 5, 6)
-    SG_IPCASE(3, 7, 8)
-    SG_IPCASE(4, 9, 10)
-    SG_IPCASE(5, 11, 12)
-    SG_IPCASE(6, 13, 14)
-    SG_IPCASE(7, 15, 16)
-    default: break;
-  }
+  switch (level) { SG_LEVELS(SG_IPCASE) default: break; }
 #undef SG_IPCASE
 }
 
@@ -856,47 +1075,66 @@ __device__ __forceinline__ void contract_ip_level(int kind, int level,
 // the coupling potential pointwise, grid -> basis, D_l * result to HBM.
 template <typename G, typename R>
 __device__ __forceinline__ void run_term_inplace(const TermCtx &a, cptr<TermDev> T,
-                                                 lds_p<typename Cx<R>::T> buf) {
-  typedef lds_p<typename Cx<R>::T> P;
-  const R *tab = (const R *)a.tab;
+                                                 lds_p<typename Cx<R>::T> buf,
+                                                 lds_p<const R> lt) {
   const int na = T->na;
   const int nbasis = T->nbasis;
   const int ngrid = T->ngrid;
   const int off = T->off;
   const double cf = T->coeff;
+  // the coefficient block, into LDS after the grid buffer (published by the
+  // sync after the gather)
+  const lds_p<R> coef = (lds_p<R>)(buf + ngrid);
+  for (int i = G::tid(); i < kCoefUsed; i += G::N) coef[i] = (R)a.pcoef[i];
   {
+    const int l0 = T->lev[0];
     const int nb0 = T->nb[0], nq0 = T->nq[0];
-    gather_b2g<G, R, P>(a, T->lev[0], nb0, nq0, off, nbasis / nb0, tab + T->bt[0], buf);
+    const lds_p<const R> M0 = lt + std_table_base(l0);
+#define SG_GCASE(L_, NB_, NQ_)                                                   \
+  case L_: gather_ip<G, R, NB_, NQ_>(a, off, nbasis / NB_, M0, buf); break;
+    switch (l0) { SG_LEVELS(SG_GCASE) default: break; }
+#undef SG_GCASE
     G::sync();
     int stride = nq0;
     int nouter = nbasis / nb0;
     for (int p = 1; p < na; ++p) {
       nouter /= T->nb[p];
-      contract_ip_level<G, R>(0, T->lev[p], buf, tab + T->bt[p], stride, nouter);
+      contract_ip_level<G, R>(0, T->lev[p], buf, lt, stride, nouter);
       G::sync();
       stride *= T->nq[p];
     }
   }
-  potential<G, R, P>(a, T, T->lev[0], buf, buf, ngrid / T->nq[0]);
-  G::sync();
+  {
+    const int nfib = ngrid / T->nq[0];
+#define SG_PIPCASE(L_, NB_, NQ_)                                                 \
+  case L_: potential_ip<G, R, NQ_>(a, T, buf, nfib, lt, coef); break;
+    switch (T->lev[0]) { SG_LEVELS(SG_PIPCASE) default: break; }
+#undef SG_PIPCASE
+    G::sync();
+  }
   {
     int stride = 1;
     int nouter = ngrid;
     for (int p = 0; p < na - 1; ++p) {
       nouter /= T->nq[p];
-      contract_ip_level<G, R>(2, T->lev[p], buf, tab + T->wt[p], stride, nouter);
+      contract_ip_level<G, R>(2, T->lev[p], buf, lt, stride, nouter);
       G::sync();
       stride *= T->nb[p];
     }
     const int p = na - 1;
-    g2b_store<G, R, P>(a.std_maps, T->lev[p], T->nb[p], T->nq[p], buf, a.tm + off,
-                       tab + T->wt[p], cf, stride);
+    const int lp = T->lev[p];
+    const lds_p<const R> Mw = lt + std_table_base(lp) + (2 * lp + 1) * (2 * lp + 2);
+#define SG_SCASE(L_, NB_, NQ_)                                                   \
+  case L_: g2b_ip<G, R, NQ_, NB_>(buf, a.tm + off, Mw, cf, stride); break;
+    switch (lp) { SG_LEVELS(SG_SCASE) default: break; }
+#undef SG_SCASE
   }
 }
 
 // One term: the scalar case, then the in-place or the ping-pong form.
 template <typename G, typename R, typename P>
-__device__ __forceinline__ void run_any(const TermCtx &a, cptr<TermDev> T, P base, int inplace) {
+__device__ __forceinline__ void run_any(const TermCtx &a, cptr<TermDev> T, P base, int inplace,
+                                        char *lds_raw) {
   if (T->na == 0) {
     if (G::tid() == 0) {
       const double c0 = T->c0[a.split ? kPotSplit : kPotFull];
@@ -905,7 +1143,9 @@ __device__ __forceinline__ void run_any(const TermCtx &a, cptr<TermDev> T, P bas
     }
     return;
   }
-  if (inplace) run_term_inplace<G, R>(a, T, (lds_p<typename Cx<R>::T>)base);
+  if (inplace)
+    run_term_inplace<G, R>(a, T, (lds_p<typename Cx<R>::T>)base,
+                           (lds_p<const R>)(lds_raw + a.lt_off));
   else run_term<G, R, P>(a, T, base, T->ngrid);
 }
 
@@ -933,6 +1173,8 @@ __device__ __forceinline__ TermCtx make_ctx(const SweepArgs &a, cptr<InstDev> I,
   c.pc = (cptr<double>)(I->pairs + (size_t)t * kPairStride + (r32 ? 2 * kMaxPairs : 0));
   if (sizeof(R) == sizeof(float)) c.tab = I->tab32;
   else c.tab = r32 ? (const void *)I->tab32r : (const void *)I->tab64;
+  c.lt_off = (sizeof(R) == sizeof(double) && r32) ? a.tab_a : 0;
+  c.pcoef = (glb_p<const double>)(I->potc + ((size_t)t * 2 + (r32 ? 1 : 0)) * kCoefStride);
   return c;
 }
 
@@ -940,6 +1182,17 @@ template <typename R>
 __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
   extern __shared__ char lds_raw[];
   typedef typename Cx<R>::T C;
+  // the standard-map tables into LDS (every wavefront takes part)
+  {
+    const lds_p<Z64> dst = (lds_p<Z64>)lds_raw;
+    const glb_p<const Z64> sa = (glb_p<const Z64>)a.stab;
+    const glb_p<const Z64> sb = (glb_p<const Z64>)a.stab_r;
+    const int na16 = a.tab_a >> 4, nb16 = a.tab_b >> 4;
+    for (int i = threadIdx.x; i < na16 + nb16; i += kThreads)
+      stc(dst + i, i < na16 ? ldc<Z64>(sa + i) : ldc<Z64>(sb + (i - na16)));
+    if (na16 + nb16 > 0) __syncthreads();
+  }
+  char *const pack_lds = lds_raw + a.tab_a + a.tab_b;
   const cptr<PackDev> P = a.packs + blockIdx.x;
   const int kind = P->block;
   if (kind != kPackWaves) {
@@ -949,9 +1202,10 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
     const cptr<TermDev> T = (cptr<TermDev>)(I->terms + t);
     const TermCtx c = make_ctx<R>(a, I, t);
     if (kind == kPackBlockLds)
-      run_any<BlockGroup, R, lds_p<C>>(c, T, (lds_p<C>)lds_raw, P->inplace[0]);
+      run_any<BlockGroup, R, lds_p<C>>(c, T, (lds_p<C>)pack_lds, P->inplace[0], lds_raw);
     else
-      run_any<BlockGroup, R, glb_p<C>>(c, T, (glb_p<C>)(a.scratch + P->scratch_off), 0);
+      run_any<BlockGroup, R, glb_p<C>>(c, T, (glb_p<C>)(a.scratch + P->scratch_off), 0,
+                                       lds_raw);
     return;
   }
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -961,7 +1215,8 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
   const int t = P->term[w];
   const cptr<TermDev> T = (cptr<TermDev>)(I->terms + t);
   const TermCtx c = make_ctx<R>(a, I, t);
-  run_any<WaveGroup, R, lds_p<C>>(c, T, (lds_p<C>)(lds_raw + P->lds_off[w]), P->inplace[w]);
+  run_any<WaveGroup, R, lds_p<C>>(c, T, (lds_p<C>)(pack_lds + P->lds_off[w]), P->inplace[w],
+                                  lds_raw);
 }
 
 template <typename R>
@@ -994,11 +1249,15 @@ hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   a.k = c.k;
   a.split = split_form(pl, c.prec) ? 1 : 0;
   a.mixed = c.prec == SG_MIXED ? 1 : 0;
+  a.stab = a.stab_r = nullptr;
+  a.tab_a = a.tab_b = 0;
   hipError_t e = hipSuccess;
   if (c.prec == SG_FP64) {
     const PackSet &ps = pl->sets[pl->fp64_split ? kSetSplit64 : kSetGrid64];
     if (ps.count == 0) return hipSuccess;
     a.packs = (cptr<PackDev>)(pl->d_packs + ps.first);
+    a.stab = pl->d_stab64;
+    a.tab_a = ps.tab_bytes;
     return launch_packs<double>(a, ps.count, ps.lds_bytes, s, c.ev0, c.ev1);
   }
   // mixed: terms with large |D_l| in FP64, the rest in FP32.  The FP64 terms
@@ -1008,12 +1267,20 @@ hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   const PackSet &p64 = pl->sets[kSetMixed64], &p32 = pl->sets[kSetMixed32];
   if (p64.count > 0) {
     a.packs = (cptr<PackDev>)(pl->d_packs + p64.first);
+    a.stab = pl->d_stab64;
+    a.stab_r = pl->d_stab32r;
+    a.tab_a = pl->any_round32 ? p64.tab_bytes / 2 : p64.tab_bytes;
+    a.tab_b = pl->any_round32 ? p64.tab_bytes / 2 : 0;
     e = launch_packs<double>(a, p64.count, p64.lds_bytes, s, c.ev0,
                              p32.count > 0 ? nullptr : c.ev1);
     if (e != hipSuccess) return e;
   }
   if (p32.count > 0) {
     a.packs = (cptr<PackDev>)(pl->d_packs + p32.first);
+    a.stab = pl->d_stab32;
+    a.stab_r = nullptr;
+    a.tab_a = p32.tab_bytes;
+    a.tab_b = 0;
     e = launch_packs<float>(a, p32.count, p32.lds_bytes, s, p64.count > 0 ? nullptr : c.ev0,
                             c.ev1);
   }

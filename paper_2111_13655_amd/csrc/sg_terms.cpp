@@ -318,6 +318,7 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
   // ---- per-term operator coefficients -------------------------------------
   h.terms.resize(h.nterms);
   h.pairs.assign((size_t)h.nterms * kPairStride, 0.0);
+  h.potc.assign((size_t)h.nterms * 2 * kCoefStride, 0.0);
   h.grid_literal = h.grid_active = h.max_basis = h.max_grid = 0;
   h.flops_fp64 = h.flops_mixed = 0.0;
   std::vector<double> cost(h.nterms);
@@ -338,8 +339,8 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
     int64_t nbas = 1, ngr = 1;
     for (size_t p = 0; p < act.size(); ++p) {
       const int l = lv[act[p]];
-      T.lev[p] = (int8_t)l;
-      T.mode[p] = (int8_t)act[p];
+      T.lev[p] = l;
+      T.mode[p] = act[p];
       T.nb[p] = size_map(h.nbA, h.nbB, l);
       T.nq[p] = size_map(h.nqA, h.nqB, l);
       T.bt[p] = h.tdesc.lev[l].bt;
@@ -396,6 +397,28 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
       T.beta[0][p] = be;
       T.beta[1][p] = r32(be);
       T.kin[p] = -0.5 * h.omega[m];
+    }
+    // split coefficient blocks (exact, then rounded to FP32)
+    for (int v = 0; v < 2; ++v) {
+      double *cb = &h.potc[((size_t)t * 2 + v) * kCoefStride];
+      const int pot = v == 0 ? kPotSplit : kPotSplitRounded;
+      const double *pv = pr + (v == 0 ? 0 : 2 * kMaxPairs);
+      const int na = (int)act.size();
+      cb[0] = T.c0[pot];
+      if (na > 0) {
+        cb[1] = T.alpha[pot][0];
+        cb[2] = T.beta[v][0];
+      }
+      for (int q = 1; q < na; ++q) {
+        cb[2 + q] = T.alpha[pot][q];
+        cb[9 + q] = T.beta[v][q];
+        cb[16 + q] = pv[2 * pair_index(0, q)];
+        cb[23 + q] = pv[2 * pair_index(0, q) + 1];
+        for (int r = q + 1; r < na; ++r) {
+          cb[coef_pair(q, r)] = pv[2 * pair_index(q, r)];
+          cb[coef_pair(q, r) + 1] = pv[2 * pair_index(q, r) + 1];
+        }
+      }
     }
     // sizes and algorithmic flops (4 per complex x real multiply-add)
     h.grid_literal += glit;
