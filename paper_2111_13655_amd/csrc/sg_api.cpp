@@ -178,7 +178,7 @@ sg_status upload_problem(sg_problem *p, sg_problem **out) {
   SG_UP(d_terms, h.terms)
   SG_UP(d_tables32, h.tables32)
   SG_UP(d_tables32r, h.tables32r)
-  SG_UP(d_mb, h.MB)
+  SG_UP(d_mb, h.mbd)
   SG_UP(d_inv_ptr, h.inv_ptr)
   SG_UP(d_inv_col, h.inv_col)
   SG_UP(d_rows, h.rows)

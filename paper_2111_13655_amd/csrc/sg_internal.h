@@ -88,7 +88,7 @@ struct InstDev {
   const double *potc;       // [nterms][2][kCoefStride] split coefficient blocks
   const int32_t *mb;
   const int32_t *inv_ptr;
-  const int32_t *inv_col;
+  const int32_t *inv_col;   // [N_s] term-major entries of each compact row
   const int32_t *rows;      // long rows first, then short rows
   const double *h0;
   const double *tab64;      // one-mode tables, exact
@@ -183,6 +183,7 @@ struct Compiled {
   std::vector<int32_t> MB;           // [N_s]
   std::vector<int32_t> inv_ptr;      // [ncs+1] inverse CSR row pointers
   std::vector<int32_t> inv_col;      // [N_s] term-major positions, ascending
+  std::vector<int32_t> mbd;          // [N_s] M^B, positions lexicographic (device order)
   std::vector<double> h0;            // [ncs] sum_i omega_i (n_i + 1/2)
   // tables
   std::vector<double> tables;

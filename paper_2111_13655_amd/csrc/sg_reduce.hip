@@ -4,10 +4,12 @@
 // The scatter-add is done as a gather: every compact index sums its
 // term-major contributions through the inverse of M^B in a fixed order (a
 // whole wavefront for a long row, a group of 8 lanes for each of 8 short
-// rows), so results are bitwise reproducible and independent of which other
-// instances share the launch.  The exact FP64 diagonal part of the mixed
-// path, the Chebyshev recurrence, the series accumulation and the norm /
-// energy partial sums are fused into the epilogue.
+// rows).  Term positions are lexicographic like the compact basis, so the
+// contributions of neighbouring rows to one term are neighbours in memory.
+// Results are bitwise reproducible and independent of which other instances
+// share the launch.  The exact FP64 diagonal of the split operator, the Chebyshev
+// recurrence, the series accumulation and the norm / energy partial sums are
+// fused into the epilogue.
 #include <hip/hip_ext.h>
 
 #include "sg_internal.h"
@@ -18,9 +20,26 @@ namespace {
 
 constexpr int kRedThreads = 256;
 
+template <typename T> using glb_p = __attribute__((address_space(1))) T *;
+template <typename T> using cptr = const __attribute__((address_space(4))) T *;
+
+struct alignas(16) Z64 { double x, y; };
+template <typename P>
+__device__ __forceinline__ Z64 ldz(P p) {
+  Z64 v;
+  v.x = p->x;
+  v.y = p->y;
+  return v;
+}
+template <typename P>
+__device__ __forceinline__ void stz(P p, double x, double y) {
+  p->x = x;
+  p->y = y;
+}
+
 struct ReduceArgs {
-  const InstDev *inst;
-  const RedItem *items;
+  cptr<InstDev> inst;
+  cptr<RedItem> items;
   int64_t nitems;
   double2 *x0o, *x1o;
   int mode;            // 0 apply, 1 Chebyshev
@@ -30,23 +49,21 @@ struct ReduceArgs {
 };
 
 // Sum of tm[col[j]] for j = b + sub, b + sub + G, ... < e, in increasing j.
-// Four index loads and then four value loads are issued before any add, so a
-// long row waits for one memory round trip per four entries, not per entry.
+// Four index loads and then four value loads are issued before any add.
 template <int G>
-__device__ __forceinline__ void strided_sum(const int32_t *__restrict__ col,
-                                            const double2 *__restrict__ tm, int b, int e,
-                                            int sub, double *sr, double *si) {
+__device__ __forceinline__ void strided_sum(glb_p<const int32_t> col, glb_p<const Z64> tm, int b,
+                                            int e, int sub, double *sr, double *si) {
   int j = b + sub;
   for (; j + 3 * G < e; j += 4 * G) {
     const int c0 = col[j], c1 = col[j + G], c2 = col[j + 2 * G], c3 = col[j + 3 * G];
-    const double2 v0 = tm[c0], v1 = tm[c1], v2 = tm[c2], v3 = tm[c3];
+    const Z64 v0 = ldz(tm + c0), v1 = ldz(tm + c1), v2 = ldz(tm + c2), v3 = ldz(tm + c3);
     *sr += v0.x; *si += v0.y;
     *sr += v1.x; *si += v1.y;
     *sr += v2.x; *si += v2.y;
     *sr += v3.x; *si += v3.y;
   }
   for (; j < e; j += G) {
-    const double2 v = tm[col[j]];
+    const Z64 v = ldz(tm + col[j]);
     *sr += v.x;
     *si += v.y;
   }
@@ -59,90 +76,123 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+// The row's epilogue inputs, loaded before its sum so that their latency
+// overlaps it.
+struct RowIn {
+  Z64 vk;     // the vector H acts on
+  double d;   // exact diagonal (split form)
+  Z64 pr;     // phi_{k-2}
+  Z64 ac;     // running series sum
+};
+
+__device__ __forceinline__ RowIn row_inputs(const ReduceArgs &a, cptr<InstDev> I, int64_t row) {
+  RowIn in{};
+  double2 *x0 = a.x0o ? a.x0o : I->x0;
+  double2 *x1 = a.x1o ? a.x1o : I->x1;
+  const double2 *vin = (a.mode == 0) ? x0 : (((a.k - 1) & 1) ? x1 : x0);
+  in.vk = ldz((glb_p<const Z64>)vin + row);
+  in.d = a.split ? ((glb_p<const double>)I->h0)[row] : 0.0;
+  if (a.mode == 1 && a.k > 1) {
+    const double2 *prev = (a.k & 1) ? x1 : x0;
+    in.pr = ldz((glb_p<const Z64>)prev + row);
+    in.ac = ldz((glb_p<const Z64>)I->acc + row);
+  }
+  return in;
+}
+
 // Row epilogue: (H psi)[row] = s (+ exact diagonal), then either the plain
 // output or one Chebyshev recurrence step phi_k = -2i Hs phi_{k-1} + phi_{k-2}
 // (phi_1 = -i Hs phi_0), acc += a_k phi_k, and on the last term
 // psi <- exp(-i Ebar dt) acc.
-__device__ __forceinline__ void row_epilogue(const ReduceArgs &a, const InstDev *I, int64_t row,
-                                             double sr, double si, double *pn, double *pe) {
+__device__ __forceinline__ void row_epilogue(const ReduceArgs &a, cptr<InstDev> I, int64_t row,
+                                             const RowIn &in, double sr, double si, double *pn,
+                                             double *pe) {
   double2 *x0 = a.x0o ? a.x0o : I->x0;
   double2 *x1 = a.x1o ? a.x1o : I->x1;
-  const double2 *vin = (a.mode == 0) ? x0 : (((a.k - 1) & 1) ? x1 : x0);
-  const double2 vk = vin[row];
+  const Z64 vk = in.vk;
   if (a.split) {
-    const double d = I->h0[row];
-    sr = fma(d, vk.x, sr);
-    si = fma(d, vk.y, si);
+    sr = fma(in.d, vk.x, sr);
+    si = fma(in.d, vk.y, si);
   }
   if (a.mode == 0) {
-    x1[row] = make_double2(sr, si);
+    stz((glb_p<Z64>)x1 + row, sr, si);
     return;
   }
   double2 *prev = (a.k & 1) ? x1 : x0;   // phi_{k-2} in, phi_k out
   const double zr = (sr - I->ebar * vk.x) * I->inv_half;
   const double zi = (si - I->ebar * vk.y) * I->inv_half;
   const double ak = I->cheb_a[a.k];
-  double2 phi, accv;
+  double phx, phy, acx, acy;
   if (a.k == 1) {
     const double a0 = I->cheb_a[0];
-    phi = make_double2(zi, -zr);  // -i z
-    accv = make_double2(a0 * vk.x + ak * phi.x, a0 * vk.y + ak * phi.y);
+    phx = zi;                              // -i z
+    phy = -zr;
+    acx = a0 * vk.x + ak * phx;
+    acy = a0 * vk.y + ak * phy;
     *pn = vk.x * vk.x + vk.y * vk.y;
-    *pe = vk.x * sr + vk.y * si;  // Re(conj(psi) H psi)
+    *pe = vk.x * sr + vk.y * si;           // Re(conj(psi) H psi)
   } else {
-    const double2 pr = prev[row];
-    phi = make_double2(2.0 * zi + pr.x, -2.0 * zr + pr.y);  // -2i z + phi_{k-2}
-    const double2 ac = I->acc[row];
-    accv = make_double2(ac.x + ak * phi.x, ac.y + ak * phi.y);
+    phx = 2.0 * zi + in.pr.x;              // -2i z + phi_{k-2}
+    phy = -2.0 * zr + in.pr.y;
+    acx = in.ac.x + ak * phx;
+    acy = in.ac.y + ak * phy;
   }
   if (a.k == I->K - 1) {
-    x0[row] = make_double2(I->phase_re * accv.x - I->phase_im * accv.y,
-                           I->phase_re * accv.y + I->phase_im * accv.x);
+    stz((glb_p<Z64>)x0 + row, I->phase_re * acx - I->phase_im * acy,
+        I->phase_re * acy + I->phase_im * acx);
   } else {
-    prev[row] = phi;
-    I->acc[row] = accv;
+    stz((glb_p<Z64>)prev + row, phx, phy);
+    stz((glb_p<Z64>)I->acc + row, acx, acy);
   }
 }
 
 // step 5 (second half): compact[r] = sum of its term-major contributions
 __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * (kRedThreads / 64) + wave;
   if (gw >= a.nitems) return;
-  const RedItem it = a.items[gw];
-  const InstDev *I = a.inst + it.inst;
+  const cptr<RedItem> it = a.items + gw;
+  const cptr<InstDev> I = a.inst + it->inst;
   if (!I->active || (a.mode == 1 && a.k > I->K - 1)) return;
+  const glb_p<const Z64> tm = (glb_p<const Z64>)I->tm;
+  const glb_p<const int32_t> ptr = (glb_p<const int32_t>)I->inv_ptr;
+  const glb_p<const int32_t> rows = (glb_p<const int32_t>)I->rows;
+  const glb_p<const int32_t> col = (glb_p<const int32_t>)I->inv_col;
   double pn = 0.0, pe = 0.0;
-  if (it.first < I->nlong) {
-    const int64_t row = I->rows[it.first];
-    const int b = I->inv_ptr[row], e = I->inv_ptr[row + 1];
+  if (it->first < I->nlong) {
+    const int64_t row = __builtin_amdgcn_readfirstlane(rows[it->first]);
+    const int b = __builtin_amdgcn_readfirstlane(ptr[row]);
+    const int e = __builtin_amdgcn_readfirstlane(ptr[row + 1]);
+    const RowIn in = row_inputs(a, I, row);
     double sr = 0.0, si = 0.0;
-    strided_sum<64>(I->inv_col, I->tm, b, e, lane, &sr, &si);
+    strided_sum<64>(col, tm, b, e, lane, &sr, &si);
     sr = group_sum<64>(sr);
     si = group_sum<64>(si);
-    if (lane == 0) row_epilogue(a, I, row, sr, si, &pn, &pe);
+    if (lane == 0) row_epilogue(a, I, row, in, sr, si, &pn, &pe);
   } else {
-    const int64_t ri = (int64_t)it.first + lane / kShortLanes;
+    const int64_t ri = (int64_t)it->first + lane / kShortLanes;
     const int sub = lane % kShortLanes;
     const bool valid = ri < I->ncs;
     double sr = 0.0, si = 0.0;
     int64_t row = 0;
+    RowIn in{};
     if (valid) {
-      row = I->rows[ri];
-      const int b = I->inv_ptr[row], e = I->inv_ptr[row + 1];
-      strided_sum<kShortLanes>(I->inv_col, I->tm, b, e, sub, &sr, &si);
+      row = rows[ri];
+      const int b = ptr[row], e = ptr[row + 1];
+      in = row_inputs(a, I, row);
+      strided_sum<kShortLanes>(col, tm, b, e, sub, &sr, &si);
     }
     sr = group_sum<kShortLanes>(sr);
     si = group_sum<kShortLanes>(si);
-    if (valid && sub == 0) row_epilogue(a, I, row, sr, si, &pn, &pe);
+    if (valid && sub == 0) row_epilogue(a, I, row, in, sr, si, &pn, &pe);
   }
   if (a.mode == 1 && a.k == 1 && a.want_partials) {
     pn = group_sum<64>(pn);
     pe = group_sum<64>(pe);
     if (lane == 0) {
-      I->partials[2 * it.local] = pn;
-      I->partials[2 * it.local + 1] = pe;
+      I->partials[2 * it->local] = pn;
+      I->partials[2 * it->local + 1] = pe;
     }
   }
 }
@@ -236,8 +286,8 @@ __global__ __launch_bounds__(256) void axpby_kernel(int64_t n, double2 *y, const
 
 hipError_t launch_reduce(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   ReduceArgs a;
-  a.inst = pl->d_inst;
-  a.items = pl->d_items;
+  a.inst = (cptr<InstDev>)pl->d_inst;
+  a.items = (cptr<RedItem>)pl->d_items;
   a.nitems = (int64_t)pl->items.size();
   a.x0o = c.x0o;
   a.x1o = c.x1o;

@@ -49,7 +49,7 @@ struct alignas(8) Z32 { float x, y; };
 struct TermCtx {
   glb_p<const int32_t> mb;
   glb_p<const Z64> psi;      // the vector H is applied to
-  glb_p<Z64> tm;
+  glb_p<Z64> tm;             // term-major contributions
   const void *tab;           // one-mode tables in the arithmetic type
   cptr<double> pc;           // the term's pair coefficients (variant chosen)
   int std_maps;              // nb = 1 + 2l, nq = 2 + 2l
@@ -87,6 +87,11 @@ __device__ __forceinline__ void stc(P p, const C &v) {
   p->x = v.x;
   p->y = v.y;
 }
+
+// Where a term's outputs go: entry i of the term lands at tm[i].
+struct Out {
+  glb_p<Z64> tm;
+};
 
 template <typename R> struct Cx;
 template <> struct Cx<double> {
@@ -298,7 +303,7 @@ __device__ __forceinline__ void gather_fixed(const TermCtx &a, int off, int nfib
 }
 
 template <typename G, typename R, typename P, int NI, int NO>
-__device__ __forceinline__ void g2b_fixed(P in, glb_p<Z64> tm, const R *M, double cf,
+__device__ __forceinline__ void g2b_fixed(P in, Out o, const R *M, double cf,
                                           int stride) {
   typedef typename Cx<R>::T C;
   constexpr int FPT = Fpt<NI>::value;
@@ -328,7 +333,7 @@ __device__ __forceinline__ void g2b_fixed(P in, glb_p<Z64> tm, const R *M, doubl
           re = fma(m, x[j][k].x, re);
           im = fma(m, x[j][k].y, im);
         }
-        if (ok[j]) stc(tm + lo[j] + u * stride, Z64{cf * (double)re, cf * (double)im});
+        if (ok[j]) stc(o.tm + lo[j] + u * stride, Z64{cf * (double)re, cf * (double)im});
       }
     }
   }
@@ -428,7 +433,7 @@ __device__ __forceinline__ void gather_b2g(const TermCtx &a, int level, int nb, 
 // (nouter = 1), written as D_l * result in FP64 to the term-major buffer.
 // ---------------------------------------------------------------------------
 template <typename G, typename R, typename P, int NI_, int NO_>
-__device__ __forceinline__ void g2b_store_impl(P in, glb_p<Z64> tm, const R *M, double cf,
+__device__ __forceinline__ void g2b_store_impl(P in, Out o, const R *M, double cf,
                                                int ni, int no, int stride) {
   typedef typename Cx<R>::T C;
   const int NI = NI_ > 0 ? NI_ : ni;
@@ -450,27 +455,27 @@ __device__ __forceinline__ void g2b_store_impl(P in, glb_p<Z64> tm, const R *M, 
           im = fma(m, x[k].y, im);
         }
       }
-      stc(tm + lo + u * stride, Z64{cf * (double)re, cf * (double)im});
+      stc(o.tm + lo + u * stride, Z64{cf * (double)re, cf * (double)im});
     }
   }
 }
 
 template <typename G, typename R, typename P>
 __device__ __forceinline__ void g2b_store(int std_maps, int level, int nb, int nq, P in,
-                                          glb_p<Z64> tm, const R *M, double cf, int stride) {
+                                          Out o, const R *M, double cf, int stride) {
   if (std_maps) {
     switch (level) {
-      case 1: g2b_fixed<G, R, P, 4, 3>(in, tm, M, cf, stride); return;
-      case 2: g2b_fixed<G, R, P, 6, 5>(in, tm, M, cf, stride); return;
-      case 3: g2b_fixed<G, R, P, 8, 7>(in, tm, M, cf, stride); return;
-      case 4: g2b_fixed<G, R, P, 10, 9>(in, tm, M, cf, stride); return;
-      case 5: g2b_fixed<G, R, P, 12, 11>(in, tm, M, cf, stride); return;
-      case 6: g2b_fixed<G, R, P, 14, 13>(in, tm, M, cf, stride); return;
-      case 7: g2b_fixed<G, R, P, 16, 15>(in, tm, M, cf, stride); return;
+      case 1: g2b_fixed<G, R, P, 4, 3>(in, o, M, cf, stride); return;
+      case 2: g2b_fixed<G, R, P, 6, 5>(in, o, M, cf, stride); return;
+      case 3: g2b_fixed<G, R, P, 8, 7>(in, o, M, cf, stride); return;
+      case 4: g2b_fixed<G, R, P, 10, 9>(in, o, M, cf, stride); return;
+      case 5: g2b_fixed<G, R, P, 12, 11>(in, o, M, cf, stride); return;
+      case 6: g2b_fixed<G, R, P, 14, 13>(in, o, M, cf, stride); return;
+      case 7: g2b_fixed<G, R, P, 16, 15>(in, o, M, cf, stride); return;
       default: break;
     }
   }
-  g2b_store_impl<G, R, P, 0, 0>(in, tm, M, cf, nq, nb, stride);
+  g2b_store_impl<G, R, P, 0, 0>(in, o, M, cf, nq, nb, stride);
 }
 
 // ---------------------------------------------------------------------------
@@ -522,12 +527,13 @@ __device__ __forceinline__ void potential_impl(const TermCtx &a, cptr<TermDev> T
         A = fma((R)al[q], x2, A);
         A = fma((R)be[q], xq[q], A);
         B = fma((R)pc[2 * pair_index(0, q)], x2, B);
-        B = fma((R)pc[2 * pair_index(0, q) + 1], xq[q], B);
+        Cc = fma((R)pc[2 * pair_index(0, q) + 1], x2, Cc);
 #pragma unroll
         for (int r = q + 1; r < kMaxActive; ++r) {
           if (r < na) {
-            A = fma((R)pc[2 * pair_index(q, r)] * x2, xq[r] * xq[r], A);
-            A = fma((R)pc[2 * pair_index(q, r) + 1] * x2, xq[r], A);
+            const R y2 = xq[r] * xq[r];
+            A = fma((R)pc[2 * pair_index(q, r)] * x2, y2, A);
+            A = fma((R)pc[2 * pair_index(q, r) + 1] * y2, xq[q], A);
           }
         }
       }
@@ -625,11 +631,12 @@ __device__ __forceinline__ void potential_fixed(const TermCtx &a, cptr<TermDev> 
     const cptr<double> al = in_loop_uniform(&T->alpha[pot][0]);
     const cptr<double> be = in_loop_uniform(&T->beta[bv][0]);
     const cptr<double> pc = in_loop_uniform(a.pc);
-    R A[FPT], B[FPT];
+    R A[FPT], B[FPT], Cl[FPT];
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
       A[j] = c0;
       B[j] = al0;
+      Cl[j] = be0;
     }
 #pragma unroll
     for (int q = 1; q < kMaxActive; ++q) {
@@ -642,7 +649,7 @@ __device__ __forceinline__ void potential_fixed(const TermCtx &a, cptr<TermDev> 
           A[j] = fma(alq, x2, A[j]);
           A[j] = fma(beq, xq[j][q], A[j]);
           B[j] = fma(c0q, x2, B[j]);
-          B[j] = fma(k0q, xq[j][q], B[j]);
+          Cl[j] = fma(k0q, x2, Cl[j]);
         }
 #pragma unroll
         for (int r = q + 1; r < kMaxActive; ++r) {
@@ -651,8 +658,9 @@ __device__ __forceinline__ void potential_fixed(const TermCtx &a, cptr<TermDev> 
 #pragma unroll
             for (int j = 0; j < FPT; ++j) {
               const R x2 = xq[j][q] * xq[j][q];
-              A[j] = fma(cqr * x2, xq[j][r] * xq[j][r], A[j]);
-              A[j] = fma(kqr * x2, xq[j][r], A[j]);
+              const R y2 = xq[j][r] * xq[j][r];
+              A[j] = fma(cqr * x2, y2, A[j]);
+              A[j] = fma(kqr * y2, xq[j][q], A[j]);
             }
           }
         }
@@ -665,7 +673,7 @@ __device__ __forceinline__ void potential_fixed(const TermCtx &a, cptr<TermDev> 
       const R xv = xw[u];
 #pragma unroll
       for (int j = 0; j < FPT; ++j) {
-        const R V = fma(fma(B[j], xv, be0), xv, A[j]);
+        const R V = fma(fma(B[j], xv, Cl[j]), xv, A[j]);
         const C xu = ldc<C>(src + fb[j] * NQ + u);
         R re = V * xu.x, im = V * xu.y;
         if (KIN) {
@@ -781,7 +789,7 @@ __device__ __forceinline__ void run_term(const TermCtx &a, cptr<TermDev> T, P ba
       stride *= nb;
     }
     const int p = na - 1;
-    g2b_store<G, R, P>(a.std_maps, T->lev[p], T->nb[p], T->nq[p], src, a.tm + off,
+    g2b_store<G, R, P>(a.std_maps, T->lev[p], T->nb[p], T->nq[p], src, Out{a.tm + off},
                        tab + T->wt[p], cf, stride);
   }
 }
@@ -914,8 +922,8 @@ __device__ __forceinline__ void gather_ip(const TermCtx &a, int off, int nfib, l
 }
 
 template <typename G, typename R, int NI, int NO>
-__device__ __forceinline__ void g2b_ip(lds_p<typename Cx<R>::T> in, glb_p<Z64> tm,
-                                       lds_p<const R> M, double cf, int stride) {
+__device__ __forceinline__ void g2b_ip(lds_p<typename Cx<R>::T> in, Out o, lds_p<const R> M,
+                                       double cf, int stride) {
   typedef typename Cx<R>::T C;
   constexpr int FPT = Fpt<NI>::value;
   for (int f0 = 0; f0 < stride; f0 += FPT * G::N) {
@@ -950,7 +958,7 @@ __device__ __forceinline__ void g2b_ip(lds_p<typename Cx<R>::T> in, glb_p<Z64> t
           re = fma(cur[k], x[j][k].x, re);
           im = fma(cur[k], x[j][k].y, im);
         }
-        if (ok[j]) stc(tm + lo[j] + u * stride, Z64{cf * (double)re, cf * (double)im});
+        if (ok[j]) stc(o.tm + lo[j] + u * stride, Z64{cf * (double)re, cf * (double)im});
       }
       if (RowAhead<NI>::value) {
 #pragma unroll
@@ -1007,11 +1015,12 @@ __device__ __forceinline__ void potential_ip(const TermCtx &a, cptr<TermDev> T,
         for (int j = 0; j < FPT; ++j) xq[j][q] = 0;
       }
     }
-    R A[FPT], B[FPT];
+    R A[FPT], B[FPT], Cl[FPT];
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
       A[j] = c0;
       B[j] = al0;
+      Cl[j] = be0;
     }
 #pragma unroll
     for (int q = 1; q < kMaxActive; ++q) {
@@ -1024,7 +1033,7 @@ __device__ __forceinline__ void potential_ip(const TermCtx &a, cptr<TermDev> T,
           A[j] = fma(alq, x2, A[j]);
           A[j] = fma(beq, xq[j][q], A[j]);
           B[j] = fma(c0q, x2, B[j]);
-          B[j] = fma(k0q, xq[j][q], B[j]);
+          Cl[j] = fma(k0q, x2, Cl[j]);
         }
 #pragma unroll
         for (int r = q + 1; r < kMaxActive; ++r) {
@@ -1033,8 +1042,9 @@ __device__ __forceinline__ void potential_ip(const TermCtx &a, cptr<TermDev> T,
 #pragma unroll
             for (int j = 0; j < FPT; ++j) {
               const R x2 = xq[j][q] * xq[j][q];
-              A[j] = fma(cqr * x2, xq[j][r] * xq[j][r], A[j]);
-              A[j] = fma(kqr * x2, xq[j][r], A[j]);
+              const R y2 = xq[j][r] * xq[j][r];
+              A[j] = fma(cqr * x2, y2, A[j]);
+              A[j] = fma(kqr * y2, xq[j][q], A[j]);
             }
           }
         }
@@ -1046,7 +1056,7 @@ __device__ __forceinline__ void potential_ip(const TermCtx &a, cptr<TermDev> T,
 #pragma unroll
       for (int j = 0; j < FPT; ++j) {
         if (j >= nj) break;
-        const R V = fma(fma(B[j], xv, be0), xv, A[j]);
+        const R V = fma(fma(B[j], xv, Cl[j]), xv, A[j]);
         const C xu = ldc<C>(buf + fb[j] * NQ + u);
         if (ok[j]) stc(buf + fb[j] * NQ + u, Cx<R>::make(V * xu.x, V * xu.y));
       }
@@ -1125,7 +1135,7 @@ __device__ __forceinline__ void run_term_inplace(const TermCtx &a, cptr<TermDev>
     const int lp = T->lev[p];
     const lds_p<const R> Mw = lt + std_table_base(lp) + (2 * lp + 1) * (2 * lp + 2);
 #define SG_SCASE(L_, NB_, NQ_)                                                   \
-  case L_: g2b_ip<G, R, NQ_, NB_>(buf, a.tm + off, Mw, cf, stride); break;
+  case L_: g2b_ip<G, R, NQ_, NB_>(buf, Out{a.tm + off}, Mw, cf, stride); break;
     switch (lp) { SG_LEVELS(SG_SCASE) default: break; }
 #undef SG_SCASE
   }

@@ -239,7 +239,13 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
     h.off[t + 1] = h.off[t] + sz;
   }
   if (h.off[h.nterms] != sizes[1]) { *err = "internal: N_s mismatch"; return SG_EINVAL; }
+  // M^B in Table 2's position order (mode 1 fastest), and the device copy
+  // with positions in lexicographic order (mode D fastest, as the compact
+  // basis): consecutive compact indices then sit at consecutive positions of
+  // every term holding them, so the term sweep writes each term contiguously
+  // and the reduce's reads of neighbouring rows share cache lines.
   h.MB.resize(h.off[h.nterms]);
+  h.mbd.resize(h.off[h.nterms]);
   {
     std::vector<uint8_t> n(D);
     std::vector<int> nb(D);
@@ -252,17 +258,25 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
           n[i] = 0;
         }
       }
+      for (int i = 0; i < D; ++i) n[i] = 0;
+      for (int64_t s = h.off[t]; s < h.off[t + 1]; ++s) {
+        h.mbd[s] = (int32_t)rank(n.data());
+        for (int i = D - 1; i >= 0; --i) {  // mode D fastest
+          if (++n[i] < nb[i]) break;
+          n[i] = 0;
+        }
+      }
     }
   }
 
-  // ---- inverse mapping (CSR over compact indices, positions ascending) ---
+  // ---- inverse of the device mapping (CSR over compact indices) ----------
   h.inv_ptr.assign(h.ncs + 1, 0);
-  for (int32_t cs : h.MB) h.inv_ptr[cs + 1]++;
+  for (int32_t cs : h.mbd) h.inv_ptr[cs + 1]++;
   for (int64_t i = 0; i < h.ncs; ++i) h.inv_ptr[i + 1] += h.inv_ptr[i];
-  h.inv_col.resize(h.MB.size());
+  h.inv_col.resize(h.mbd.size());
   {
     std::vector<int32_t> fill(h.inv_ptr.begin(), h.inv_ptr.end() - 1);
-    for (size_t s = 0; s < h.MB.size(); ++s) h.inv_col[fill[h.MB[s]]++] = (int32_t)s;
+    for (size_t s = 0; s < h.mbd.size(); ++s) h.inv_col[fill[h.mbd[s]]++] = (int32_t)s;
   }
 
   // ---- exact diagonal harmonic part on the compact basis ----------------
@@ -328,10 +342,13 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
     const uint8_t *lv = &h.lev[size_t(t) * D];
     std::vector<int> act, zero;
     int64_t glit = 1;
-    for (int i = 0; i < D; ++i) {
+    // active modes in decreasing mode id: the first is the fastest index of
+    // the device position order
+    for (int i = D - 1; i >= 0; --i) {
       glit *= size_map(h.nqA, h.nqB, lv[i]);
       if (size_map(h.nbA, h.nbB, lv[i]) > 1) act.push_back(i); else zero.push_back(i);
     }
+    std::reverse(zero.begin(), zero.end());   // the level-0 sums below take zero ascending
     if ((int)act.size() > kMaxActive) { *err = "a term has more than 8 active modes"; return SG_EINVAL; }
     T.off = (int32_t)h.off[t];
     T.na = (int32_t)act.size();
@@ -360,9 +377,11 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
     double *prr = pr + 2 * kMaxPairs;
     for (size_t q = 0; q < act.size(); ++q)
       for (size_t r = q + 1; r < act.size(); ++r) {
+        // act[q] > act[r]: c is symmetric; k_ij Q_i^2 Q_j (i < j) is the
+        // coefficient of x_r^2 x_q here
         const int pi = pair_index((int)q, (int)r);
-        pr[2 * pi] = h.c[(size_t)act[q] * D + act[r]];
-        pr[2 * pi + 1] = h.k[(size_t)act[q] * D + act[r]];
+        pr[2 * pi] = h.c[(size_t)act[r] * D + act[q]];
+        pr[2 * pi + 1] = h.k[(size_t)act[r] * D + act[q]];
         prr[2 * pi] = r32(pr[2 * pi]);
         prr[2 * pi + 1] = r32(pr[2 * pi + 1]);
       }

@@ -36,10 +36,12 @@ def _mix():
 
 
 def _alone(sg, inst, dt, nsteps, lo, hi, prec, check_every=0):
+    # norm-drift gate: FP64 rounding, or the mixed path's 1e-6 bar
+    tol = 1e-8 if prec == sg.SG_FP64 else 1e-6
     with sg.Problem.from_instance(inst) as P:
         psi = empty(P.n_cs)
         sg.sg_init_gaussian(P.handle, inst.shift, psi)
-        status, st, _, _ = sg.sg_propagate_chebyshev(P.handle, psi, dt, nsteps, lo, hi,
+        status, st, _, _ = sg.sg_propagate_chebyshev(P.handle, psi, dt, nsteps, lo, hi, tol=tol,
                                                      precision=prec, check_every=check_every)
         assert status == sg.SG_OK
         return to_host(psi), st
