@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -28,21 +29,25 @@ __host__ __device__ constexpr int pair_index(int q, int r) {  // q < r < kMaxAct
   return q * (2 * kMaxActive - q - 1) / 2 + (r - q - 1);
 }
 
+// The first kTermHdrDwords dwords (the header) are what the in-place sweep
+// reads; a wavefront loads them with one vector load and reads fields from
+// lanes.
 struct alignas(16) TermDev {
   int32_t off;       // start of the term in the term-major layout (N_s)
   int32_t nbasis;    // prod over active modes of nb
   int32_t ngrid;     // prod over active modes of nq
   int32_t na;        // number of active modes
-  int32_t lev[kMaxActive];  // levels of the active modes, increasing mode id
-  int32_t mode[kMaxActive]; // their mode ids (32-bit: read with scalar loads)
+  int32_t lev[kMaxActive];  // levels of the active modes, decreasing mode id
   int32_t nb[kMaxActive];   // per active mode: basis size
   int32_t nq[kMaxActive];   //   grid size
-  int32_t bt[kMaxActive];   //   offsets of its level's tables in the table array
+  float rcp_nq[kMaxActive]; //   1/nq for fast index division
+  double coeff;             // D_l
+  // ---- end of header ----
+  int32_t mode[kMaxActive]; // mode ids of the active modes
+  int32_t bt[kMaxActive];   // offsets of each level's tables in the table array
   int32_t wt[kMaxActive];
   int32_t kg[kMaxActive];
   int32_t xo[kMaxActive];
-  float rcp_nq[kMaxActive]; //   1/nq for fast index division
-  double coeff;             // D_l
   // Effective-potential coefficients in three variants (kPot*): the FP64
   // path; the mixed path (no separable harmonic part); the mixed path's
   // values rounded to FP32 (held in FP64), for instances whose FP64 terms
@@ -53,6 +58,11 @@ struct alignas(16) TermDev {
   double kin[kMaxActive];          // -1/2 omega_p (kinetic prefactor)
 };
 constexpr int kPotFull = 0, kPotSplit = 1, kPotSplitRounded = 2;
+constexpr int kTermHdrDwords = 38;
+static_assert(offsetof(TermDev, coeff) == 4 * (kTermHdrDwords - 2), "term header layout");
+static_assert(offsetof(TermDev, lev) == 16 && offsetof(TermDev, nb) == 48 &&
+                  offsetof(TermDev, nq) == 80 && offsetof(TermDev, rcp_nq) == 112,
+              "term header layout");
 // Per-term coefficient block of the split coupling potential (exact and
 // FP32-rounded variants), which an in-place term copies into LDS next to its
 // grid buffer:  [0] c0, [1] alpha_0, [2] beta_0, [2+q] alpha_q, [9+q] beta_q,

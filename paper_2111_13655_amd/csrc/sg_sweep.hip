@@ -802,6 +802,31 @@ __device__ __forceinline__ void run_term(const TermCtx &a, cptr<TermDev> T, P ba
 // the outputs over the inputs.  Matrix rows are read one row ahead.  Outputs
 // are the same FMA chains, in the same order, as in the ping-pong form.
 // ---------------------------------------------------------------------------
+// The term record's header held across a wavefront: lane i has dword i.
+// Fields are read with v_readlane (no memory access after the one load).
+struct TermHdr {
+  uint32_t v;
+  __device__ __forceinline__ int i32(int idx) const {
+    return (int)__builtin_amdgcn_readlane((int)v, idx);
+  }
+  __device__ __forceinline__ int off() const { return i32(0); }
+  __device__ __forceinline__ int nbasis() const { return i32(1); }
+  __device__ __forceinline__ int ngrid() const { return i32(2); }
+  __device__ __forceinline__ int na() const { return i32(3); }
+  __device__ __forceinline__ int lev(int p) const { return i32(4 + p); }
+  __device__ __forceinline__ int nb(int p) const { return i32(12 + p); }
+  __device__ __forceinline__ int nq(int p) const { return i32(20 + p); }
+  __device__ __forceinline__ float rcp_nq(int p) const { return __int_as_float(i32(28 + p)); }
+  __device__ __forceinline__ double coeff() const {
+    return __hiloint2double(i32(37), i32(36));
+  }
+};
+__device__ __forceinline__ TermHdr load_hdr(cptr<TermDev> T) {
+  const int lane = threadIdx.x & 63;
+  const glb_p<const uint32_t> w = (glb_p<const uint32_t>)(const TermDev *)T;
+  return TermHdr{w[lane < kTermHdrDwords ? lane : 0]};
+}
+
 template <typename R, int NI>
 __device__ __forceinline__ void ld_row(lds_p<const R> M, int u, R (&r)[NI]) {
 #pragma unroll
@@ -971,13 +996,13 @@ __device__ __forceinline__ void g2b_ip(lds_p<typename Cx<R>::T> in, Out o, lds_p
 // The split coupling potential in place (fibers along mode 0; nodes from the
 // LDS tables).  Same arithmetic as potential_fixed without the kinetic part.
 template <typename G, typename R, int NQ>
-__device__ __forceinline__ void potential_ip(const TermCtx &a, cptr<TermDev> T,
+__device__ __forceinline__ void potential_ip(const TermCtx &a, const TermHdr &T,
                                              lds_p<typename Cx<R>::T> buf, int nfib,
                                              lds_p<const R> lt, lds_p<const R> cf) {
   typedef typename Cx<R>::T C;
   constexpr int FPT = NQ <= 8 ? 2 : 1;
-  const int na = T->na;
-  const int l0 = T->lev[0];
+  const int na = T.na();
+  const int l0 = T.lev(0);
   const lds_p<const R> x0 = lt + std_table_base(l0) + 2 * (2 * l0 + 1) * (2 * l0 + 2);
   const R c0 = cf[0];
   const R al0 = cf[1];
@@ -999,9 +1024,9 @@ __device__ __forceinline__ void potential_ip(const TermCtx &a, cptr<TermDev> T,
 #pragma unroll
     for (int q = 1; q < kMaxActive; ++q) {
       if (q < na) {
-        const float rq = T->rcp_nq[q];
-        const int nq = T->nq[q];
-        const int lq = T->lev[q];
+        const float rq = T.rcp_nq(q);
+        const int nq = T.nq(q);
+        const int lq = T.lev(q);
         const lds_p<const R> xn = lt + std_table_base(lq) + 2 * (2 * lq + 1) * (2 * lq + 2);
 #pragma unroll
         for (int j = 0; j < FPT; ++j) {
@@ -1084,21 +1109,21 @@ __device__ __forceinline__ void contract_ip_level(int kind, int level,
 // Alg. 1 for one term of the split operator in place: gather + basis -> grid,
 // the coupling potential pointwise, grid -> basis, D_l * result to HBM.
 template <typename G, typename R>
-__device__ __forceinline__ void run_term_inplace(const TermCtx &a, cptr<TermDev> T,
+__device__ __forceinline__ void run_term_inplace(const TermCtx &a, const TermHdr &T,
                                                  lds_p<typename Cx<R>::T> buf,
                                                  lds_p<const R> lt) {
-  const int na = T->na;
-  const int nbasis = T->nbasis;
-  const int ngrid = T->ngrid;
-  const int off = T->off;
-  const double cf = T->coeff;
+  const int na = T.na();
+  const int nbasis = T.nbasis();
+  const int ngrid = T.ngrid();
+  const int off = T.off();
+  const double cf = T.coeff();
   // the coefficient block, into LDS after the grid buffer (published by the
   // sync after the gather)
   const lds_p<R> coef = (lds_p<R>)(buf + ngrid);
   for (int i = G::tid(); i < kCoefUsed; i += G::N) coef[i] = (R)a.pcoef[i];
   {
-    const int l0 = T->lev[0];
-    const int nb0 = T->nb[0], nq0 = T->nq[0];
+    const int l0 = T.lev(0);
+    const int nb0 = T.nb(0), nq0 = T.nq(0);
     const lds_p<const R> M0 = lt + std_table_base(l0);
 #define SG_GCASE(L_, NB_, NQ_)                                                   \
   case L_: gather_ip<G, R, NB_, NQ_>(a, off, nbasis / NB_, M0, buf); break;
@@ -1108,17 +1133,17 @@ __device__ __forceinline__ void run_term_inplace(const TermCtx &a, cptr<TermDev>
     int stride = nq0;
     int nouter = nbasis / nb0;
     for (int p = 1; p < na; ++p) {
-      nouter /= T->nb[p];
-      contract_ip_level<G, R>(0, T->lev[p], buf, lt, stride, nouter);
+      nouter /= T.nb(p);
+      contract_ip_level<G, R>(0, T.lev(p), buf, lt, stride, nouter);
       G::sync();
-      stride *= T->nq[p];
+      stride *= T.nq(p);
     }
   }
   {
-    const int nfib = ngrid / T->nq[0];
+    const int nfib = ngrid / T.nq(0);
 #define SG_PIPCASE(L_, NB_, NQ_)                                                 \
   case L_: potential_ip<G, R, NQ_>(a, T, buf, nfib, lt, coef); break;
-    switch (T->lev[0]) { SG_LEVELS(SG_PIPCASE) default: break; }
+    switch (T.lev(0)) { SG_LEVELS(SG_PIPCASE) default: break; }
 #undef SG_PIPCASE
     G::sync();
   }
@@ -1126,13 +1151,13 @@ __device__ __forceinline__ void run_term_inplace(const TermCtx &a, cptr<TermDev>
     int stride = 1;
     int nouter = ngrid;
     for (int p = 0; p < na - 1; ++p) {
-      nouter /= T->nq[p];
-      contract_ip_level<G, R>(2, T->lev[p], buf, lt, stride, nouter);
+      nouter /= T.nq(p);
+      contract_ip_level<G, R>(2, T.lev(p), buf, lt, stride, nouter);
       G::sync();
-      stride *= T->nb[p];
+      stride *= T.nb(p);
     }
     const int p = na - 1;
-    const int lp = T->lev[p];
+    const int lp = T.lev(p);
     const lds_p<const R> Mw = lt + std_table_base(lp) + (2 * lp + 1) * (2 * lp + 2);
 #define SG_SCASE(L_, NB_, NQ_)                                                   \
   case L_: g2b_ip<G, R, NQ_, NB_>(buf, Out{a.tm + off}, Mw, cf, stride); break;
@@ -1154,7 +1179,7 @@ __device__ __forceinline__ void run_any(const TermCtx &a, cptr<TermDev> T, P bas
     return;
   }
   if (inplace)
-    run_term_inplace<G, R>(a, T, (lds_p<typename Cx<R>::T>)base,
+    run_term_inplace<G, R>(a, load_hdr(T), (lds_p<typename Cx<R>::T>)base,
                            (lds_p<const R>)(lds_raw + a.lt_off));
   else run_term<G, R, P>(a, T, base, T->ngrid);
 }
