@@ -109,6 +109,136 @@ def cpu_baseline(inst, info, budget_s: float):
             "grid_pts_per_s_literal": rate * info["grid_literal"]}
 
 
+def _throughput(sg, P, prec, reps):
+    """Back-to-back applies between two events on the current stream: applies/s."""
+    import torch
+    n = P.n_cs
+    x = torch.zeros(n, dtype=torch.complex128, device="cuda")
+    x[0] = 1.0
+    y = torch.empty_like(x)
+    for _ in range(3):
+        P.apply(x, y, prec)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        P.apply(x, y, prec)
+    e1.record()
+    e1.synchronize()
+    return reps / (e0.elapsed_time(e1) * 1e-3)
+
+
+def mixed_vs_fp64(sg, reps=20):
+    """(D, L) = (12, 6): the precision autotuner's choice at the 1e-6 bar, its
+    measured error against the FP64 apply, and both throughputs."""
+    import torch
+    import sg_inputs
+    inst = sg_inputs.config2()
+    P = sg.Problem.from_instance(inst)
+    n = P.n_cs
+    psi = torch.empty(n, dtype=torch.complex128, device="cuda")
+    sg.sg_init_gaussian(P.handle, inst.shift, psi)
+    thr, err_tuned = sg.sg_tune_mixed(P.handle, psi, 1e-6, 3)
+    # error on an independent random state
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x = torch.from_numpy(v / np.linalg.norm(v)).to("cuda")
+    y64, y32 = torch.empty_like(x), torch.empty_like(x)
+    P.apply(x, y64, sg.SG_FP64)
+    P.apply(x, y32, sg.SG_MIXED)
+    torch.cuda.synchronize()
+    err = float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64))
+    t64 = _throughput(sg, P, sg.SG_FP64, reps)
+    t32 = _throughput(sg, P, sg.SG_MIXED, reps)
+    info = sg.sg_problem_info(P.handle)
+    P.close()
+    return {"workload": "D=12 L=6 coupled anharmonic (same family), one apply",
+            "fp64_applies_per_s": t64, "mixed_applies_per_s": t32, "speedup": t32 / t64,
+            "mixed_threshold": thr, "rel_err_vs_fp64_tuning_state": err_tuned,
+            "rel_err_vs_fp64_random_state": err, "tol": 1e-6,
+            "grid_pts_per_s_active_mixed": t32 * info["grid_active"]}
+
+
+def batched(sg, steps):
+    """64 independent instances (D ~ U{4..10}, L ~ U{4..7}) advanced together
+    in mixed precision: instance-applies/s over a bounded number of steps."""
+    import torch
+    import sg_inputs
+    insts = sg_inputs.config3()
+    probs = [sg.Problem.from_instance(i) for i in insts]
+    psis, lo, hi = [], [], []
+    for P, inst in zip(probs, insts):
+        x = torch.empty(P.n_cs, dtype=torch.complex128, device="cuda")
+        sg.sg_init_gaussian(P.handle, inst.shift, x)
+        psis.append(x)
+        a, b = sg.sg_spectral_bounds(P.handle, 40)
+        lo.append(a)
+        hi.append(b)
+    b = sg.sg_batch_create([P.handle for P in probs])
+    dts = [i.meta["dt"] for i in insts]
+    sg.sg_batch_propagate(b, psis, dts, 1, lo, hi, tol=1e-6, precision=sg.SG_MIXED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, st = sg.sg_batch_propagate(b, psis, dts, steps, lo, hi, tol=1e-6,
+                                       precision=sg.SG_MIXED, check_every=steps,
+                                       use_graph=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    applies = sum(s["applies"] for s in st)
+    grid = sum(P.info["grid_active"] * s["applies"] for P, s in zip(probs, st))
+    sg.sg_batch_free(b)
+    for P in probs:
+        P.close()
+    return {"workload": "64 instances, D ~ U{4..10}, L ~ U{4..7}, mixed, dt = 0.05",
+            "steps": steps, "status": int(status), "seconds": dt,
+            "instance_applies_per_s": applies / dt, "grid_pts_per_s_active": grid / dt,
+            "ms_per_batched_step": dt / steps * 1e3}
+
+
+def serve(sg, window_s, steps_scale):
+    """The Poisson request stream (20 req/s; D ~ U{3..20}, L ~ U{3..6} capped
+    so that N_s <= 5e7; steps ~ U{50..2000}) over its first window_s seconds,
+    every request's step count multiplied by steps_scale so that the sample
+    drains in bounded time.  Requests are submitted at their arrival times
+    and stay resident until done; latency is submit -> result."""
+    import sg_inputs
+    reqs = [r for r in sg_inputs.config4() if r.arrival_s < window_s]
+    srv = sg.sg_serve_create(max_slots=64, precision=sg.SG_MIXED, check_every=100, tol=1e-6,
+                             compile_threads=8)
+    tickets = []
+    t0 = time.perf_counter()
+    for r in reqs:
+        inst = r.inst
+        L = inst.L
+        while L > 0 and sg.sg_count_sizes(inst.D, L)[1] > 5e7:
+            L -= 1
+        now = time.perf_counter() - t0
+        if r.arrival_s > now:
+            time.sleep(r.arrival_s - now)
+        nsteps = max(1, int(round(r.steps * steps_scale)))
+        tickets.append((sg.sg_serve_submit(srv, inst.D, L, inst.omega, inst.c, inst.k,
+                                           inst.shift, 0.05, nsteps), nsteps))
+    lat, applies, ok, statuses = [], 0, 0, {}
+    for t, _ in tickets:
+        while True:
+            res = sg.sg_serve_poll(srv, t)
+            if res is not None:
+                break
+            time.sleep(0.001)
+        lat.append(res["t_done"] - res["t_submit"])
+        applies += res["stats"]["applies"]
+        ok += res["status"] == sg.SG_OK
+        statuses[str(res["status"])] = statuses.get(str(res["status"]), 0) + 1
+    wall = time.perf_counter() - t0
+    sg.sg_serve_destroy(srv)
+    lat = np.array(lat)
+    return {"workload": "Poisson 20 req/s, D ~ U{3..20}, L ~ U{3..6} (N_s <= 5e7), mixed",
+            "window_s": window_s, "steps_scale": steps_scale, "requests": len(reqs),
+            "completed_ok": int(ok), "statuses": statuses, "wall_s": wall, "requests_per_s": len(reqs) / wall,
+            "instance_applies_per_s": applies / wall,
+            "latency_s_p50": float(np.percentile(lat, 50)),
+            "latency_s_p99": float(np.percentile(lat, 99))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +249,11 @@ def main():
     ap.add_argument("--latency-samples", type=int, default=1000)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed-vs-FP64, batched and serving sections")
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--serve-window", type=float, default=3.0)
+    ap.add_argument("--serve-steps-scale", type=float, default=0.05)
     ap.add_argument("--grid-kinetic", action="store_true",
                     help="SG_FP64 in the literal form (kinetic matrices on every term grid) "
                          "instead of the default exact diagonal split")
@@ -250,10 +385,20 @@ def main():
                      "kernel": "sweep_kernel",
                      "flops_per_launch": sweep_flops},
     }
+    P.close()
+    if not args.no_extras:
+        log("[bench] mixed vs fp64 (D=12, L=6)")
+        out["mixed_vs_fp64"] = mixed_vs_fp64(sg)
+        log(f"[bench] {out['mixed_vs_fp64']}")
+        log("[bench] batched (64 instances)")
+        out["batched"] = batched(sg, args.batch_steps)
+        log(f"[bench] {out['batched']}")
+        log("[bench] serving")
+        out["serve"] = serve(sg, args.serve_window, args.serve_steps_scale)
+        log(f"[bench] {out['serve']}")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline")
         out["cpu_baseline"] = cpu_baseline(inst, info, args.cpu_budget)
-    P.close()
     print(json.dumps(out), flush=True)
 
 

@@ -238,6 +238,22 @@ struct Plan;
 
 }  // namespace sg
 
+namespace sg {
+// A problem's own term packs and reduce items, kept so that plans over many
+// problems (batches, the server) concatenate them instead of packing every
+// term again.  Built for a fixed mixed threshold and operator form.
+struct PackCache {
+  bool valid = false;
+  int32_t thr = -1, grid_kinetic = -1;
+  std::vector<PackDev> packs[kPackSets];   // inst = 0
+  std::vector<double> cost[kPackSets];
+  int32_t pack_lds[kPackSets] = {0, 0, 0, 0};   // largest pack, tables excluded
+  int64_t scratch[kPackSets] = {0, 0, 0, 0};    // scratch bytes of each set
+  std::vector<RedItem> items;              // inst = 0
+  bool inst32 = false;
+};
+}  // namespace sg
+
 // Device-resident state of a built problem.
 struct sg_problem {
   sg::Compiled h;
@@ -261,6 +277,7 @@ struct sg_problem {
   double *d_partials = nullptr;    // [2 * n_items] reduction partials
   double *d_cheb_a = nullptr;      // [kMaxChebTerms] series coefficients
   int grid_kinetic = 0;            // 1: SG_FP64 applies the kinetic matrices on the grid
+  sg::PackCache pcache;            // packs for multi-problem plans
   double *d_result = nullptr;      // 8 doubles
   double *h_result = nullptr;      // pinned host mirror of d_result
   int64_t device_bytes = 0;

@@ -76,8 +76,12 @@ Cand make_cand(int32_t inst, int32_t term, const Compiled &h, bool split, int el
   return c;
 }
 
+// dense: as few wave packs as the terms fill (plans over many problems);
+// otherwise enough packs to give every compute unit work.  costs (nullable)
+// receives the estimated cost of each pack appended to out.
 void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vector<PackDev> *out,
-              PackSet *set, int64_t *scratch_bytes) {
+              PackSet *set, int64_t *scratch_bytes, bool dense = false,
+              std::vector<double> *costs = nullptr) {
   set->first = (int32_t)out->size();
   set->count = 0;
   set->lds_bytes = 0;
@@ -96,7 +100,7 @@ void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vect
   const int64_t nsmall = (int64_t)small.size();
   int64_t nbins = (nsmall + kPackTerms - 1) / kPackTerms;
   const int64_t want = (int64_t)kComputeUnits * per_cu - (int64_t)big.size();
-  nbins = std::max<int64_t>(nbins, std::min<int64_t>(nsmall, want));
+  if (!dense) nbins = std::max<int64_t>(nbins, std::min<int64_t>(nsmall, want));
   struct Bin {
     double load;
     int64_t id;
@@ -176,6 +180,7 @@ void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vect
       *scratch_bytes += (2 * c.ngrid * elem + 255) & ~(int64_t)255;
     }
     out->push_back(pk);
+    if (costs) costs->push_back(c.cost);
   }
   std::vector<int64_t> order(bins.size());
   for (size_t i = 0; i < bins.size(); ++i) order[i] = (int64_t)i;
@@ -184,6 +189,7 @@ void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vect
   for (int64_t i : order) {
     if (bins[i].n == 0) continue;
     out->push_back(bins[i]);
+    if (costs) costs->push_back(bin_load[i]);
     lds = std::max<int>(lds, (int)bin_bytes[i]);
   }
   set->count = (int32_t)(out->size() - set->first);
@@ -241,6 +247,57 @@ void inst_from_problem(const sg_problem *p, InstDev *d) {
   d->active = 1;
 }
 
+namespace {
+
+// LDS bytes of the standard tables up to level 7 (the largest a cached pack
+// set leaves room for).
+constexpr int kTabMax64 = ((std_table_base(8) * 8 + 15) / 16) * 16;
+constexpr int kTabMax32 = ((std_table_base(8) * 4 + 15) / 16) * 16;
+
+void reduce_items(const Compiled &h, int32_t inst, std::vector<RedItem> *items) {
+  for (int64_t q = 0; q < h.n_long_rows; ++q) items->push_back({inst, (int32_t)q, (int32_t)q, 0});
+  const int64_t nshort = h.ncs - h.n_long_rows;
+  int32_t local = (int32_t)h.n_long_rows;
+  for (int64_t q = 0; q < nshort; q += kShortLanes)
+    items->push_back({inst, (int32_t)(h.n_long_rows + q), local++, 0});
+}
+
+void build_cache(sg_problem *p) {
+  PackCache &c = p->pcache;
+  const Compiled &h = p->h;
+  if (c.valid && c.thr == h.mixed_max_fp32_coeff && c.grid_kinetic == p->grid_kinetic) return;
+  std::vector<Cand> cg64, cs64, m64, m32;
+  c.inst32 = false;
+  for (int64_t t = 0; t < h.nterms; ++t) {
+    cg64.push_back(make_cand(0, (int32_t)t, h, false, 16));
+    cs64.push_back(make_cand(0, (int32_t)t, h, true, 16));
+    if (std::abs(h.coeff[t]) <= h.mixed_max_fp32_coeff) {
+      m32.push_back(make_cand(0, (int32_t)t, h, true, 8));
+      c.inst32 = true;
+    } else {
+      m64.push_back(make_cand(0, (int32_t)t, h, true, 16));
+    }
+  }
+  const std::vector<Cand> *cs[kPackSets] = {&cg64, &cs64, &m64, &m32};
+  const int elem[kPackSets] = {16, 16, 16, 8};
+  const int tab[kPackSets] = {0, kTabMax64, 2 * kTabMax64, kTabMax32};
+  for (int k = 0; k < kPackSets; ++k) {
+    c.packs[k].clear();
+    c.cost[k].clear();
+    PackSet ps;
+    c.scratch[k] = 0;
+    pack_set(*cs[k], elem[k], tab[k], &c.packs[k], &ps, &c.scratch[k], true, &c.cost[k]);
+    c.pack_lds[k] = ps.count ? ps.lds_bytes - ps.tab_bytes : 0;
+  }
+  c.items.clear();
+  reduce_items(h, 0, &c.items);
+  c.thr = h.mixed_max_fp32_coeff;
+  c.grid_kinetic = p->grid_kinetic;
+  c.valid = true;
+}
+
+}  // namespace
+
 sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::string *err) {
   pl->probs = probs;
   pl->inst.assign(probs.size(), InstDev{});
@@ -249,32 +306,36 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
   pl->scratch_bytes = 0;
   pl->any32 = false;
   pl->fp64_split = false;
+  const bool multi = probs.size() > 1;
   std::vector<Cand> cg64, cs64, m64, m32;
   bool split_all = true;
   for (size_t i = 0; i < probs.size(); ++i) {
-    const sg_problem *p = probs[i];
+    sg_problem *p = probs[i];
     const Compiled &h = p->h;
     inst_from_problem(p, &pl->inst[i]);
     split_all = split_all && h.split_exact && !p->grid_kinetic;
     bool inst32 = false;
-    for (int64_t t = 0; t < h.nterms; ++t) {
-      cg64.push_back(make_cand((int32_t)i, (int32_t)t, h, false, 16));
-      cs64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16));
-      if (std::abs(h.coeff[t]) <= h.mixed_max_fp32_coeff) {
-        m32.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 8));
-        inst32 = true;
-      } else {
-        m64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16));
+    if (multi) {
+      build_cache(p);
+      inst32 = p->pcache.inst32;
+      const size_t first = pl->items.size();
+      pl->items.insert(pl->items.end(), p->pcache.items.begin(), p->pcache.items.end());
+      for (size_t q = first; q < pl->items.size(); ++q) pl->items[q].inst = (int32_t)i;
+    } else {
+      for (int64_t t = 0; t < h.nterms; ++t) {
+        cg64.push_back(make_cand((int32_t)i, (int32_t)t, h, false, 16));
+        cs64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16));
+        if (std::abs(h.coeff[t]) <= h.mixed_max_fp32_coeff) {
+          m32.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 8));
+          inst32 = true;
+        } else {
+          m64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16));
+        }
       }
+      reduce_items(h, (int32_t)i, &pl->items);
     }
     pl->inst[i].round32 = inst32 ? 1 : 0;
     pl->any32 = pl->any32 || inst32;
-    for (int64_t q = 0; q < h.n_long_rows; ++q)
-      pl->items.push_back({(int32_t)i, (int32_t)q, (int32_t)q, 0});
-    const int64_t nshort = h.ncs - h.n_long_rows;
-    int32_t local = (int32_t)h.n_long_rows;
-    for (int64_t q = 0; q < nshort; q += kShortLanes)
-      pl->items.push_back({(int32_t)i, (int32_t)(h.n_long_rows + q), local++, 0});
   }
   pl->fp64_split = split_all;
   // standard-map tables (identical for every such instance) for LDS
@@ -316,14 +377,49 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
   const int64_t E = (int64_t)pl->stab64.size();
   const int t64 = (int)((E * 8 + 15) & ~(int64_t)15);
   const int t32 = (int)((E * 4 + 15) & ~(int64_t)15);
-  // the set SG_FP64 launches do not use stays empty
-  if (split_all) cg64.clear(); else cs64.clear();
-  pack_set(cg64, 16, 0, &pl->packs, &pl->sets[kSetGrid64], &pl->scratch_bytes);
-  pack_set(cs64, 16, t64, &pl->packs, &pl->sets[kSetSplit64], &pl->scratch_bytes);
-  pack_set(m64, 16, pl->any_round32 ? 2 * t64 : t64, &pl->packs, &pl->sets[kSetMixed64],
-           &pl->scratch_bytes);
-  pack_set(m32, 8, t32, &pl->packs, &pl->sets[kSetMixed32], &pl->scratch_bytes);
-  (void)err;
+  const int tabs[kPackSets] = {0, t64, pl->any_round32 ? 2 * t64 : t64, t32};
+  if (!multi) {
+    // the set SG_FP64 launches do not use stays empty
+    if (split_all) cg64.clear(); else cs64.clear();
+    pack_set(cg64, 16, tabs[kSetGrid64], &pl->packs, &pl->sets[kSetGrid64], &pl->scratch_bytes);
+    pack_set(cs64, 16, tabs[kSetSplit64], &pl->packs, &pl->sets[kSetSplit64], &pl->scratch_bytes);
+    pack_set(m64, 16, tabs[kSetMixed64], &pl->packs, &pl->sets[kSetMixed64], &pl->scratch_bytes);
+    pack_set(m32, 8, tabs[kSetMixed32], &pl->packs, &pl->sets[kSetMixed32], &pl->scratch_bytes);
+    return SG_OK;
+  }
+  // concatenate the problems' cached packs, most expensive first
+  for (int k = 0; k < kPackSets; ++k) {
+    PackSet &set = pl->sets[k];
+    set.first = (int32_t)pl->packs.size();
+    set.count = 0;
+    set.tab_bytes = 0;
+    set.lds_bytes = 0;
+    if ((k == kSetGrid64 && split_all) || (k == kSetSplit64 && !split_all)) continue;
+    std::vector<std::pair<double, PackDev>> all;
+    int pack_lds = 0;
+    for (size_t i = 0; i < probs.size(); ++i) {
+      const PackCache &c = probs[i]->pcache;
+      const int64_t base = pl->scratch_bytes;
+      for (size_t q = 0; q < c.packs[k].size(); ++q) {
+        PackDev pk = c.packs[k][q];
+        for (int w = 0; w < pk.n; ++w) pk.inst[w] = (int32_t)i;
+        if (pk.block == kPackBlockScratch) pk.scratch_off += base;
+        all.push_back({c.cost[k][q], pk});
+      }
+      pl->scratch_bytes += c.scratch[k];
+      pack_lds = std::max(pack_lds, c.pack_lds[k]);
+    }
+    std::stable_sort(all.begin(), all.end(),
+                     [](const std::pair<double, PackDev> &a, const std::pair<double, PackDev> &b) {
+                       return a.first > b.first;
+                     });
+    for (const auto &x : all) pl->packs.push_back(x.second);
+    set.count = (int32_t)all.size();
+    if (set.count) {
+      set.tab_bytes = tabs[k];
+      set.lds_bytes = tabs[k] + pack_lds;
+    }
+  }
   return SG_OK;
 }
 
