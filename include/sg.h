@@ -298,6 +298,41 @@ sg_status sg_set_operator_form(sg_problem *p, int32_t grid_kinetic);
 sg_status sg_tune_mixed(sg_problem *p, const void *psi, double tol, int32_t reps,
                         int32_t *chosen, double *chosen_error, void *stream);
 
+/* Lowest eigenpairs of H_S by block Davidson: the method the paper uses to
+ * converge stationary states (Sec. 3, flowchart text), here on sg_apply_H
+ * (FP64).  nev eigenpairs; max_basis (2 nev .. 256) subspace vectors before a
+ * restart from the Ritz block; at most max_iter iterations; converged when
+ * every residual norm ||H x - theta x|| (x normalised) is <= tol.  guess:
+ * nullable device block of nguess complex128[N_cs] vectors to start from
+ * (e.g. a lower-level solution embedded with sg_embed_basis); the start block
+ * is the guess, the unit vectors at the nev lowest harmonic energies and one
+ * fixed pseudo-random vector (reaching every symmetry sector of H), less the
+ * vectors the earlier ones span.  nev buffer Ritz pairs are iterated beside
+ * the wanted ones.  Outputs:
+ * evals[nev] (host, ascending); evecs (nullable device complex128[nev][N_cs],
+ * orthonormal, real-valued); resnorms[nev] (nullable host); stats (nullable).
+ * Returns SG_ETOL (outputs still written) when not every pair converged.
+ * Allocates its workspace (2 max_basis + 2 nev vectors); synchronises
+ * `stream`. */
+typedef struct {
+  int32_t iterations;
+  int32_t applies;            /* H_S applications */
+  int32_t restarts;
+  int32_t converged;          /* pairs with residual <= tol */
+} sg_eig_stats;
+sg_status sg_eigensolve(sg_problem *p, int32_t nev, int32_t max_basis, int32_t max_iter,
+                        double tol, const void *guess, int32_t nguess, double *evals,
+                        void *evecs, double *resnorms, sg_eig_stats *stats, void *stream);
+
+/* The paper's low-level start (Sec. 4 example run: a wave-function guess from
+ * a diagonalisation at low L, then Davidson at the target L): copies a state
+ * of problem `from` into the compact basis of `to` (same D and basis size
+ * map, from->L <= to->L; the lower-level compact basis is a subset), zero
+ * elsewhere.  x: device complex128[N_cs(from)]; y: device
+ * complex128[N_cs(to)].  Synchronises `stream`. */
+sg_status sg_embed_basis(const sg_problem *from, const sg_problem *to, const void *x, void *y,
+                         void *stream);
+
 /* Per-kernel timing for measurement.  sg_set_timing(p, 1) resets the
  * counters and attaches a pair of HIP events to every term-sweep and reduce
  * launch made through this handle (hipExtLaunchKernel: the events take the

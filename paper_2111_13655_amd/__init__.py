@@ -24,7 +24,8 @@ __all__ = [
     "sg_free", "sg_problem_info", "sg_basis_indices", "sg_term_levels",
     "sg_mapping_table", "sg_init_gaussian", "sg_apply_H", "sg_spectral_bounds",
     "sg_propagate_chebyshev", "sg_set_timing", "sg_get_timing", "sg_set_mixed_threshold",
-    "sg_tune_mixed", "sg_set_operator_form", "sg_batch_create", "sg_batch_propagate", "sg_batch_free",
+    "sg_tune_mixed", "sg_set_operator_form", "sg_eigensolve", "sg_embed_basis",
+    "sg_batch_create", "sg_batch_propagate", "sg_batch_free",
     "ServeConfig", "sg_serve_create", "sg_serve_submit", "sg_serve_poll", "sg_serve_cancel",
     "sg_serve_counters", "sg_serve_destroy", "Problem",
 ]
@@ -99,6 +100,14 @@ class ServeConfig(ctypes.Structure):
                 ("compile_threads", ctypes.c_int32)]
 
 
+class EigStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("applies", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("converged", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("D", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("n_cs", ctypes.c_int64), ("psi_host", ctypes.c_void_p),
@@ -144,6 +153,12 @@ _SIGNATURES = {
                                           ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(PropStats), _P]),
     "sg_batch_free": (ctypes.c_int, [_P]),
+    "sg_eigensolve": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_double, _P, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_double), _P,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(EigStats),
+                                     _P]),
+    "sg_embed_basis": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "sg_serve_create": (ctypes.c_int, [ctypes.POINTER(ServeConfig), ctypes.POINTER(_P)]),
     "sg_serve_submit": (ctypes.c_int, [_P, ctypes.POINTER(ProblemDesc),
                                        ctypes.POINTER(ctypes.c_double), ctypes.c_double,
@@ -346,6 +361,41 @@ def sg_get_timing(h) -> dict:
     t = Timing()
     _check(lib().sg_get_timing(h, ctypes.byref(t)))
     return t.as_dict()
+
+
+def sg_eigensolve(h, nev: int, max_basis: int = 0, max_iter: int = 200, tol: float = 1e-9,
+                  guess=None, evecs=None, stream=None):
+    """Returns (status, eigenvalues, residual norms, stats).  guess: optional
+    device complex128 tensor [nguess, N_cs]; evecs: optional device complex128
+    tensor [nev, N_cs] that receives the eigenvectors."""
+    n_cs = sg_problem_info(h)["n_cs"]
+    if max_basis <= 0:
+        max_basis = min(max(4 * nev, 16), 256)
+    ev = np.zeros(nev)
+    rn = np.zeros(nev)
+    st = EigStats()
+    g, ng = None, 0
+    if guess is not None:
+        if guess.dim() != 2 or guess.shape[1] != n_cs:
+            raise ValueError("guess must be [nguess, N_cs]")
+        _vec_ptr(guess.reshape(-1), guess.numel(), "guess")
+        g, ng = ctypes.c_void_p(guess.data_ptr()), guess.shape[0]
+    out = None
+    if evecs is not None:
+        _vec_ptr(evecs.reshape(-1), nev * n_cs, "evecs")
+        out = ctypes.c_void_p(evecs.data_ptr())
+    status = lib().sg_eigensolve(h, int(nev), int(max_basis), int(max_iter), float(tol), g, ng,
+                                 _dptr(ev), out, _dptr(rn), ctypes.byref(st), _stream_ptr(stream))
+    if status not in (SG_OK, SG_ETOL):
+        _check(status)
+    return status, ev, rn, st.as_dict()
+
+
+def sg_embed_basis(h_from, h_to, x, y, stream=None) -> None:
+    nf = sg_problem_info(h_from)["n_cs"]
+    nt = sg_problem_info(h_to)["n_cs"]
+    _check(lib().sg_embed_basis(h_from, h_to, _vec_ptr(x, nf, "x"), _vec_ptr(y, nt, "y"),
+                                _stream_ptr(stream)))
 
 
 def sg_batch_create(handles) -> ctypes.c_void_p:

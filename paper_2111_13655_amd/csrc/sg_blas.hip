@@ -1,0 +1,155 @@
+// Vector kernels of the eigensolver (gfx950): block inner products with a
+// fixed-order second stage (bitwise reproducible), block linear combinations,
+// the diagonal (Davidson) correction and the basis embedding of the
+// level-to-level restart.  All are HBM-bound streams over N_cs complex values.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "sg_internal.h"
+
+namespace sg {
+
+namespace {
+
+constexpr int kBlasThreads = 256;
+constexpr int kDotBlocks = 128;   // partial sums per inner product
+
+template <typename T> using glb_p = __attribute__((address_space(1))) T *;
+
+// partials[(j * kDotBlocks + b) * 2 + {0,1}] = sum over block b's share of
+// conj(V_j[i]) w[i]   (V_j = V + j * ld)
+__global__ __launch_bounds__(kBlasThreads) void multi_dot_kernel(const double2 *V, int64_t ld,
+                                                                 const double2 *w, int64_t n,
+                                                                 double *partials) {
+  __shared__ double s0[kBlasThreads], s1[kBlasThreads];
+  const int b = blockIdx.x, j = blockIdx.y;
+  const glb_p<const double2> v = (glb_p<const double2>)(V + (size_t)j * ld);
+  const glb_p<const double2> x = (glb_p<const double2>)w;
+  double re = 0.0, im = 0.0;
+  for (int64_t i = (int64_t)b * kBlasThreads + threadIdx.x; i < n;
+       i += (int64_t)kDotBlocks * kBlasThreads) {
+    const double vr = v[i].x, vi = v[i].y, xr = x[i].x, xi = x[i].y;
+    re += vr * xr + vi * xi;
+    im += vr * xi - vi * xr;
+  }
+  s0[threadIdx.x] = re;
+  s1[threadIdx.x] = im;
+  __syncthreads();
+  for (int s = kBlasThreads / 2; s >= 1; s >>= 1) {
+    if (threadIdx.x < s) {
+      s0[threadIdx.x] += s0[threadIdx.x + s];
+      s1[threadIdx.x] += s1[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[((size_t)j * kDotBlocks + b) * 2] = s0[0];
+    partials[((size_t)j * kDotBlocks + b) * 2 + 1] = s1[0];
+  }
+}
+
+// out[j] = sum_b partials[j][b], in block order (one thread per j)
+__global__ void multi_dot_finish(const double *partials, int m, double *out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  double re = 0.0, im = 0.0;
+  for (int b = 0; b < kDotBlocks; ++b) {
+    re += partials[((size_t)j * kDotBlocks + b) * 2];
+    im += partials[((size_t)j * kDotBlocks + b) * 2 + 1];
+  }
+  out[2 * j] = re;
+  out[2 * j + 1] = im;
+}
+
+// x[i] = beta x[i] + sum_j c_j V_j[i]   (c complex, j in order)
+__global__ __launch_bounds__(kBlasThreads) void multi_axpy_kernel(double2 *x, double beta,
+                                                                  const double2 *V, int64_t ld,
+                                                                  int m, const double *c,
+                                                                  int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlasThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlasThreads) {
+    // beta = 0 overwrites x (which may hold anything)
+    double re = beta == 0.0 ? 0.0 : beta * x[i].x, im = beta == 0.0 ? 0.0 : beta * x[i].y;
+    for (int j = 0; j < m; ++j) {
+      const double2 v = V[(size_t)j * ld + i];
+      const double cr = c[2 * j], ci = c[2 * j + 1];
+      re += cr * v.x - ci * v.y;
+      im += cr * v.y + ci * v.x;
+    }
+    x[i] = make_double2(re, im);
+  }
+}
+
+// t[i] = r[i] / (theta - d[i]), with |theta - d[i]| kept away from zero
+__global__ __launch_bounds__(kBlasThreads) void precondition_kernel(double2 *t, const double2 *r,
+                                                                    const double *d,
+                                                                    double theta, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlasThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlasThreads) {
+    double den = theta - d[i];
+    if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
+    t[i] = make_double2(r[i].x / den, r[i].y / den);
+  }
+}
+
+__global__ __launch_bounds__(kBlasThreads) void zero_kernel(double2 *y, int64_t ny) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlasThreads + threadIdx.x; i < ny;
+       i += (int64_t)gridDim.x * kBlasThreads)
+    y[i] = make_double2(0.0, 0.0);
+}
+
+__global__ __launch_bounds__(kBlasThreads) void scatter_kernel(const double2 *x,
+                                                               const int32_t *map, int64_t nx,
+                                                               double2 *y) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlasThreads + threadIdx.x; i < nx;
+       i += (int64_t)gridDim.x * kBlasThreads)
+    y[map[i]] = x[i];
+}
+
+int grid_for(int64_t n) {
+  const int64_t b = (n + kBlasThreads - 1) / kBlasThreads;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 4096));
+}
+
+}  // namespace
+
+int dot_partials_per_vector() { return kDotBlocks; }
+
+hipError_t launch_multi_dot(const double2 *V, int64_t ld, int m, const double2 *w, int64_t n,
+                            double *partials, double *out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, m), dim3(kBlasThreads), 0, s, V, ld, w, n,
+                     partials);
+  hipLaunchKernelGGL(multi_dot_finish, dim3((m + 63) / 64), dim3(64), 0, s,
+                     (const double *)partials, m, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_axpy(double2 *x, double beta, const double2 *V, int64_t ld, int m,
+                             const double *c, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid_for(n)), dim3(kBlasThreads), 0, s, x, beta, V,
+                     ld, m, c, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_precondition(double2 *t, const double2 *r, const double *d, double theta,
+                               int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(precondition_kernel, dim3(grid_for(n)), dim3(kBlasThreads), 0, s, t, r, d,
+                     theta, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(double2 *y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n)), dim3(kBlasThreads), 0, s, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_embed(const double2 *x, const int32_t *map, int64_t nx, double2 *y, int64_t ny,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for(ny)), dim3(kBlasThreads), 0, s, y, ny);
+  hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(nx)), dim3(kBlasThreads), 0, s, x, map, nx, y);
+  return hipGetLastError();
+}
+
+}  // namespace sg

@@ -361,6 +361,20 @@ hipError_t launch_dot(const sg_problem *p, const double2 *a, const double2 *b,
 hipError_t launch_axpby(int64_t n, double2 *y, const double2 *x, double a_re,
                         double a_im, double b, hipStream_t s);  // y = a x + b y
 
+// Vector kernels of the eigensolver (sg_blas.hip).  out[2j..2j+1] =
+// sum_i conj(V_j[i]) w[i] with V_j = V + j*ld; partials holds
+// 2 * dot_partials_per_vector() doubles per j.
+int dot_partials_per_vector();
+hipError_t launch_multi_dot(const double2 *V, int64_t ld, int m, const double2 *w, int64_t n,
+                            double *partials, double *out, hipStream_t s);
+hipError_t launch_multi_axpy(double2 *x, double beta, const double2 *V, int64_t ld, int m,
+                             const double *c, int64_t n, hipStream_t s);  // x = beta x + V c
+hipError_t launch_precondition(double2 *t, const double2 *r, const double *d, double theta,
+                               int64_t n, hipStream_t s);
+hipError_t launch_zero(double2 *y, int64_t n, hipStream_t s);
+hipError_t launch_embed(const double2 *x, const int32_t *map, int64_t nx, double2 *y, int64_t ny,
+                        hipStream_t s);
+
 // Launch with optional event timing (sg_api.cpp); the drivers use these.
 hipError_t run_sweep(sg_problem *timing_owner, const Plan *pl, const LaunchCtl &c,
                      hipStream_t s);
