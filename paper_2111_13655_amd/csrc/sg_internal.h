@@ -151,6 +151,7 @@ struct PackSet {
   int32_t count = 0;
   int32_t lds_bytes = 0;        // dynamic LDS of the launch (tables + largest pack)
   int32_t tab_bytes = 0;        // LDS at offset 0 holding the standard-map tables
+  int32_t all_inplace = 0;      // every term of the set runs in place (or is scalar)
 };
 // The one-mode tables of the standard size maps (nb = 2l+1, nq = 2l+2) are
 // the same for every instance; a launch copies them into LDS once per

@@ -64,7 +64,12 @@ Cand make_cand(int32_t inst, int32_t term, const Compiled &h, bool split, int el
   Cand c{inst, term, h.cost[term], 0, 0, 0, T.ngrid};
   const bool std_maps = h.nbA == 1 && h.nbB == 2 && h.nqA == 2 && h.nqB == 2;
   const int64_t one = (int64_t)T.ngrid * elem;
-  if (split && std_maps && T.na > 0 && inplace_fits(T, kSweepThreads)) {
+  if (split && std_maps && T.na == 0) {
+    // the scalar case: one product, no grid buffer
+    c.inplace = 1;
+    c.slice = elem;
+    c.wave = 1;
+  } else if (split && std_maps && inplace_fits(T, kSweepThreads)) {
     c.inplace = 1;
     c.slice = one + kCoefLdsBytes;
     c.wave = inplace_fits(T, 64) ? 1 : 0;
@@ -298,6 +303,22 @@ void build_cache(sg_problem *p) {
 
 }  // namespace
 
+// Does every pack of each set run its terms in place?  Such a set launches
+// the sweep without the ping-pong form.
+static void mark_inplace_sets(Plan *pl) {
+  for (int k = 0; k < kPackSets; ++k) {
+    PackSet &set = pl->sets[k];
+    bool all = set.count > 0;
+    for (int32_t i = set.first; all && i < set.first + set.count; ++i) {
+      const PackDev &pk = pl->packs[i];
+      if (pk.block == kPackBlockScratch) all = false;
+      const int n = pk.block == kPackWaves ? pk.n : 1;
+      for (int w = 0; w < n; ++w) all = all && pk.inplace[w] != 0;
+    }
+    set.all_inplace = all ? 1 : 0;
+  }
+}
+
 sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::string *err) {
   pl->probs = probs;
   pl->inst.assign(probs.size(), InstDev{});
@@ -385,6 +406,7 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
     pack_set(cs64, 16, tabs[kSetSplit64], &pl->packs, &pl->sets[kSetSplit64], &pl->scratch_bytes);
     pack_set(m64, 16, tabs[kSetMixed64], &pl->packs, &pl->sets[kSetMixed64], &pl->scratch_bytes);
     pack_set(m32, 8, tabs[kSetMixed32], &pl->packs, &pl->sets[kSetMixed32], &pl->scratch_bytes);
+    mark_inplace_sets(pl);
     return SG_OK;
   }
   // concatenate the problems' cached packs, most expensive first
@@ -420,6 +442,7 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
       set.lds_bytes = tabs[k] + pack_lds;
     }
   }
+  mark_inplace_sets(pl);
   return SG_OK;
 }
 

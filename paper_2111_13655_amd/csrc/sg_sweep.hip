@@ -836,6 +836,47 @@ __device__ __forceinline__ void ld_row(lds_p<const R> M, int u, R (&r)[NI]) {
 // more registers than the latency they hide).
 template <int NI> struct RowAhead { static constexpr bool value = NI <= 8; };
 
+// The rows of a one-mode matrix (NO rows of NI entries, row-major in LDS) as
+// a contraction walks its outputs.  Level-1 matrices (at most 4 rows) are held
+// whole: every row load is issued before the first output and the row loop
+// is unrolled.  Longer matrices are read one row ahead in a rolled loop.
+template <typename R, int NI, int NO>
+struct Rows {
+  static constexpr bool kAll = NO <= 4;
+  R all[kAll ? NO : 1][NI];
+  R cur[NI], nxt[NI];
+  lds_p<const R> M;
+  __device__ __forceinline__ explicit Rows(lds_p<const R> m) : M(m) {}
+  // issue the first loads (before the group sync that precedes the outputs)
+  __device__ __forceinline__ void prime() {
+    if constexpr (kAll) {
+#pragma unroll
+      for (int u = 0; u < NO; ++u) ld_row<R, NI>(M, u, all[u]);
+    } else {
+      ld_row<R, NI>(M, 0, cur);
+    }
+  }
+  // body(u, row) for u = 0..NO-1 in order
+  template <typename Body>
+  __device__ __forceinline__ void run(Body &&body) {
+    if constexpr (kAll) {
+#pragma unroll
+      for (int u = 0; u < NO; ++u) body(u, all[u]);
+    } else {
+#pragma unroll 1
+      for (int u = 0; u < NO; ++u) {
+        if (!RowAhead<NI>::value) ld_row<R, NI>(M, u, cur);
+        else if (u + 1 < NO) ld_row<R, NI>(M, u + 1, nxt);
+        body(u, cur);
+        if (RowAhead<NI>::value) {
+#pragma unroll
+          for (int k = 0; k < NI; ++k) cur[k] = nxt[k];
+        }
+      }
+    }
+  }
+};
+
 template <typename G, typename R, int NI, int NO>
 __device__ __forceinline__ void contract_ip(lds_p<typename Cx<R>::T> buf, lds_p<const R> M,
                                             int stride, int nouter) {
@@ -862,31 +903,22 @@ __device__ __forceinline__ void contract_ip(lds_p<typename Cx<R>::T> buf, lds_p<
 #pragma unroll
     for (int k = 0; k < NI; ++k) x[j][k] = ldc<C>(buf + ib + k * stride);
   }
-  R cur[NI], nxt[NI];
-  ld_row<R, NI>(M, 0, cur);
+  Rows<R, NI, NO> rows(M);
+  rows.prime();
   G::sync();
-#pragma unroll 1
-  for (int u = 0; u < NO; ++u) {
-    if (!RowAhead<NI>::value) ld_row<R, NI>(M, u, cur);
-    else if (u + 1 < NO) ld_row<R, NI>(M, u + 1, nxt);
+  rows.run([&](int u, const R (&row)[NI]) {
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
       if (j >= nj) break;
       R re = 0, im = 0;
 #pragma unroll
       for (int k = 0; k < NI; ++k) {
-        re = fma(cur[k], x[j][k].x, re);
-        im = fma(cur[k], x[j][k].y, im);
+        re = fma(row[k], x[j][k].x, re);
+        im = fma(row[k], x[j][k].y, im);
       }
       if (ok[j]) stc(buf + ob[j] + u * stride, Cx<R>::make(re, im));
     }
-    if (RowAhead<NI>::value) {
-      if (RowAhead<NI>::value) {
-#pragma unroll
-        for (int k = 0; k < NI; ++k) cur[k] = nxt[k];
-      }
-    }
-  }
+  });
 }
 
 template <typename G, typename R, int NI, int NO>
@@ -921,28 +953,21 @@ __device__ __forceinline__ void gather_ip(const TermCtx &a, int off, int nfib, l
         x[j][k] = Cx<R>::make((R)v.x, (R)v.y);
       }
     }
-    R cur[NI], nxt[NI];
-    ld_row<R, NI>(M, 0, cur);
-#pragma unroll 1
-    for (int u = 0; u < NO; ++u) {
-      if (!RowAhead<NI>::value) ld_row<R, NI>(M, u, cur);
-      else if (u + 1 < NO) ld_row<R, NI>(M, u + 1, nxt);
+    Rows<R, NI, NO> rows(M);
+    rows.prime();
+    rows.run([&](int u, const R (&row)[NI]) {
 #pragma unroll
       for (int j = 0; j < FPT; ++j) {
         if (j >= nj) break;
         R re = 0, im = 0;
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
-          re = fma(cur[k], x[j][k].x, re);
-          im = fma(cur[k], x[j][k].y, im);
+          re = fma(row[k], x[j][k].x, re);
+          im = fma(row[k], x[j][k].y, im);
         }
         if (ok[j]) stc(out + fb[j] * NO + u, Cx<R>::make(re, im));
       }
-      if (RowAhead<NI>::value) {
-#pragma unroll
-        for (int k = 0; k < NI; ++k) cur[k] = nxt[k];
-      }
-    }
+    });
   }
 }
 
@@ -968,125 +993,111 @@ __device__ __forceinline__ void g2b_ip(lds_p<typename Cx<R>::T> in, Out o, lds_p
 #pragma unroll
       for (int k = 0; k < NI; ++k) x[j][k] = ldc<C>(in + lo[j] + k * stride);
     }
-    R cur[NI], nxt[NI];
-    ld_row<R, NI>(M, 0, cur);
-#pragma unroll 1
-    for (int u = 0; u < NO; ++u) {
-      if (!RowAhead<NI>::value) ld_row<R, NI>(M, u, cur);
-      else if (u + 1 < NO) ld_row<R, NI>(M, u + 1, nxt);
+    Rows<R, NI, NO> rows(M);
+    rows.prime();
+    rows.run([&](int u, const R (&row)[NI]) {
 #pragma unroll
       for (int j = 0; j < FPT; ++j) {
         if (j >= nj) break;
         R re = 0, im = 0;
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
-          re = fma(cur[k], x[j][k].x, re);
-          im = fma(cur[k], x[j][k].y, im);
+          re = fma(row[k], x[j][k].x, re);
+          im = fma(row[k], x[j][k].y, im);
         }
         if (ok[j]) stc(o.tm + lo[j] + u * stride, Z64{cf * (double)re, cf * (double)im});
       }
-      if (RowAhead<NI>::value) {
-#pragma unroll
-        for (int k = 0; k < NI; ++k) cur[k] = nxt[k];
-      }
-    }
+    });
   }
 }
 
-// The split coupling potential in place (fibers along mode 0; nodes from the
-// LDS tables).  Same arithmetic as potential_fixed without the kinetic part.
-template <typename G, typename R, int NQ>
-__device__ __forceinline__ void potential_ip(const TermCtx &a, const TermHdr &T,
-                                             lds_p<typename Cx<R>::T> buf, int nfib,
-                                             lds_p<const R> lt, lds_p<const R> cf) {
+// The first grid -> basis contraction (along mode 0, whose fibers are
+// contiguous) with the split coupling potential applied to the fibers as they
+// are loaded.  Along a mode-0 fiber the potential is A + x0 (C + B x0), where
+// A, B, C depend on the fiber's coordinates in the other active modes (nodes
+// from the LDS tables, coefficients from the term's LDS block).  STORE: mode 0
+// is the only active mode and the outputs, times D_l, go to HBM; otherwise
+// they overwrite the fibers in place (at most inplace_fpt(NQ) fibers per
+// thread).
+template <typename G, typename R, int NQ, int NB, bool STORE>
+__device__ __forceinline__ void pot_g2b0_ip(const TermHdr &T, lds_p<typename Cx<R>::T> buf,
+                                            lds_p<const R> lt, lds_p<const R> cf, int nfib,
+                                            Out o, double dl) {
   typedef typename Cx<R>::T C;
-  constexpr int FPT = NQ <= 8 ? 2 : 1;
+  constexpr int FPT = inplace_fpt(NQ);
   const int na = T.na();
   const int l0 = T.lev(0);
-  const lds_p<const R> x0 = lt + std_table_base(l0) + 2 * (2 * l0 + 1) * (2 * l0 + 2);
-  const R c0 = cf[0];
-  const R al0 = cf[1];
-  const R be0 = cf[2];
-  for (int f0 = 0; f0 < nfib; f0 += FPT * G::N) {
-    const int nj = min(FPT, (nfib - f0 + G::N - 1) / G::N);
-    bool ok[FPT];
-    int fb[FPT];
+  const int nj = min(FPT, (nfib + G::N - 1) / G::N);
+  bool ok[FPT];
+  int fb[FPT];
+  R A[FPT], B[FPT], Cl[FPT];
 #pragma unroll
-    for (int j = 0; j < FPT; ++j) {
-      const int f = f0 + G::tid() + j * G::N;
-      ok[j] = f < nfib && j < nj;
-      fb[j] = ok[j] ? f : 0;
-    }
-    R xq[FPT][kMaxActive];
-    int rem[FPT];
-#pragma unroll
-    for (int j = 0; j < FPT; ++j) rem[j] = fb[j];
+  for (int j = 0; j < FPT; ++j) {
+    if (j >= nj) break;
+    const int f = G::tid() + j * G::N;
+    ok[j] = f < nfib;
+    fb[j] = ok[j] ? f : 0;
+    // the fiber's coordinates along modes 1.., and its A, B, C
+    R xq[kMaxActive];
+    int rem = fb[j];
+    A[j] = cf[0];
+    B[j] = cf[1];
+    Cl[j] = cf[2];
 #pragma unroll
     for (int q = 1; q < kMaxActive; ++q) {
-      if (q < na) {
-        const float rq = T.rcp_nq(q);
-        const int nq = T.nq(q);
-        const int lq = T.lev(q);
-        const lds_p<const R> xn = lt + std_table_base(lq) + 2 * (2 * lq + 1) * (2 * lq + 2);
+      if (q >= na) break;
+      const int hi = fdiv(rem, T.rcp_nq(q));
+      const int uq = rem - hi * T.nq(q);
+      rem = hi;
+      const int lq = T.lev(q);
+      xq[q] = lt[std_table_base(lq) + 2 * (2 * lq + 1) * (2 * lq + 2) + uq];
+      const R x2 = xq[q] * xq[q];
+      A[j] = fma(cf[2 + q], x2, A[j]);
+      A[j] = fma(cf[9 + q], xq[q], A[j]);
+      B[j] = fma(cf[16 + q], x2, B[j]);
+      Cl[j] = fma(cf[23 + q], x2, Cl[j]);
 #pragma unroll
-        for (int j = 0; j < FPT; ++j) {
-          const int hi = fdiv(rem[j], rq);
-          const int uq = rem[j] - hi * nq;
-          rem[j] = hi;
-          xq[j][q] = xn[uq];
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < FPT; ++j) xq[j][q] = 0;
-      }
-    }
-    R A[FPT], B[FPT], Cl[FPT];
-#pragma unroll
-    for (int j = 0; j < FPT; ++j) {
-      A[j] = c0;
-      B[j] = al0;
-      Cl[j] = be0;
-    }
-#pragma unroll
-    for (int q = 1; q < kMaxActive; ++q) {
-      if (q < na) {
-        const R alq = cf[2 + q], beq = cf[9 + q];
-        const R c0q = cf[16 + q], k0q = cf[23 + q];
-#pragma unroll
-        for (int j = 0; j < FPT; ++j) {
-          const R x2 = xq[j][q] * xq[j][q];
-          A[j] = fma(alq, x2, A[j]);
-          A[j] = fma(beq, xq[j][q], A[j]);
-          B[j] = fma(c0q, x2, B[j]);
-          Cl[j] = fma(k0q, x2, Cl[j]);
-        }
-#pragma unroll
-        for (int r = q + 1; r < kMaxActive; ++r) {
-          if (r < na) {
-            const R cqr = cf[coef_pair(q, r)], kqr = cf[coef_pair(q, r) + 1];
-#pragma unroll
-            for (int j = 0; j < FPT; ++j) {
-              const R x2 = xq[j][q] * xq[j][q];
-              const R y2 = xq[j][r] * xq[j][r];
-              A[j] = fma(cqr * x2, y2, A[j]);
-              A[j] = fma(kqr * y2, xq[j][q], A[j]);
-            }
-          }
-        }
-      }
-    }
-#pragma unroll 1
-    for (int u = 0; u < NQ; ++u) {
-      const R xv = x0[u];
-#pragma unroll
-      for (int j = 0; j < FPT; ++j) {
-        if (j >= nj) break;
-        const R V = fma(fma(B[j], xv, Cl[j]), xv, A[j]);
-        const C xu = ldc<C>(buf + fb[j] * NQ + u);
-        if (ok[j]) stc(buf + fb[j] * NQ + u, Cx<R>::make(V * xu.x, V * xu.y));
+      for (int r = 1; r < q; ++r) {   // pair (r, q), r < q
+        const R cqr = cf[coef_pair(r, q)], kqr = cf[coef_pair(r, q) + 1];
+        A[j] = fma(cqr * (xq[r] * xq[r]), x2, A[j]);
+        A[j] = fma(kqr * x2, xq[r], A[j]);
       }
     }
   }
+  const lds_p<const R> x0 = lt + std_table_base(l0) + 2 * NB * NQ;
+  R xn[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) xn[k] = x0[k];
+  C x[FPT][NQ];
+#pragma unroll
+  for (int j = 0; j < FPT; ++j) {
+    if (j >= nj) break;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      const C v = ldc<C>(buf + fb[j] * NQ + k);
+      const R V = fma(fma(B[j], xn[k], Cl[j]), xn[k], A[j]);
+      x[j][k] = Cx<R>::make(V * v.x, V * v.y);
+    }
+  }
+  Rows<R, NQ, NB> rows(lt + std_table_base(l0) + NB * NQ);
+  rows.prime();
+  if (!STORE) G::sync();
+  rows.run([&](int v, const R (&row)[NQ]) {
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      if (j >= nj) break;
+      R re = 0, im = 0;
+#pragma unroll
+      for (int k = 0; k < NQ; ++k) {
+        re = fma(row[k], x[j][k].x, re);
+        im = fma(row[k], x[j][k].y, im);
+      }
+      if (ok[j]) {
+        if (STORE) stc(o.tm + fb[j] * NB + v, Z64{dl * (double)re, dl * (double)im});
+        else stc(buf + fb[j] * NB + v, Cx<R>::make(re, im));
+      }
+    }
+  });
 }
 
 // Level dispatch of the in-place steps (standard maps: nb = 2l+1, nq = 2l+2).
@@ -1107,7 +1118,8 @@ __device__ __forceinline__ void contract_ip_level(int kind, int level,
 }
 
 // Alg. 1 for one term of the split operator in place: gather + basis -> grid,
-// the coupling potential pointwise, grid -> basis, D_l * result to HBM.
+// then grid -> basis with the coupling potential applied to the fibers of the
+// first contraction, D_l * result to HBM.
 template <typename G, typename R>
 __device__ __forceinline__ void run_term_inplace(const TermCtx &a, const TermHdr &T,
                                                  lds_p<typename Cx<R>::T> buf,
@@ -1121,8 +1133,8 @@ __device__ __forceinline__ void run_term_inplace(const TermCtx &a, const TermHdr
   // sync after the gather)
   const lds_p<R> coef = (lds_p<R>)(buf + ngrid);
   for (int i = G::tid(); i < kCoefUsed; i += G::N) coef[i] = (R)a.pcoef[i];
+  const int l0 = T.lev(0);
   {
-    const int l0 = T.lev(0);
     const int nb0 = T.nb(0), nq0 = T.nq(0);
     const lds_p<const R> M0 = lt + std_table_base(l0);
 #define SG_GCASE(L_, NB_, NQ_)                                                   \
@@ -1139,18 +1151,23 @@ __device__ __forceinline__ void run_term_inplace(const TermCtx &a, const TermHdr
       stride *= T.nq(p);
     }
   }
-  {
-    const int nfib = ngrid / T.nq(0);
-#define SG_PIPCASE(L_, NB_, NQ_)                                                 \
-  case L_: potential_ip<G, R, NQ_>(a, T, buf, nfib, lt, coef); break;
-    switch (T.lev(0)) { SG_LEVELS(SG_PIPCASE) default: break; }
-#undef SG_PIPCASE
-    G::sync();
+  const int nfib = ngrid / T.nq(0);
+  if (na == 1) {
+#define SG_P1CASE(L_, NB_, NQ_)                                                  \
+  case L_: pot_g2b0_ip<G, R, NQ_, NB_, true>(T, buf, lt, coef, nfib, Out{a.tm + off}, cf); break;
+    switch (l0) { SG_LEVELS(SG_P1CASE) default: break; }
+#undef SG_P1CASE
+    return;
   }
+#define SG_PCASE(L_, NB_, NQ_)                                                   \
+  case L_: pot_g2b0_ip<G, R, NQ_, NB_, false>(T, buf, lt, coef, nfib, Out{a.tm + off}, cf); break;
+  switch (l0) { SG_LEVELS(SG_PCASE) default: break; }
+#undef SG_PCASE
+  G::sync();
   {
-    int stride = 1;
-    int nouter = ngrid;
-    for (int p = 0; p < na - 1; ++p) {
+    int stride = T.nb(0);
+    int nouter = nfib;
+    for (int p = 1; p < na - 1; ++p) {
       nouter /= T.nq(p);
       contract_ip_level<G, R>(2, T.lev(p), buf, lt, stride, nouter);
       G::sync();
@@ -1166,8 +1183,9 @@ __device__ __forceinline__ void run_term_inplace(const TermCtx &a, const TermHdr
   }
 }
 
-// One term: the scalar case, then the in-place or the ping-pong form.
-template <typename G, typename R, typename P>
+// One term: the scalar case, then the in-place or the ping-pong form (IP: the
+// launch holds in-place terms only, and the ping-pong form is not compiled in).
+template <typename G, typename R, typename P, bool IP>
 __device__ __forceinline__ void run_any(const TermCtx &a, cptr<TermDev> T, P base, int inplace,
                                         char *lds_raw) {
   if (T->na == 0) {
@@ -1178,10 +1196,10 @@ __device__ __forceinline__ void run_any(const TermCtx &a, cptr<TermDev> T, P bas
     }
     return;
   }
-  if (inplace)
+  if (IP || inplace)
     run_term_inplace<G, R>(a, load_hdr(T), (lds_p<typename Cx<R>::T>)base,
                            (lds_p<const R>)(lds_raw + a.lt_off));
-  else run_term<G, R, P>(a, T, base, T->ngrid);
+  else if constexpr (!IP) run_term<G, R, P>(a, T, base, T->ngrid);
 }
 
 // Is instance I part of this launch, and which vector does H act on?
@@ -1213,8 +1231,10 @@ __device__ __forceinline__ TermCtx make_ctx(const SweepArgs &a, cptr<InstDev> I,
   return c;
 }
 
-template <typename R>
-__global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
+// IP: every term of the launch runs in place.  Two workgroups per compute
+// unit: at most 128 VGPRs per lane.
+template <typename R, bool IP>
+__global__ __launch_bounds__(kThreads, 4) void sweep_kernel(SweepArgs a) {
   extern __shared__ char lds_raw[];
   typedef typename Cx<R>::T C;
   // the standard-map tables into LDS (every wavefront takes part)
@@ -1236,11 +1256,16 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
     const int t = P->term[0];
     const cptr<TermDev> T = (cptr<TermDev>)(I->terms + t);
     const TermCtx c = make_ctx<R>(a, I, t);
-    if (kind == kPackBlockLds)
-      run_any<BlockGroup, R, lds_p<C>>(c, T, (lds_p<C>)pack_lds, P->inplace[0], lds_raw);
-    else
-      run_any<BlockGroup, R, glb_p<C>>(c, T, (glb_p<C>)(a.scratch + P->scratch_off), 0,
-                                       lds_raw);
+    if constexpr (IP) {
+      run_any<BlockGroup, R, lds_p<C>, true>(c, T, (lds_p<C>)pack_lds, 1, lds_raw);
+    } else {
+      if (kind == kPackBlockLds)
+        run_any<BlockGroup, R, lds_p<C>, false>(c, T, (lds_p<C>)pack_lds, P->inplace[0],
+                                                lds_raw);
+      else
+        run_any<BlockGroup, R, glb_p<C>, false>(c, T, (glb_p<C>)(a.scratch + P->scratch_off), 0,
+                                                lds_raw);
+    }
     return;
   }
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1250,26 +1275,33 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs a) {
   const int t = P->term[w];
   const cptr<TermDev> T = (cptr<TermDev>)(I->terms + t);
   const TermCtx c = make_ctx<R>(a, I, t);
-  run_any<WaveGroup, R, lds_p<C>>(c, T, (lds_p<C>)(pack_lds + P->lds_off[w]), P->inplace[w],
-                                  lds_raw);
+  run_any<WaveGroup, R, lds_p<C>, IP>(c, T, (lds_p<C>)(pack_lds + P->lds_off[w]),
+                                      P->inplace[w], lds_raw);
 }
 
-template <typename R>
-hipError_t launch_packs(const SweepArgs &a, int npacks, int lds, hipStream_t s,
-                        hipEvent_t ev0, hipEvent_t ev1) {
+template <typename R, bool IP>
+hipError_t launch_packs_as(const SweepArgs &a, int npacks, int lds, hipStream_t s,
+                           hipEvent_t ev0, hipEvent_t ev1) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)sweep_kernel<R>,
+    hipError_t e = hipFuncSetAttribute((const void *)sweep_kernel<R, IP>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   if (ev0 || ev1)
-    hipExtLaunchKernelGGL(sweep_kernel<R>, dim3((unsigned)npacks), dim3(kThreads), lds, s, ev0,
-                          ev1, 0, a);
+    hipExtLaunchKernelGGL((sweep_kernel<R, IP>), dim3((unsigned)npacks), dim3(kThreads), lds, s,
+                          ev0, ev1, 0, a);
   else
-    hipLaunchKernelGGL(sweep_kernel<R>, dim3((unsigned)npacks), dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((sweep_kernel<R, IP>), dim3((unsigned)npacks), dim3(kThreads), lds, s, a);
   return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_packs(const SweepArgs &a, const PackSet &ps, hipStream_t s, hipEvent_t ev0,
+                        hipEvent_t ev1) {
+  if (ps.all_inplace) return launch_packs_as<R, true>(a, ps.count, ps.lds_bytes, s, ev0, ev1);
+  return launch_packs_as<R, false>(a, ps.count, ps.lds_bytes, s, ev0, ev1);
 }
 
 }  // namespace
@@ -1293,7 +1325,7 @@ hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
     a.packs = (cptr<PackDev>)(pl->d_packs + ps.first);
     a.stab = pl->d_stab64;
     a.tab_a = ps.tab_bytes;
-    return launch_packs<double>(a, ps.count, ps.lds_bytes, s, c.ev0, c.ev1);
+    return launch_packs<double>(a, ps, s, c.ev0, c.ev1);
   }
   // mixed: terms with large |D_l| in FP64, the rest in FP32.  The FP64 terms
   // of an instance that also has FP32 terms read the FP32-rounded tables, so
@@ -1306,7 +1338,7 @@ hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
     a.stab_r = pl->d_stab32r;
     a.tab_a = pl->any_round32 ? p64.tab_bytes / 2 : p64.tab_bytes;
     a.tab_b = pl->any_round32 ? p64.tab_bytes / 2 : 0;
-    e = launch_packs<double>(a, p64.count, p64.lds_bytes, s, c.ev0,
+    e = launch_packs<double>(a, p64, s, c.ev0,
                              p32.count > 0 ? nullptr : c.ev1);
     if (e != hipSuccess) return e;
   }
@@ -1316,7 +1348,7 @@ hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
     a.stab_r = nullptr;
     a.tab_a = p32.tab_bytes;
     a.tab_b = 0;
-    e = launch_packs<float>(a, p32.count, p32.lds_bytes, s, p64.count > 0 ? nullptr : c.ev0,
+    e = launch_packs<float>(a, p32, s, p64.count > 0 ? nullptr : c.ev0,
                             c.ev1);
   }
   return e;
