@@ -97,6 +97,8 @@ void release(sg_problem *p) {
   hipFree(p->d_tm);
   hipFree(p->d_work);
   hipFree(p->d_partials);
+  hipFree(p->d_rpart);
+  hipFree(p->d_rcnt);
   hipFree(p->d_cheb_a);
   hipFree(p->d_result);
   if (p->h_result) hipHostFree(p->h_result);
@@ -158,7 +160,8 @@ int64_t estimate_device_bytes(const Compiled &h) {
   const int64_t ns = (int64_t)h.MB.size();
   return (int64_t)h.terms.size() * (int64_t)sizeof(TermDev) + (int64_t)h.pairs.size() * 8 + (int64_t)h.potc.size() * 8 +
          ns * 4 * 2 + (h.ncs + 1) * 4 + h.ncs * 4 + h.ncs * 8 + ns * 16 + 4 * h.ncs * 16 +
-         2 * std::max<int64_t>(h.n_items, 256) * 8 + (int64_t)h.tables.size() * 20 +
+         4 * std::max<int64_t>(h.n_items, 256) * 8 + 4 * std::max<int64_t>(h.n_long_rows, 1) +
+         (int64_t)h.tables.size() * 20 +
          (int64_t)sizeof(double) * (kMaxChebTerms + 8);
 }
 
@@ -179,8 +182,8 @@ sg_status upload_problem(sg_problem *p, sg_problem **out) {
   SG_UP(d_tables32, h.tables32)
   SG_UP(d_tables32r, h.tables32r)
   SG_UP(d_mb, h.mbd)
-  SG_UP(d_inv_ptr, h.inv_ptr)
-  SG_UP(d_inv_col, h.inv_col)
+  SG_UP(d_inv_ptr, h.red_ptr)
+  SG_UP(d_inv_col, h.red_col)
   SG_UP(d_rows, h.rows)
   SG_UP(d_tables, h.tables)
   SG_UP(d_pairs, h.pairs)
@@ -199,6 +202,17 @@ sg_status upload_problem(sg_problem *p, sg_problem **out) {
   e = hipMalloc((void **)&p->d_partials, 2 * (size_t)npart * sizeof(double));
   if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
   bytes += 2 * npart * (int64_t)sizeof(double);
+  e = hipMalloc((void **)&p->d_rpart, 2 * (size_t)npart * sizeof(double));
+  if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
+  bytes += 2 * npart * (int64_t)sizeof(double);
+  {
+    const size_t cnt_bytes = (size_t)std::max<int64_t>(h.n_long_rows, 1) * sizeof(int32_t);
+    e = hipMalloc((void **)&p->d_rcnt, cnt_bytes);
+    if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
+    e = hipMemset(p->d_rcnt, 0, cnt_bytes);
+    if (e != hipSuccess) { release(p); return hip_fail(e, "clear the row counters"); }
+    bytes += (int64_t)cnt_bytes;
+  }
   e = hipMalloc((void **)&p->d_cheb_a, kMaxChebTerms * sizeof(double));
   if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
   e = hipMalloc((void **)&p->d_result, 8 * sizeof(double));

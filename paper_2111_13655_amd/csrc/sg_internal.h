@@ -97,8 +97,8 @@ struct InstDev {
   const double *pairs;
   const double *potc;       // [nterms][2][kCoefStride] split coefficient blocks
   const int32_t *mb;
-  const int32_t *inv_ptr;
-  const int32_t *inv_col;   // [N_s] term-major entries of each compact row
+  const int32_t *inv_ptr;   // [N_cs+1] indexed by reduce item row, not compact index
+  const int32_t *inv_col;   // [N_s] term-major entries of rows[0], rows[1], ...
   const int32_t *rows;      // long rows first, then short rows
   const double *h0;
   const double *tab64;      // one-mode tables, exact
@@ -108,6 +108,8 @@ struct InstDev {
   double2 *x0, *x1;         // apply: x0 -> x1.  Chebyshev: phi buffers, x0 = psi
   double2 *acc;             // Chebyshev running sum
   double *partials;         // [2 * nitems] norm / energy partial sums
+  double *rpart;            // [2 * nitems] partial sums of split long rows
+  int32_t *rcnt;            // [nlong] arrival counters of split long rows (kept at 0)
   double *result;           // [2] finalised sums
   const double *cheb_a;     // [K] series coefficients (2 - delta_k0) J_k(R)
   int64_t ncs;
@@ -168,13 +170,17 @@ enum PackSetId { kSetGrid64 = 0, kSetSplit64 = 1, kSetMixed64 = 2, kSetMixed32 =
 // Rows of the inverse mapping longer than this are reduced by a whole
 // wavefront, shorter ones by a group of 8 lanes.
 constexpr int kLongRow = 64;
+// Long rows are summed in chunks of at most kRowChunk entries, one wavefront
+// each (spread over compute units); the last chunk to finish adds the chunk
+// sums in chunk order.
+constexpr int kRowChunk = 256;
 constexpr int kShortLanes = 8;
 // One reduce work item = one wavefront: a long row, or 8 short rows.
 struct RedItem {
   int32_t inst;
   int32_t first;    // index into the instance's row list
   int32_t local;    // item index inside the instance (partial-sum slot)
-  int32_t pad;
+  int32_t chunk;    // long rows: chunk | (number of chunks << 16); short rows: 0
 };
 
 // Host-side term compiler output.
@@ -194,6 +200,8 @@ struct Compiled {
   std::vector<int32_t> MB;           // [N_s]
   std::vector<int32_t> inv_ptr;      // [ncs+1] inverse CSR row pointers
   std::vector<int32_t> inv_col;      // [N_s] term-major positions, ascending
+  std::vector<int32_t> red_ptr;      // [ncs+1] the inverse CSR with its rows in `rows` order
+  std::vector<int32_t> red_col;      // [N_s]   (what the reduce kernel reads)
   std::vector<int32_t> mbd;          // [N_s] M^B, positions lexicographic (device order)
   std::vector<double> h0;            // [ncs] sum_i omega_i (n_i + 1/2)
   // tables
@@ -276,6 +284,8 @@ struct sg_problem {
   double2 *d_tm = nullptr;         // term-major results [N_s]
   double2 *d_work = nullptr;       // 4 * N_cs: Chebyshev phi, ACC, spares
   double *d_partials = nullptr;    // [2 * n_items] reduction partials
+  double *d_rpart = nullptr;       // [2 * n_items] chunk sums of long rows
+  int32_t *d_rcnt = nullptr;       // [n_long_rows] chunk arrival counters
   double *d_cheb_a = nullptr;      // [kMaxChebTerms] series coefficients
   int grid_kinetic = 0;            // 1: SG_FP64 applies the kinetic matrices on the grid
   sg::PackCache pcache;            // packs for multi-problem plans

@@ -239,6 +239,8 @@ void inst_from_problem(const sg_problem *p, InstDev *d) {
   d->x1 = p->d_work + h.ncs;
   d->acc = p->d_work + 2 * h.ncs;
   d->partials = p->d_partials;
+  d->rpart = p->d_rpart;
+  d->rcnt = p->d_rcnt;
   d->result = p->d_result;
   d->cheb_a = p->d_cheb_a;
   d->ncs = h.ncs;
@@ -260,9 +262,13 @@ constexpr int kTabMax64 = ((std_table_base(8) * 8 + 15) / 16) * 16;
 constexpr int kTabMax32 = ((std_table_base(8) * 4 + 15) / 16) * 16;
 
 void reduce_items(const Compiled &h, int32_t inst, std::vector<RedItem> *items) {
-  for (int64_t q = 0; q < h.n_long_rows; ++q) items->push_back({inst, (int32_t)q, (int32_t)q, 0});
+  int32_t local = 0;
+  for (int64_t q = 0; q < h.n_long_rows; ++q) {
+    const int64_t len = h.red_ptr[q + 1] - h.red_ptr[q];
+    const int32_t nch = (int32_t)((len + kRowChunk - 1) / kRowChunk);
+    for (int32_t c = 0; c < nch; ++c) items->push_back({inst, (int32_t)q, local++, c | (nch << 16)});
+  }
   const int64_t nshort = h.ncs - h.n_long_rows;
-  int32_t local = (int32_t)h.n_long_rows;
   for (int64_t q = 0; q < nshort; q += kShortLanes)
     items->push_back({inst, (int32_t)(h.n_long_rows + q), local++, 0});
 }

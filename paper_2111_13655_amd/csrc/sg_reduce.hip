@@ -49,23 +49,26 @@ struct ReduceArgs {
 };
 
 // Sum of tm[col[j]] for j = b + sub, b + sub + G, ... < e, in increasing j.
-// Four index loads and then four value loads are issued before any add.
-template <int G>
+// Rounds of U entries per lane: U index loads, then U value loads, then the
+// adds, so that a row of up to U*G entries costs one dependent pair of loads.
+template <int G, int U>
 __device__ __forceinline__ void strided_sum(glb_p<const int32_t> col, glb_p<const Z64> tm, int b,
                                             int e, int sub, double *sr, double *si) {
-  int j = b + sub;
-  for (; j + 3 * G < e; j += 4 * G) {
-    const int c0 = col[j], c1 = col[j + G], c2 = col[j + 2 * G], c3 = col[j + 3 * G];
-    const Z64 v0 = ldz(tm + c0), v1 = ldz(tm + c1), v2 = ldz(tm + c2), v3 = ldz(tm + c3);
-    *sr += v0.x; *si += v0.y;
-    *sr += v1.x; *si += v1.y;
-    *sr += v2.x; *si += v2.y;
-    *sr += v3.x; *si += v3.y;
-  }
-  for (; j < e; j += G) {
-    const Z64 v = ldz(tm + col[j]);
-    *sr += v.x;
-    *si += v.y;
+  for (int j = b + sub; j < e; j += U * G) {
+    int c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) c[u] = j + u * G < e ? col[j + u * G] : 0;
+    Z64 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (j + u * G < e) v[u] = ldz(tm + c[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (j + u * G < e) {
+        *sr += v[u].x;
+        *si += v[u].y;
+      }
+    }
   }
 }
 
@@ -160,16 +163,69 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
   const glb_p<const int32_t> rows = (glb_p<const int32_t>)I->rows;
   const glb_p<const int32_t> col = (glb_p<const int32_t>)I->inv_col;
   double pn = 0.0, pe = 0.0;
+  int slot = it->local;     // where this item's norm / energy partials go
+  bool write_part = true;
   if (it->first < I->nlong) {
-    const int64_t row = __builtin_amdgcn_readfirstlane(rows[it->first]);
-    const int b = __builtin_amdgcn_readfirstlane(ptr[row]);
-    const int e = __builtin_amdgcn_readfirstlane(ptr[row + 1]);
+    const int q = it->first;
+    const int c = it->chunk & 0xffff, nch = it->chunk >> 16;
+    const int64_t row = __builtin_amdgcn_readfirstlane(rows[q]);
+    const int b = __builtin_amdgcn_readfirstlane(ptr[q]);
+    const int e = __builtin_amdgcn_readfirstlane(ptr[q + 1]);
     const RowIn in = row_inputs(a, I, row);
+    const int cb = b + c * kRowChunk;
     double sr = 0.0, si = 0.0;
-    strided_sum<64>(col, tm, b, e, lane, &sr, &si);
+    strided_sum<64, kRowChunk / 64>(col, tm, cb, min(e, cb + kRowChunk), lane, &sr, &si);
     sr = group_sum<64>(sr);
     si = group_sum<64>(si);
-    if (lane == 0) row_epilogue(a, I, row, in, sr, si, &pn, &pe);
+    if (nch == 1) {
+      if (lane == 0) row_epilogue(a, I, row, in, sr, si, &pn, &pe);
+    } else {
+      // publish this chunk's sum, then count arrivals; the last chunk adds the
+      // chunk sums in chunk order (device-scope atomics: chunks run on
+      // different compute units)
+      const int first_slot = it->local - c;
+      int last = 0;
+      if (lane == 0) {
+        __hip_atomic_store(I->rpart + 2 * it->local, sr, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(I->rpart + 2 * it->local + 1, si, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);
+        const int old = __hip_atomic_fetch_add(I->rcnt + q, 1, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        last = old == nch - 1;
+      }
+      last = __builtin_amdgcn_readfirstlane(last);
+      if (last) {
+        if (lane == 0) {
+          double tr = 0.0, ti = 0.0;
+          for (int cc = 0; cc < nch; ++cc) {
+            if (cc == c) {
+              tr += sr;
+              ti += si;
+            } else {
+              tr += __hip_atomic_load(I->rpart + 2 * (first_slot + cc), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+              ti += __hip_atomic_load(I->rpart + 2 * (first_slot + cc) + 1, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+            }
+          }
+          row_epilogue(a, I, row, in, tr, ti, &pn, &pe);
+          __hip_atomic_store(I->rcnt + q, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // the row's partials go to its first chunk's slot; a later chunk also
+        // clears its own slot
+        slot = first_slot;
+        if (c != 0 && a.mode == 1 && a.k == 1 && a.want_partials && lane == 0) {
+          I->partials[2 * it->local] = 0.0;
+          I->partials[2 * it->local + 1] = 0.0;
+        }
+      } else {
+        // chunk 0's slot belongs to the row; other chunks clear their own
+        write_part = c != 0;
+        pn = pe = 0.0;
+      }
+    }
   } else {
     const int64_t ri = (int64_t)it->first + lane / kShortLanes;
     const int sub = lane % kShortLanes;
@@ -179,20 +235,20 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
     RowIn in{};
     if (valid) {
       row = rows[ri];
-      const int b = ptr[row], e = ptr[row + 1];
+      const int b = ptr[ri], e = ptr[ri + 1];
       in = row_inputs(a, I, row);
-      strided_sum<kShortLanes>(col, tm, b, e, sub, &sr, &si);
+      strided_sum<kShortLanes, kLongRow / kShortLanes>(col, tm, b, e, sub, &sr, &si);
     }
     sr = group_sum<kShortLanes>(sr);
     si = group_sum<kShortLanes>(si);
     if (valid && sub == 0) row_epilogue(a, I, row, in, sr, si, &pn, &pe);
   }
-  if (a.mode == 1 && a.k == 1 && a.want_partials) {
+  if (a.mode == 1 && a.k == 1 && a.want_partials && write_part) {
     pn = group_sum<64>(pn);
     pe = group_sum<64>(pe);
     if (lane == 0) {
-      I->partials[2 * it->local] = pn;
-      I->partials[2 * it->local + 1] = pe;
+      I->partials[2 * slot] = pn;
+      I->partials[2 * slot + 1] = pe;
     }
   }
 }

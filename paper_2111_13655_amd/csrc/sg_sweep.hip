@@ -832,6 +832,35 @@ __device__ __forceinline__ void ld_row(lds_p<const R> M, int u, R (&r)[NI]) {
 #pragma unroll
   for (int k = 0; k < NI; ++k) r[k] = M[u * NI + k];
 }
+
+// LDS bank skew for fibers stored contiguously, one fiber per lane (the
+// mode-0 fibers at grid size, whose length n is even): lane t visits entry
+// (i + fiber_skew) mod n at step i, so that the lanes of one 128-byte LDS pass
+// (8 lanes of 16-byte or 16 lanes of 8-byte values) hit distinct banks, also
+// when a pass spans twice as many lanes.  Zero for odd n.
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+constexpr int igcd(int a, int b) { return b == 0 ? a : igcd(b, a % b); }
+template <int N, int ELEM>
+__device__ __forceinline__ int fiber_skew() {
+  if constexpr (N % 2 != 0) {
+    return 0;
+  } else {
+    constexpr int P = 128 / ELEM;
+    constexpr int S = ilog2(P / igcd(N, P));
+    const int t = (int)threadIdx.x;
+    return ((t & (P - 1)) >> S) ^ ((t / P) & 1);
+  }
+}
+__device__ __forceinline__ int wrap_add(int i, int s, int n) {
+  const int v = i + s;
+  return v >= n ? v - n : v;
+}
+// row u of M with its columns rotated by cs: r[k] = M[u*NI + (k + cs) mod NI]
+template <typename R, int NI>
+__device__ __forceinline__ void ld_row_rot(lds_p<const R> M, int u, int cs, R (&r)[NI]) {
+#pragma unroll
+  for (int k = 0; k < NI; ++k) r[k] = M[u * NI + wrap_add(k, cs, NI)];
+}
 // Rows are prefetched one ahead for short rows only (long rows would cost
 // more registers than the latency they hide).
 template <int NI> struct RowAhead { static constexpr bool value = NI <= 8; };
@@ -840,20 +869,29 @@ template <int NI> struct RowAhead { static constexpr bool value = NI <= 8; };
 // a contraction walks its outputs.  Level-1 matrices (at most 4 rows) are held
 // whole: every row load is issued before the first output and the row loop
 // is unrolled.  Longer matrices are read one row ahead in a rolled loop.
-template <typename R, int NI, int NO>
+// SKEW: per-lane rotations (rs of the rows, cs of the columns): step u reads
+// row (u + rs) mod NO with column k holding entry (k + cs) mod NI.
+template <typename R, int NI, int NO, bool SKEW = false>
 struct Rows {
   static constexpr bool kAll = NO <= 4;
   R all[kAll ? NO : 1][NI];
   R cur[NI], nxt[NI];
   lds_p<const R> M;
+  int rs = 0, cs = 0;
   __device__ __forceinline__ explicit Rows(lds_p<const R> m) : M(m) {}
+  __device__ __forceinline__ Rows(lds_p<const R> m, int row_skew, int col_skew)
+      : M(m), rs(row_skew), cs(col_skew) {}
+  __device__ __forceinline__ void ld(int u, R (&r)[NI]) const {
+    if constexpr (SKEW) ld_row_rot<R, NI>(M, wrap_add(u, rs, NO), cs, r);
+    else ld_row<R, NI>(M, u, r);
+  }
   // issue the first loads (before the group sync that precedes the outputs)
   __device__ __forceinline__ void prime() {
     if constexpr (kAll) {
 #pragma unroll
-      for (int u = 0; u < NO; ++u) ld_row<R, NI>(M, u, all[u]);
+      for (int u = 0; u < NO; ++u) ld(u, all[u]);
     } else {
-      ld_row<R, NI>(M, 0, cur);
+      ld(0, cur);
     }
   }
   // body(u, row) for u = 0..NO-1 in order
@@ -865,8 +903,8 @@ struct Rows {
     } else {
 #pragma unroll 1
       for (int u = 0; u < NO; ++u) {
-        if (!RowAhead<NI>::value) ld_row<R, NI>(M, u, cur);
-        else if (u + 1 < NO) ld_row<R, NI>(M, u + 1, nxt);
+        if (!RowAhead<NI>::value) ld(u, cur);
+        else if (u + 1 < NO) ld(u + 1, nxt);
         body(u, cur);
         if (RowAhead<NI>::value) {
 #pragma unroll
@@ -953,9 +991,13 @@ __device__ __forceinline__ void gather_ip(const TermCtx &a, int off, int nfib, l
         x[j][k] = Cx<R>::make((R)v.x, (R)v.y);
       }
     }
-    Rows<R, NI, NO> rows(M);
+    // the outputs of one fiber are contiguous: rows visited in a per-lane
+    // rotated order keep the stores free of LDS bank conflicts
+    const int sk = fiber_skew<NO, (int)sizeof(C)>();
+    Rows<R, NI, NO, true> rows(M, sk, 0);
     rows.prime();
     rows.run([&](int u, const R (&row)[NI]) {
+      const int uu = wrap_add(u, sk, NO);
 #pragma unroll
       for (int j = 0; j < FPT; ++j) {
         if (j >= nj) break;
@@ -965,7 +1007,7 @@ __device__ __forceinline__ void gather_ip(const TermCtx &a, int off, int nfib, l
           re = fma(row[k], x[j][k].x, re);
           im = fma(row[k], x[j][k].y, im);
         }
-        if (ok[j]) stc(out + fb[j] * NO + u, Cx<R>::make(re, im));
+        if (ok[j]) stc(out + fb[j] * NO + uu, Cx<R>::make(re, im));
       }
     });
   }
@@ -1029,57 +1071,75 @@ __device__ __forceinline__ void pot_g2b0_ip(const TermHdr &T, lds_p<typename Cx<
   const int l0 = T.lev(0);
   const int nj = min(FPT, (nfib + G::N - 1) / G::N);
   bool ok[FPT];
-  int fb[FPT];
+  int fb[FPT], rem[FPT];
   R A[FPT], B[FPT], Cl[FPT];
+  R xq[FPT][kMaxActive];
+  {
+    const R c0 = cf[0], al0 = cf[1], be0 = cf[2];
 #pragma unroll
-  for (int j = 0; j < FPT; ++j) {
-    if (j >= nj) break;
-    const int f = G::tid() + j * G::N;
-    ok[j] = f < nfib;
-    fb[j] = ok[j] ? f : 0;
-    // the fiber's coordinates along modes 1.., and its A, B, C
-    R xq[kMaxActive];
-    int rem = fb[j];
-    A[j] = cf[0];
-    B[j] = cf[1];
-    Cl[j] = cf[2];
+    for (int j = 0; j < FPT; ++j) {
+      const int f = G::tid() + j * G::N;
+      ok[j] = f < nfib && j < nj;
+      fb[j] = ok[j] ? f : 0;
+      rem[j] = fb[j];
+      A[j] = c0;
+      B[j] = al0;
+      Cl[j] = be0;
+    }
+  }
+  // the fibers' coordinates along modes 1.. and their A, B, C; each
+  // coefficient is read once for all of the thread's fibers
 #pragma unroll
-    for (int q = 1; q < kMaxActive; ++q) {
-      if (q >= na) break;
-      const int hi = fdiv(rem, T.rcp_nq(q));
-      const int uq = rem - hi * T.nq(q);
-      rem = hi;
-      const int lq = T.lev(q);
-      xq[q] = lt[std_table_base(lq) + 2 * (2 * lq + 1) * (2 * lq + 2) + uq];
-      const R x2 = xq[q] * xq[q];
-      A[j] = fma(cf[2 + q], x2, A[j]);
-      A[j] = fma(cf[9 + q], xq[q], A[j]);
-      B[j] = fma(cf[16 + q], x2, B[j]);
-      Cl[j] = fma(cf[23 + q], x2, Cl[j]);
+  for (int q = 1; q < kMaxActive; ++q) {
+    if (q >= na) break;
+    const float rq = T.rcp_nq(q);
+    const int nq = T.nq(q);
+    const int lq = T.lev(q);
+    const lds_p<const R> xn = lt + std_table_base(lq) + 2 * (2 * lq + 1) * (2 * lq + 2);
+    const R alq = cf[2 + q], beq = cf[9 + q], c0q = cf[16 + q], k0q = cf[23 + q];
 #pragma unroll
-      for (int r = 1; r < q; ++r) {   // pair (r, q), r < q
-        const R cqr = cf[coef_pair(r, q)], kqr = cf[coef_pair(r, q) + 1];
-        A[j] = fma(cqr * (xq[r] * xq[r]), x2, A[j]);
-        A[j] = fma(kqr * x2, xq[r], A[j]);
+    for (int j = 0; j < FPT; ++j) {
+      if (j >= nj) break;
+      const int hi = fdiv(rem[j], rq);
+      const int uq = rem[j] - hi * nq;
+      rem[j] = hi;
+      xq[j][q] = xn[uq];
+      const R x2 = xq[j][q] * xq[j][q];
+      A[j] = fma(alq, x2, A[j]);
+      A[j] = fma(beq, xq[j][q], A[j]);
+      B[j] = fma(c0q, x2, B[j]);
+      Cl[j] = fma(k0q, x2, Cl[j]);
+    }
+#pragma unroll
+    for (int r = 1; r < q; ++r) {   // pair (r, q), r < q
+      const R cqr = cf[coef_pair(r, q)], kqr = cf[coef_pair(r, q) + 1];
+#pragma unroll
+      for (int j = 0; j < FPT; ++j) {
+        if (j >= nj) break;
+        const R x2 = xq[j][q] * xq[j][q];
+        A[j] = fma(cqr * (xq[j][r] * xq[j][r]), x2, A[j]);
+        A[j] = fma(kqr * x2, xq[j][r], A[j]);
       }
     }
   }
+  // fiber entries in a per-lane rotated order (free of LDS bank conflicts):
+  // slot k holds entry (k + sk) mod NQ, with its node and matrix column
+  const int sk = fiber_skew<NQ, (int)sizeof(C)>();
   const lds_p<const R> x0 = lt + std_table_base(l0) + 2 * NB * NQ;
-  R xn[NQ];
-#pragma unroll
-  for (int k = 0; k < NQ; ++k) xn[k] = x0[k];
   C x[FPT][NQ];
 #pragma unroll
   for (int j = 0; j < FPT; ++j) {
     if (j >= nj) break;
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
-      const C v = ldc<C>(buf + fb[j] * NQ + k);
-      const R V = fma(fma(B[j], xn[k], Cl[j]), xn[k], A[j]);
+      const int kk = wrap_add(k, sk, NQ);
+      const C v = ldc<C>(buf + fb[j] * NQ + kk);
+      const R xv = x0[kk];
+      const R V = fma(fma(B[j], xv, Cl[j]), xv, A[j]);
       x[j][k] = Cx<R>::make(V * v.x, V * v.y);
     }
   }
-  Rows<R, NQ, NB> rows(lt + std_table_base(l0) + NB * NQ);
+  Rows<R, NQ, NB, true> rows(lt + std_table_base(l0) + NB * NQ, 0, sk);
   rows.prime();
   if (!STORE) G::sync();
   rows.run([&](int v, const R (&row)[NQ]) {

@@ -487,7 +487,22 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
   h.n_long_rows = (int64_t)h.rows.size();
   for (int64_t r = 0; r < h.ncs; ++r)
     if (h.inv_ptr[r + 1] - h.inv_ptr[r] <= kLongRow) h.rows.push_back((int32_t)r);
-  h.n_items = h.n_long_rows + (h.ncs - h.n_long_rows + kShortLanes - 1) / kShortLanes;
+  h.n_items = (h.ncs - h.n_long_rows + kShortLanes - 1) / kShortLanes;
+  for (int64_t q = 0; q < h.n_long_rows; ++q) {
+    const int64_t len = h.inv_ptr[h.rows[q] + 1] - h.inv_ptr[h.rows[q]];
+    h.n_items += (len + kRowChunk - 1) / kRowChunk;
+  }
+  // the inverse CSR in that row order: the reduce loads a row's id and its
+  // bounds at the same index, in parallel
+  h.red_ptr.assign(h.ncs + 1, 0);
+  h.red_col.clear();
+  h.red_col.reserve(h.inv_col.size());
+  for (int64_t i = 0; i < h.ncs; ++i) {
+    const int32_t r = h.rows[i];
+    h.red_col.insert(h.red_col.end(), h.inv_col.begin() + h.inv_ptr[r],
+                     h.inv_col.begin() + h.inv_ptr[r + 1]);
+    h.red_ptr[i + 1] = (int32_t)h.red_col.size();
+  }
   return SG_OK;
 }
 
