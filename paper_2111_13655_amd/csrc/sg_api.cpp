@@ -97,6 +97,7 @@ void release(sg_problem *p) {
   hipFree(p->d_tm);
   hipFree(p->d_work);
   hipFree(p->d_partials);
+  hipFree(p->d_abc);
   hipFree(p->d_rpart);
   hipFree(p->d_rcnt);
   hipFree(p->d_cheb_a);
@@ -161,6 +162,7 @@ int64_t estimate_device_bytes(const Compiled &h) {
   return (int64_t)h.terms.size() * (int64_t)sizeof(TermDev) + (int64_t)h.pairs.size() * 8 + (int64_t)h.potc.size() * 8 +
          ns * 4 * 2 + (h.ncs + 1) * 4 + h.ncs * 4 + h.ncs * 8 + ns * 16 + 4 * h.ncs * 16 +
          4 * std::max<int64_t>(h.n_items, 256) * 8 + 4 * std::max<int64_t>(h.n_long_rows, 1) +
+         6 * std::max<int64_t>(h.nfib, 1) * 8 +
          (int64_t)h.tables.size() * 20 +
          (int64_t)sizeof(double) * (kMaxChebTerms + 8);
 }
@@ -190,6 +192,17 @@ sg_status upload_problem(sg_problem *p, sg_problem **out) {
   SG_UP(d_potc, h.potc)
   SG_UP(d_h0, h.h0)
 #undef SG_UP
+  {
+    // per-fiber coefficients of the split coupling potential, both variants
+    const size_t abc_bytes = 6 * (size_t)std::max<int64_t>(h.nfib, 1) * sizeof(double);
+    e = hipMalloc((void **)&p->d_abc, abc_bytes);
+    if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
+    bytes += (int64_t)abc_bytes;
+    e = launch_fiber_coeffs(p->d_terms, h.nterms, p->d_potc, p->d_tables, p->d_tables32r,
+                            p->d_abc, h.nfib, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) { release(p); return hip_fail(e, "per-fiber potential coefficients"); }
+  }
   size_t tm_bytes = (size_t)ns * sizeof(double2);
   e = hipMalloc((void **)&p->d_tm, tm_bytes);
   if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation of the term-major buffer failed"); }

@@ -42,6 +42,7 @@ struct alignas(16) TermDev {
   int32_t nq[kMaxActive];   //   grid size
   float rcp_nq[kMaxActive]; //   1/nq for fast index division
   double coeff;             // D_l
+  int32_t foff;             // first mode-0 fiber of the term in the per-fiber arrays
   // ---- end of header ----
   int32_t mode[kMaxActive]; // mode ids of the active modes
   int32_t bt[kMaxActive];   // offsets of each level's tables in the table array
@@ -58,8 +59,9 @@ struct alignas(16) TermDev {
   double kin[kMaxActive];          // -1/2 omega_p (kinetic prefactor)
 };
 constexpr int kPotFull = 0, kPotSplit = 1, kPotSplitRounded = 2;
-constexpr int kTermHdrDwords = 38;
-static_assert(offsetof(TermDev, coeff) == 4 * (kTermHdrDwords - 2), "term header layout");
+constexpr int kTermHdrDwords = 39;
+static_assert(offsetof(TermDev, coeff) == 4 * (kTermHdrDwords - 3), "term header layout");
+static_assert(offsetof(TermDev, foff) == 4 * (kTermHdrDwords - 1), "term header layout");
 static_assert(offsetof(TermDev, lev) == 16 && offsetof(TermDev, nb) == 48 &&
                   offsetof(TermDev, nq) == 80 && offsetof(TermDev, rcp_nq) == 112,
               "term header layout");
@@ -104,6 +106,11 @@ struct InstDev {
   const double *tab64;      // one-mode tables, exact
   const float *tab32;       // the same in FP32
   const double *tab32r;     // FP32-rounded, held in FP64
+  // Per mode-0 fiber of every term with active modes (fiber f of term t at
+  // t.foff + f): the split coupling potential along the fiber is
+  // A + x0 (C + B x0).  [2 variants: exact, FP32-rounded][A, B, C][nfib]
+  const double *abc;
+  int64_t nfib;
   double2 *tm;              // term-major results
   double2 *x0, *x1;         // apply: x0 -> x1.  Chebyshev: phi buffers, x0 = psi
   double2 *acc;             // Chebyshev running sum
@@ -210,6 +217,7 @@ struct Compiled {
   std::vector<TermDev> terms;        // [nterms]
   std::vector<double> pairs;         // [nterms][kMaxPairs][2]: c_pq, k_pq of active pairs
   std::vector<double> potc;          // [nterms][2][kCoefStride]: split coefficient blocks
+  int64_t nfib = 0;                  // mode-0 fibers over all terms with active modes
   std::vector<float> tables32;       // the same tables in FP32 (mixed path)
   std::vector<double> tables32r;     // FP32-rounded tables held in FP64 (mixed-path
                                      // FP64 terms: same operator as the FP32 terms)
@@ -279,6 +287,7 @@ struct sg_problem {
   double *d_tables = nullptr;
   double *d_pairs = nullptr;       // [nterms][kPairStride]
   double *d_potc = nullptr;        // [nterms][2][kCoefStride]
+  double *d_abc = nullptr;         // [2][3][nfib] per-fiber potential coefficients
   double *d_h0 = nullptr;
   // work buffers
   double2 *d_tm = nullptr;         // term-major results [N_s]
@@ -365,6 +374,11 @@ inline bool split_form(const Plan *pl, sg_precision prec) {
   return prec == SG_MIXED || pl->fp64_split;
 }
 hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s);
+// Fills abc ([2][3][nfib]) from the term records, coefficient blocks and
+// one-mode tables of one problem (device pointers).
+hipError_t launch_fiber_coeffs(const TermDev *terms, int64_t nterms, const double *potc,
+                               const double *tab64, const double *tab32r, double *abc,
+                               int64_t nfib, hipStream_t s);
 hipError_t launch_reduce(const Plan *pl, const LaunchCtl &c, hipStream_t s);
 hipError_t launch_finalize(const Plan *pl, hipStream_t s);  // per-instance partials
 hipError_t launch_dot(const sg_problem *p, const double2 *a, const double2 *b,

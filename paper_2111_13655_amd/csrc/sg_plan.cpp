@@ -239,6 +239,8 @@ void inst_from_problem(const sg_problem *p, InstDev *d) {
   d->x1 = p->d_work + h.ncs;
   d->acc = p->d_work + 2 * h.ncs;
   d->partials = p->d_partials;
+  d->abc = p->d_abc;
+  d->nfib = p->h.nfib;
   d->rpart = p->d_rpart;
   d->rcnt = p->d_rcnt;
   d->result = p->d_result;

@@ -57,6 +57,8 @@ struct TermCtx {
   int pot;                   // kPotFull / kPotSplit / kPotSplitRounded
   int lt_off;                // byte offset of this term's tables in LDS
   glb_p<const double> pcoef; // the term's split coefficient block (variant chosen)
+  glb_p<const double> abc;   // per-fiber A, B, C (variant chosen; FP64 terms)
+  int64_t nfib;              // stride between the A, B and C arrays
 };
 
 struct SweepArgs {
@@ -123,6 +125,10 @@ struct BlockGroup {
 // range: f + 0.5 is at least 0.5 away from any multiple of d).
 __device__ __forceinline__ int fdiv(int f, float rcp) {
   return __float2int_rz(((float)f + 0.5f) * rcp);
+}
+// a * b for 0 <= a, b < 2^24 (full-rate 24-bit multiply)
+__device__ __forceinline__ int mul24(int a, int b) {
+  return (int)__umul24((unsigned)a, (unsigned)b);
 }
 
 // A wave-uniform pointer re-derived inside a divergent loop.  readfirstlane
@@ -820,6 +826,7 @@ struct TermHdr {
   __device__ __forceinline__ double coeff() const {
     return __hiloint2double(i32(37), i32(36));
   }
+  __device__ __forceinline__ int foff() const { return i32(38); }
 };
 __device__ __forceinline__ TermHdr load_hdr(cptr<TermDev> T) {
   const int lane = threadIdx.x & 63;
@@ -894,6 +901,28 @@ struct Rows {
       ld(0, cur);
     }
   }
+  // body(u, j, row) for every output row u and fiber slot j < nj: all rows of
+  // one fiber before the next when the rows are held whole (one guard per
+  // fiber), one row for all fibers at a time otherwise.
+  template <int FPT, typename Body>
+  __device__ __forceinline__ void for_outputs(int nj, Body &&body) {
+    if constexpr (kAll) {
+#pragma unroll
+      for (int j = 0; j < FPT; ++j) {
+        if (j >= nj) break;
+#pragma unroll
+        for (int u = 0; u < NO; ++u) body(u, j, all[u]);
+      }
+    } else {
+      run([&](int u, const R (&row)[NI]) {
+#pragma unroll
+        for (int j = 0; j < FPT; ++j) {
+          if (j >= nj) break;
+          body(u, j, row);
+        }
+      });
+    }
+  }
   // body(u, row) for u = 0..NO-1 in order
   template <typename Body>
   __device__ __forceinline__ void run(Body &&body) {
@@ -935,27 +964,23 @@ __device__ __forceinline__ void contract_ip(lds_p<typename Cx<R>::T> buf, lds_p<
     ok[j] = f < F;
     f = ok[j] ? f : 0;
     const int hi = fdiv(f, rcp);
-    const int lo = f - hi * stride;
-    const int ib = lo + hi * sNI;
-    ob[j] = lo + hi * sNO;
+    const int lo = f - mul24(hi, stride);
+    const int ib = lo + mul24(hi, sNI);
+    ob[j] = lo + mul24(hi, sNO);
 #pragma unroll
     for (int k = 0; k < NI; ++k) x[j][k] = ldc<C>(buf + ib + k * stride);
   }
   Rows<R, NI, NO> rows(M);
   rows.prime();
   G::sync();
-  rows.run([&](int u, const R (&row)[NI]) {
+  rows.template for_outputs<FPT>(nj, [&](int u, int j, const R (&row)[NI]) {
+    R re = 0, im = 0;
 #pragma unroll
-    for (int j = 0; j < FPT; ++j) {
-      if (j >= nj) break;
-      R re = 0, im = 0;
-#pragma unroll
-      for (int k = 0; k < NI; ++k) {
-        re = fma(row[k], x[j][k].x, re);
-        im = fma(row[k], x[j][k].y, im);
-      }
-      if (ok[j]) stc(buf + ob[j] + u * stride, Cx<R>::make(re, im));
+    for (int k = 0; k < NI; ++k) {
+      re = fma(row[k], x[j][k].x, re);
+      im = fma(row[k], x[j][k].y, im);
     }
+    if (ok[j]) stc(buf + ob[j] + u * stride, Cx<R>::make(re, im));
   });
 }
 
@@ -996,19 +1021,14 @@ __device__ __forceinline__ void gather_ip(const TermCtx &a, int off, int nfib, l
     const int sk = fiber_skew<NO, (int)sizeof(C)>();
     Rows<R, NI, NO, true> rows(M, sk, 0);
     rows.prime();
-    rows.run([&](int u, const R (&row)[NI]) {
-      const int uu = wrap_add(u, sk, NO);
+    rows.template for_outputs<FPT>(nj, [&](int u, int j, const R (&row)[NI]) {
+      R re = 0, im = 0;
 #pragma unroll
-      for (int j = 0; j < FPT; ++j) {
-        if (j >= nj) break;
-        R re = 0, im = 0;
-#pragma unroll
-        for (int k = 0; k < NI; ++k) {
-          re = fma(row[k], x[j][k].x, re);
-          im = fma(row[k], x[j][k].y, im);
-        }
-        if (ok[j]) stc(out + fb[j] * NO + uu, Cx<R>::make(re, im));
+      for (int k = 0; k < NI; ++k) {
+        re = fma(row[k], x[j][k].x, re);
+        im = fma(row[k], x[j][k].y, im);
       }
+      if (ok[j]) stc(out + fb[j] * NO + wrap_add(u, sk, NO), Cx<R>::make(re, im));
     });
   }
 }
@@ -1037,18 +1057,14 @@ __device__ __forceinline__ void g2b_ip(lds_p<typename Cx<R>::T> in, Out o, lds_p
     }
     Rows<R, NI, NO> rows(M);
     rows.prime();
-    rows.run([&](int u, const R (&row)[NI]) {
+    rows.template for_outputs<FPT>(nj, [&](int u, int j, const R (&row)[NI]) {
+      R re = 0, im = 0;
 #pragma unroll
-      for (int j = 0; j < FPT; ++j) {
-        if (j >= nj) break;
-        R re = 0, im = 0;
-#pragma unroll
-        for (int k = 0; k < NI; ++k) {
-          re = fma(row[k], x[j][k].x, re);
-          im = fma(row[k], x[j][k].y, im);
-        }
-        if (ok[j]) stc(o.tm + lo[j] + u * stride, Z64{cf * (double)re, cf * (double)im});
+      for (int k = 0; k < NI; ++k) {
+        re = fma(row[k], x[j][k].x, re);
+        im = fma(row[k], x[j][k].y, im);
       }
+      if (ok[j]) stc(o.tm + lo[j] + u * stride, Z64{cf * (double)re, cf * (double)im});
     });
   }
 }
@@ -1061,10 +1077,42 @@ __device__ __forceinline__ void g2b_ip(lds_p<typename Cx<R>::T> in, Out o, lds_p
 // is the only active mode and the outputs, times D_l, go to HBM; otherwise
 // they overwrite the fibers in place (at most inplace_fpt(NQ) fibers per
 // thread).
+// The A, B, C of the mode-0 fibers a thread takes in the first grid -> basis
+// contraction (fiber tid + j N), read from the per-problem arrays; FP64
+// terms issue these loads before the group sync that ends basis -> grid.
+template <typename R, int FPT>
+struct FiberABC {
+  R A[FPT], B[FPT], C[FPT];
+  bool have = false;
+};
+template <typename G, typename R, int NQ>
+__device__ __forceinline__ FiberABC<R, inplace_fpt(NQ)> load_abc(const TermCtx &a,
+                                                                 const TermHdr &T, int nfib) {
+  constexpr int FPT = inplace_fpt(NQ);
+  FiberABC<R, FPT> r;
+  if constexpr (sizeof(R) == sizeof(double)) {
+    const int nj = min(FPT, (nfib + G::N - 1) / G::N);
+    const glb_p<const double> A = a.abc + T.foff();
+    const glb_p<const double> B = A + a.nfib, Cc = B + a.nfib;
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      if (j >= nj) break;
+      const int f = G::tid() + j * G::N;
+      const int fi = f < nfib ? f : 0;
+      r.A[j] = A[fi];
+      r.B[j] = B[fi];
+      r.C[j] = Cc[fi];
+    }
+    r.have = true;
+  }
+  return r;
+}
+
 template <typename G, typename R, int NQ, int NB, bool STORE>
 __device__ __forceinline__ void pot_g2b0_ip(const TermHdr &T, lds_p<typename Cx<R>::T> buf,
                                             lds_p<const R> lt, lds_p<const R> cf, int nfib,
-                                            Out o, double dl) {
+                                            Out o, double dl,
+                                            const FiberABC<R, inplace_fpt(NQ)> &pre) {
   typedef typename Cx<R>::T C;
   constexpr int FPT = inplace_fpt(NQ);
   const int na = T.na();
@@ -1074,7 +1122,17 @@ __device__ __forceinline__ void pot_g2b0_ip(const TermHdr &T, lds_p<typename Cx<
   int fb[FPT], rem[FPT];
   R A[FPT], B[FPT], Cl[FPT];
   R xq[FPT][kMaxActive];
-  {
+  if (pre.have) {
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      const int f = G::tid() + j * G::N;
+      ok[j] = f < nfib && j < nj;
+      fb[j] = ok[j] ? f : 0;
+      A[j] = pre.A[j];
+      B[j] = pre.B[j];
+      Cl[j] = pre.C[j];
+    }
+  } else {
     const R c0 = cf[0], al0 = cf[1], be0 = cf[2];
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
@@ -1086,39 +1144,39 @@ __device__ __forceinline__ void pot_g2b0_ip(const TermHdr &T, lds_p<typename Cx<
       B[j] = al0;
       Cl[j] = be0;
     }
-  }
-  // the fibers' coordinates along modes 1.. and their A, B, C; each
-  // coefficient is read once for all of the thread's fibers
+    // the fibers' coordinates along modes 1.. and their A, B, C; each
+    // coefficient is read once for all of the thread's fibers
 #pragma unroll
-  for (int q = 1; q < kMaxActive; ++q) {
-    if (q >= na) break;
-    const float rq = T.rcp_nq(q);
-    const int nq = T.nq(q);
-    const int lq = T.lev(q);
-    const lds_p<const R> xn = lt + std_table_base(lq) + 2 * (2 * lq + 1) * (2 * lq + 2);
-    const R alq = cf[2 + q], beq = cf[9 + q], c0q = cf[16 + q], k0q = cf[23 + q];
-#pragma unroll
-    for (int j = 0; j < FPT; ++j) {
-      if (j >= nj) break;
-      const int hi = fdiv(rem[j], rq);
-      const int uq = rem[j] - hi * nq;
-      rem[j] = hi;
-      xq[j][q] = xn[uq];
-      const R x2 = xq[j][q] * xq[j][q];
-      A[j] = fma(alq, x2, A[j]);
-      A[j] = fma(beq, xq[j][q], A[j]);
-      B[j] = fma(c0q, x2, B[j]);
-      Cl[j] = fma(k0q, x2, Cl[j]);
-    }
-#pragma unroll
-    for (int r = 1; r < q; ++r) {   // pair (r, q), r < q
-      const R cqr = cf[coef_pair(r, q)], kqr = cf[coef_pair(r, q) + 1];
+    for (int q = 1; q < kMaxActive; ++q) {
+      if (q >= na) break;
+      const float rq = T.rcp_nq(q);
+      const int nq = T.nq(q);
+      const int lq = T.lev(q);
+      const lds_p<const R> xn = lt + std_table_base(lq) + 2 * (2 * lq + 1) * (2 * lq + 2);
+      const R alq = cf[2 + q], beq = cf[9 + q], c0q = cf[16 + q], k0q = cf[23 + q];
 #pragma unroll
       for (int j = 0; j < FPT; ++j) {
         if (j >= nj) break;
+        const int hi = fdiv(rem[j], rq);
+        const int uq = rem[j] - hi * nq;
+        rem[j] = hi;
+        xq[j][q] = xn[uq];
         const R x2 = xq[j][q] * xq[j][q];
-        A[j] = fma(cqr * (xq[j][r] * xq[j][r]), x2, A[j]);
-        A[j] = fma(kqr * x2, xq[j][r], A[j]);
+        A[j] = fma(alq, x2, A[j]);
+        A[j] = fma(beq, xq[j][q], A[j]);
+        B[j] = fma(c0q, x2, B[j]);
+        Cl[j] = fma(k0q, x2, Cl[j]);
+      }
+#pragma unroll
+      for (int r = 1; r < q; ++r) {   // pair (r, q), r < q
+        const R cqr = cf[coef_pair(r, q)], kqr = cf[coef_pair(r, q) + 1];
+#pragma unroll
+        for (int j = 0; j < FPT; ++j) {
+          if (j >= nj) break;
+          const R x2 = xq[j][q] * xq[j][q];
+          A[j] = fma(cqr * (xq[j][r] * xq[j][r]), x2, A[j]);
+          A[j] = fma(kqr * x2, xq[j][r], A[j]);
+        }
       }
     }
   }
@@ -1142,20 +1200,16 @@ __device__ __forceinline__ void pot_g2b0_ip(const TermHdr &T, lds_p<typename Cx<
   Rows<R, NQ, NB, true> rows(lt + std_table_base(l0) + NB * NQ, 0, sk);
   rows.prime();
   if (!STORE) G::sync();
-  rows.run([&](int v, const R (&row)[NQ]) {
+  rows.template for_outputs<FPT>(nj, [&](int v, int j, const R (&row)[NQ]) {
+    R re = 0, im = 0;
 #pragma unroll
-    for (int j = 0; j < FPT; ++j) {
-      if (j >= nj) break;
-      R re = 0, im = 0;
-#pragma unroll
-      for (int k = 0; k < NQ; ++k) {
-        re = fma(row[k], x[j][k].x, re);
-        im = fma(row[k], x[j][k].y, im);
-      }
-      if (ok[j]) {
-        if (STORE) stc(o.tm + fb[j] * NB + v, Z64{dl * (double)re, dl * (double)im});
-        else stc(buf + fb[j] * NB + v, Cx<R>::make(re, im));
-      }
+    for (int k = 0; k < NQ; ++k) {
+      re = fma(row[k], x[j][k].x, re);
+      im = fma(row[k], x[j][k].y, im);
+    }
+    if (ok[j]) {
+      if (STORE) stc(o.tm + fb[j] * NB + v, Z64{dl * (double)re, dl * (double)im});
+      else stc(buf + fb[j] * NB + v, Cx<R>::make(re, im));
     }
   });
 }
@@ -1207,21 +1261,29 @@ __device__ __forceinline__ void run_term_inplace(const TermCtx &a, const TermHdr
     for (int p = 1; p < na; ++p) {
       nouter /= T.nb(p);
       contract_ip_level<G, R>(0, T.lev(p), buf, lt, stride, nouter);
-      G::sync();
+      if (p + 1 < na) G::sync();   // the last sync follows the A, B, C loads
       stride *= T.nq(p);
     }
   }
   const int nfib = ngrid / T.nq(0);
   if (na == 1) {
 #define SG_P1CASE(L_, NB_, NQ_)                                                  \
-  case L_: pot_g2b0_ip<G, R, NQ_, NB_, true>(T, buf, lt, coef, nfib, Out{a.tm + off}, cf); break;
+  case L_:                                                                      \
+    pot_g2b0_ip<G, R, NQ_, NB_, true>(T, buf, lt, coef, nfib, Out{a.tm + off}, cf,   \
+                                      FiberABC<R, inplace_fpt(NQ_)>{});             \
+    break;
     switch (l0) { SG_LEVELS(SG_P1CASE) default: break; }
 #undef SG_P1CASE
     return;
   }
 #define SG_PCASE(L_, NB_, NQ_)                                                   \
-  case L_: pot_g2b0_ip<G, R, NQ_, NB_, false>(T, buf, lt, coef, nfib, Out{a.tm + off}, cf); break;
-  switch (l0) { SG_LEVELS(SG_PCASE) default: break; }
+  case L_: {                                                                    \
+    const auto pre = load_abc<G, R, NQ_>(a, T, nfib);                           \
+    G::sync();                                                                  \
+    pot_g2b0_ip<G, R, NQ_, NB_, false>(T, buf, lt, coef, nfib, Out{a.tm + off}, cf, pre); \
+    break;                                                                      \
+  }
+  switch (l0) { SG_LEVELS(SG_PCASE) default: G::sync(); break; }
 #undef SG_PCASE
   G::sync();
   {
@@ -1288,6 +1350,8 @@ __device__ __forceinline__ TermCtx make_ctx(const SweepArgs &a, cptr<InstDev> I,
   else c.tab = r32 ? (const void *)I->tab32r : (const void *)I->tab64;
   c.lt_off = (sizeof(R) == sizeof(double) && r32) ? a.tab_a : 0;
   c.pcoef = (glb_p<const double>)(I->potc + ((size_t)t * 2 + (r32 ? 1 : 0)) * kCoefStride);
+  c.abc = (glb_p<const double>)(I->abc + (r32 ? 3 * I->nfib : 0));
+  c.nfib = I->nfib;
   return c;
 }
 
@@ -1365,6 +1429,61 @@ hipError_t launch_packs(const SweepArgs &a, const PackSet &ps, hipStream_t s, hi
 }
 
 }  // namespace
+
+// The per-fiber A, B, C of the split coupling potential along the mode-0
+// fibers of every term, for both coefficient variants (exact, and the
+// FP32-rounded coefficients and nodes): the sums the in-kernel form takes,
+// once per problem.  Nodes come from the problem's one-mode tables.
+__global__ __launch_bounds__(256) void fiber_coeff_kernel(const TermDev *terms,
+                                                          const double *potc,
+                                                          const double *tab64,
+                                                          const double *tab32r, double *abc,
+                                                          int64_t nfib) {
+  const int64_t t = blockIdx.x;
+  const TermDev &T = terms[t];
+  const int na = T.na;
+  if (na == 0) return;
+  const int nf = T.ngrid / T.nq[0];
+  for (int v = 0; v < 2; ++v) {
+    const double *cf = potc + ((size_t)t * 2 + v) * kCoefStride;
+    const double *tab = v ? tab32r : tab64;
+    double *A = abc + (size_t)v * 3 * nfib + T.foff;
+    double *B = A + nfib, *Cc = B + nfib;
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+      double xq[kMaxActive] = {};
+      int rem = f;
+      double va = cf[0], vb = cf[1], vc = cf[2];
+      for (int q = 1; q < na; ++q) {
+        const int hi = rem / T.nq[q];
+        const int uq = rem - hi * T.nq[q];
+        rem = hi;
+        xq[q] = tab[T.xo[q] + uq];
+        const double x2 = xq[q] * xq[q];
+        va = fma(cf[2 + q], x2, va);
+        va = fma(cf[9 + q], xq[q], va);
+        vb = fma(cf[16 + q], x2, vb);
+        vc = fma(cf[23 + q], x2, vc);
+        for (int r = 1; r < q; ++r) {
+          const double cqr = cf[coef_pair(r, q)], kqr = cf[coef_pair(r, q) + 1];
+          va = fma(cqr * (xq[r] * xq[r]), x2, va);
+          va = fma(kqr * x2, xq[r], va);
+        }
+      }
+      A[f] = va;
+      B[f] = vb;
+      Cc[f] = vc;
+    }
+  }
+}
+
+hipError_t launch_fiber_coeffs(const TermDev *terms, int64_t nterms, const double *potc,
+                               const double *tab64, const double *tab32r, double *abc,
+                               int64_t nfib, hipStream_t s) {
+  if (nterms <= 0 || nfib <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fiber_coeff_kernel, dim3((unsigned)nterms), dim3(256), 0, s, terms, potc,
+                     tab64, tab32r, abc, nfib);
+  return hipGetLastError();
+}
 
 hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   SweepArgs a;

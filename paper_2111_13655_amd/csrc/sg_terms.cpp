@@ -24,6 +24,7 @@
 //           + sum_{p<q active} (c Q_p^2 Q_q^2 + k Q_p^2 Q_q),
 // identical (up to rounding) to the literal per-term sweep over all modes.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -335,6 +336,7 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
   h.potc.assign((size_t)h.nterms * 2 * kCoefStride, 0.0);
   h.grid_literal = h.grid_active = h.max_basis = h.max_grid = 0;
   h.flops_fp64 = h.flops_mixed = 0.0;
+  h.nfib = 0;
   std::vector<double> cost(h.nterms);
   for (int64_t t = 0; t < h.nterms; ++t) {
     TermDev &T = h.terms[t];
@@ -371,6 +373,10 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
     for (size_t p = act.size(); p < (size_t)kMaxActive; ++p) {
       T.nb[p] = T.nq[p] = 1;
       T.rcp_nq[p] = 1.0f;
+    }
+    if (!act.empty()) {
+      T.foff = (int32_t)h.nfib;
+      h.nfib += ngr / T.nq[0];
     }
     auto r32 = [](double v) { return (double)(float)v; };
     double *pr = &h.pairs[(size_t)t * kPairStride];
@@ -476,6 +482,10 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
   h.tables32r.assign(h.tables32.begin(), h.tables32.end());
   if (h.max_grid > 65536) {
     *err = "a term grid exceeds 65536 points";
+    return SG_EINVAL;
+  }
+  if (h.nfib > INT32_MAX) {
+    *err = "too many grid fibers for 32-bit offsets";
     return SG_EINVAL;
   }
 
