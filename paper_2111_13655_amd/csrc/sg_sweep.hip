@@ -58,6 +58,7 @@ struct TermCtx {
   int lt_off;                // byte offset of this term's tables in LDS
   glb_p<const double> pcoef; // the term's split coefficient block (variant chosen)
   glb_p<const double> abc;   // per-fiber A, B, C (variant chosen; FP64 terms)
+  const void *gtab;          // the standard-map tables in HBM (variant chosen)
   int64_t nfib;              // stride between the A, B and C arrays
 };
 
@@ -984,6 +985,64 @@ __device__ __forceinline__ void contract_ip(lds_p<typename Cx<R>::T> buf, lds_p<
   });
 }
 
+// Two consecutive in-place contractions along level-1 modes p and p+1 (the
+// same one-mode matrix M, NO x NI, for both) in one step: a thread takes a
+// whole NI x NI input slab (one per thread: the caller checks that the slabs
+// fit), keeps the intermediate in registers and writes the NO x NO outputs.
+// Layout: in[lo + stride*(k1 + NI*(k2 + NI*hi))] ->
+// out[lo + stride*(u1 + NO*(u2 + NO*hi))].  M is read with scalar loads.
+template <typename G, typename R, int NI, int NO>
+__device__ __forceinline__ void contract2_ip(lds_p<typename Cx<R>::T> buf, cptr<R> Ms, int stride,
+                                             int nouter) {
+  typedef typename Cx<R>::T C;
+  const int F = stride * nouter;
+  const float rcp = 1.0f / (float)stride;
+  int f = G::tid();
+  const bool ok = f < F;
+  f = ok ? f : 0;
+  const int hi = fdiv(f, rcp);
+  const int lo = f - mul24(hi, stride);
+  const int ib = lo + mul24(hi, stride * NI * NI);
+  const int ob = lo + mul24(hi, stride * NO * NO);
+  C x[NI][NI];
+#pragma unroll
+  for (int k2 = 0; k2 < NI; ++k2)
+#pragma unroll
+    for (int k1 = 0; k1 < NI; ++k1) x[k2][k1] = ldc<C>(buf + ib + stride * (k1 + NI * k2));
+  R m[NO][NI];
+#pragma unroll
+  for (int u = 0; u < NO; ++u)
+#pragma unroll
+    for (int k = 0; k < NI; ++k) m[u][k] = Ms[u * NI + k];
+  G::sync();
+  if (!ok) return;
+#pragma unroll
+  for (int u1 = 0; u1 < NO; ++u1) {
+    // t[k2] = sum_k1 M[u1][k1] x[k2][k1]: mode p done for output u1
+    C t[NI];
+#pragma unroll
+    for (int k2 = 0; k2 < NI; ++k2) {
+      R re = 0, im = 0;
+#pragma unroll
+      for (int k1 = 0; k1 < NI; ++k1) {
+        re = fma(m[u1][k1], x[k2][k1].x, re);
+        im = fma(m[u1][k1], x[k2][k1].y, im);
+      }
+      t[k2] = Cx<R>::make(re, im);
+    }
+#pragma unroll
+    for (int u2 = 0; u2 < NO; ++u2) {
+      R re = 0, im = 0;
+#pragma unroll
+      for (int k2 = 0; k2 < NI; ++k2) {
+        re = fma(m[u2][k2], t[k2].x, re);
+        im = fma(m[u2][k2], t[k2].y, im);
+      }
+      stc(buf + ob + stride * (u1 + NO * u2), Cx<R>::make(re, im));
+    }
+  }
+}
+
 template <typename G, typename R, int NI, int NO>
 __device__ __forceinline__ void gather_ip(const TermCtx &a, int off, int nfib, lds_p<const R> M,
                                           lds_p<typename Cx<R>::T> out) {
@@ -1258,11 +1317,20 @@ __device__ __forceinline__ void run_term_inplace(const TermCtx &a, const TermHdr
     G::sync();
     int stride = nq0;
     int nouter = nbasis / nb0;
-    for (int p = 1; p < na; ++p) {
-      nouter /= T.nb(p);
-      contract_ip_level<G, R>(0, T.lev(p), buf, lt, stride, nouter);
-      if (p + 1 < na) G::sync();   // the last sync follows the A, B, C loads
-      stride *= T.nq(p);
+    for (int p = 1; p < na;) {
+      // two level-1 modes in one step when every slab has a thread
+      if (p + 1 < na && T.lev(p) == 1 && T.lev(p + 1) == 1 && stride * (nouter / 9) <= G::N) {
+        nouter /= 9;
+        contract2_ip<G, R, 3, 4>(buf, (cptr<R>)a.gtab + std_table_base(1), stride, nouter);
+        stride *= 16;
+        p += 2;
+      } else {
+        nouter /= T.nb(p);
+        contract_ip_level<G, R>(0, T.lev(p), buf, lt, stride, nouter);
+        stride *= T.nq(p);
+        p += 1;
+      }
+      if (p < na) G::sync();   // the last sync follows the A, B, C loads
     }
   }
   const int nfib = ngrid / T.nq(0);
@@ -1289,11 +1357,20 @@ __device__ __forceinline__ void run_term_inplace(const TermCtx &a, const TermHdr
   {
     int stride = T.nb(0);
     int nouter = nfib;
-    for (int p = 1; p < na - 1; ++p) {
-      nouter /= T.nq(p);
-      contract_ip_level<G, R>(2, T.lev(p), buf, lt, stride, nouter);
+    for (int p = 1; p < na - 1;) {
+      if (p + 1 < na - 1 && T.lev(p) == 1 && T.lev(p + 1) == 1 &&
+          stride * (nouter / 16) <= G::N) {
+        nouter /= 16;
+        contract2_ip<G, R, 4, 3>(buf, (cptr<R>)a.gtab + std_table_base(1) + 12, stride, nouter);
+        stride *= 9;
+        p += 2;
+      } else {
+        nouter /= T.nq(p);
+        contract_ip_level<G, R>(2, T.lev(p), buf, lt, stride, nouter);
+        stride *= T.nb(p);
+        p += 1;
+      }
       G::sync();
-      stride *= T.nb(p);
     }
     const int p = na - 1;
     const int lp = T.lev(p);
@@ -1349,6 +1426,7 @@ __device__ __forceinline__ TermCtx make_ctx(const SweepArgs &a, cptr<InstDev> I,
   if (sizeof(R) == sizeof(float)) c.tab = I->tab32;
   else c.tab = r32 ? (const void *)I->tab32r : (const void *)I->tab64;
   c.lt_off = (sizeof(R) == sizeof(double) && r32) ? a.tab_a : 0;
+  c.gtab = (sizeof(R) == sizeof(double) && r32) ? a.stab_r : a.stab;
   c.pcoef = (glb_p<const double>)(I->potc + ((size_t)t * 2 + (r32 ? 1 : 0)) * kCoefStride);
   c.abc = (glb_p<const double>)(I->abc + (r32 ? 3 * I->nfib : 0));
   c.nfib = I->nfib;
