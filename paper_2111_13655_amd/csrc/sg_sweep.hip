@@ -1305,7 +1305,8 @@ __device__ __forceinline__ void run_term_inplace(const TermCtx &a, const TermHdr
   // the coefficient block, into LDS after the grid buffer (published by the
   // sync after the gather)
   const lds_p<R> coef = (lds_p<R>)(buf + ngrid);
-  for (int i = G::tid(); i < kCoefUsed; i += G::N) coef[i] = (R)a.pcoef[i];
+  if (sizeof(R) != sizeof(double) || na == 1)   // FP64 terms read A, B, C from HBM
+    for (int i = G::tid(); i < kCoefUsed; i += G::N) coef[i] = (R)a.pcoef[i];
   const int l0 = T.lev(0);
   {
     const int nb0 = T.nb(0), nq0 = T.nq(0);
@@ -1385,8 +1386,8 @@ __device__ __forceinline__ void run_term_inplace(const TermCtx &a, const TermHdr
 // One term: the scalar case, then the in-place or the ping-pong form (IP: the
 // launch holds in-place terms only, and the ping-pong form is not compiled in).
 template <typename G, typename R, typename P, bool IP>
-__device__ __forceinline__ void run_any(const TermCtx &a, cptr<TermDev> T, P base, int inplace,
-                                        char *lds_raw) {
+__device__ __forceinline__ void run_any(const TermCtx &a, cptr<TermDev> T, const TermHdr &hdr,
+                                        P base, int inplace, char *lds_raw) {
   if (T->na == 0) {
     if (G::tid() == 0) {
       const double c0 = T->c0[a.split ? kPotSplit : kPotFull];
@@ -1396,7 +1397,7 @@ __device__ __forceinline__ void run_any(const TermCtx &a, cptr<TermDev> T, P bas
     return;
   }
   if (IP || inplace)
-    run_term_inplace<G, R>(a, load_hdr(T), (lds_p<typename Cx<R>::T>)base,
+    run_term_inplace<G, R>(a, hdr, (lds_p<typename Cx<R>::T>)base,
                            (lds_p<const R>)(lds_raw + a.lt_off));
   else if constexpr (!IP) run_term<G, R, P>(a, T, base, T->ngrid);
 }
@@ -1439,6 +1440,18 @@ template <typename R, bool IP>
 __global__ __launch_bounds__(kThreads, 4) void sweep_kernel(SweepArgs a) {
   extern __shared__ char lds_raw[];
   typedef typename Cx<R>::T C;
+  // this wavefront's term (slot 0 of a one-term pack; unused slots of a wave
+  // pack hold instance 0, term 0) and its record header, loaded before the
+  // table copy so that their latency overlaps it
+  const cptr<PackDev> P = a.packs + blockIdx.x;
+  const int kind = P->block;
+  const int w = kind == kPackWaves ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
+  const bool has_term = kind != kPackWaves || w < P->n;
+  const cptr<InstDev> I = a.inst + P->inst[w];
+  const int t = P->term[w];
+  const cptr<TermDev> T = (cptr<TermDev>)(I->terms + t);
+  const TermHdr hdr = load_hdr(T);
+  const TermCtx c = make_ctx<R>(a, I, t);
   // the standard-map tables into LDS (every wavefront takes part)
   {
     const lds_p<Z64> dst = (lds_p<Z64>)lds_raw;
@@ -1449,38 +1462,25 @@ __global__ __launch_bounds__(kThreads, 4) void sweep_kernel(SweepArgs a) {
       stc(dst + i, i < na16 ? ldc<Z64>(sa + i) : ldc<Z64>(sb + (i - na16)));
     if (na16 + nb16 > 0) __syncthreads();
   }
+  if (!has_term || !live(a, I)) return;
   char *const pack_lds = lds_raw + a.tab_a + a.tab_b;
-  const cptr<PackDev> P = a.packs + blockIdx.x;
-  const int kind = P->block;
   if (kind != kPackWaves) {
-    const cptr<InstDev> I = a.inst + P->inst[0];
-    if (!live(a, I)) return;
-    const int t = P->term[0];
-    const cptr<TermDev> T = (cptr<TermDev>)(I->terms + t);
-    const TermCtx c = make_ctx<R>(a, I, t);
     if constexpr (IP) {
-      run_any<BlockGroup, R, lds_p<C>, true>(c, T, (lds_p<C>)pack_lds, 1, lds_raw);
+      run_any<BlockGroup, R, lds_p<C>, true>(c, T, hdr, (lds_p<C>)pack_lds, 1, lds_raw);
     } else {
       if (kind == kPackBlockLds)
-        run_any<BlockGroup, R, lds_p<C>, false>(c, T, (lds_p<C>)pack_lds, P->inplace[0],
+        run_any<BlockGroup, R, lds_p<C>, false>(c, T, hdr, (lds_p<C>)pack_lds, P->inplace[0],
                                                 lds_raw);
       else
-        run_any<BlockGroup, R, glb_p<C>, false>(c, T, (glb_p<C>)(a.scratch + P->scratch_off), 0,
+        run_any<BlockGroup, R, glb_p<C>, false>(c, T, hdr,
+                                                (glb_p<C>)(a.scratch + P->scratch_off), 0,
                                                 lds_raw);
     }
     return;
   }
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (w >= P->n) return;
-  const cptr<InstDev> I = a.inst + P->inst[w];
-  if (!live(a, I)) return;
-  const int t = P->term[w];
-  const cptr<TermDev> T = (cptr<TermDev>)(I->terms + t);
-  const TermCtx c = make_ctx<R>(a, I, t);
-  run_any<WaveGroup, R, lds_p<C>, IP>(c, T, (lds_p<C>)(pack_lds + P->lds_off[w]),
+  run_any<WaveGroup, R, lds_p<C>, IP>(c, T, hdr, (lds_p<C>)(pack_lds + P->lds_off[w]),
                                       P->inplace[w], lds_raw);
 }
-
 template <typename R, bool IP>
 hipError_t launch_packs_as(const SweepArgs &a, int npacks, int lds, hipStream_t s,
                            hipEvent_t ev0, hipEvent_t ev1) {
