@@ -153,6 +153,8 @@ struct PackDev {
   int32_t term[kPackTerms];
   int32_t lds_off[kPackTerms];  // byte offset of each wavefront's LDS slice
   int32_t inplace[kPackTerms];  // 1: in place (one buffer), 0: ping-pong
+  int32_t maxlev;               // highest level of an active mode of the pack's terms
+  int32_t pad;
   int64_t scratch_off;          // kPackBlockScratch: byte offset in the plan's scratch
 };
 struct PackSet {

@@ -34,6 +34,7 @@ struct Cand {
   int inplace;     // 1: one buffer, contractions in place
   int wave;        // 1: one wavefront can run it
   int64_t ngrid;
+  int maxlev;      // highest level of an active mode
 };
 
 // Does every in-place contraction of term T fit the registers of a group of
@@ -61,7 +62,8 @@ bool inplace_fits(const TermDev &T, int n) {
 // standard size maps); elem: bytes of one complex value.
 Cand make_cand(int32_t inst, int32_t term, const Compiled &h, bool split, int elem) {
   const TermDev &T = h.terms[term];
-  Cand c{inst, term, h.cost[term], 0, 0, 0, T.ngrid};
+  Cand c{inst, term, h.cost[term], 0, 0, 0, T.ngrid, 0};
+  for (int p = 0; p < T.na; ++p) c.maxlev = std::max<int>(c.maxlev, T.lev[p]);
   const bool std_maps = h.nbA == 1 && h.nbB == 2 && h.nqA == 2 && h.nqB == 2;
   const int64_t one = (int64_t)T.ngrid * elem;
   if (split && std_maps && T.na == 0) {
@@ -158,6 +160,7 @@ void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vect
     pk.term[pk.n] = c.term;
     pk.lds_off[pk.n] = (int32_t)bin_bytes[b.id];
     pk.inplace[pk.n] = c.inplace;
+    pk.maxlev = std::max<int32_t>(pk.maxlev, c.maxlev);
     bin_bytes[b.id] += c.slice;
     pk.n += 1;
     b.load += c.cost;
@@ -174,6 +177,7 @@ void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vect
     pk.inst[0] = c.inst;
     pk.term[0] = c.term;
     pk.inplace[0] = c.inplace;
+    pk.maxlev = c.maxlev;
     if (c.slice <= cap) {
       pk.block = kPackBlockLds;
       lds = std::max<int>(lds, (int)c.slice);

@@ -1452,14 +1452,18 @@ __global__ __launch_bounds__(kThreads, 4) void sweep_kernel(SweepArgs a) {
   const cptr<TermDev> T = (cptr<TermDev>)(I->terms + t);
   const TermHdr hdr = load_hdr(T);
   const TermCtx c = make_ctx<R>(a, I, t);
-  // the standard-map tables into LDS (every wavefront takes part)
+  // the standard-map tables into LDS (every wavefront takes part): the
+  // exact set at 0, the FP32-rounded FP64 set (if any) at tab_a, levels up to
+  // the pack's highest only
   {
     const lds_p<Z64> dst = (lds_p<Z64>)lds_raw;
     const glb_p<const Z64> sa = (glb_p<const Z64>)a.stab;
     const glb_p<const Z64> sb = (glb_p<const Z64>)a.stab_r;
-    const int na16 = a.tab_a >> 4, nb16 = a.tab_b >> 4;
+    const int pre = min(a.tab_a, (int)sizeof(R) * std_table_base(P->maxlev + 1));
+    const int na16 = (pre + 15) >> 4, nb16 = a.tab_b > 0 ? na16 : 0, off_b = a.tab_a >> 4;
     for (int i = threadIdx.x; i < na16 + nb16; i += kThreads)
-      stc(dst + i, i < na16 ? ldc<Z64>(sa + i) : ldc<Z64>(sb + (i - na16)));
+      stc(dst + (i < na16 ? i : off_b + (i - na16)),
+          i < na16 ? ldc<Z64>(sa + i) : ldc<Z64>(sb + (i - na16)));
     if (na16 + nb16 > 0) __syncthreads();
   }
   if (!has_term || !live(a, I)) return;
