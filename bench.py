@@ -30,7 +30,7 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 # Sources whose change invalidates recorded HBM counters of the sweep kernel.
 KERNEL_SOURCES = ["paper_2111_13655_amd/csrc/sg_sweep.hip", "paper_2111_13655_amd/csrc/sg_internal.h",
-                  "paper_2111_13655_amd/csrc/sg_plan.cpp"]
+                  "paper_2111_13655_amd/csrc/sg_plan.cpp", "paper_2111_13655_amd/csrc/sg_terms.cpp"]
 
 WORKLOADS = {
     "d6_l6_fp64": dict(D=6, L=6, dt=0.05, check_every=100, precision="fp64",
