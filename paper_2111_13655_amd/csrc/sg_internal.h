@@ -179,17 +179,20 @@ enum PackSetId { kSetGrid64 = 0, kSetSplit64 = 1, kSetMixed64 = 2, kSetMixed32 =
 // Rows of the inverse mapping longer than this are reduced by a whole
 // wavefront, shorter ones by a group of 8 lanes.
 constexpr int kLongRow = 64;
-// Long rows are summed in chunks of at most kRowChunk entries, one wavefront
-// each (spread over compute units); the last chunk to finish adds the chunk
-// sums in chunk order.
-constexpr int kRowChunk = 256;
+// Long rows are summed in chunks of at most kRowChunk entries, one workgroup
+// of kRowWaves wavefronts each (kRowChunk / kRowWaves entries per wavefront,
+// combined through LDS in wavefront order); a row of several chunks is
+// finished by the last chunk to arrive, which adds the chunk sums in chunk
+// order.
+constexpr int kRowWaves = 4;
+constexpr int kRowChunk = 1024;
 constexpr int kShortLanes = 8;
 // One reduce work item = one wavefront: a long row, or 8 short rows.
 struct RedItem {
   int32_t inst;
   int32_t first;    // index into the instance's row list
   int32_t local;    // item index inside the instance (partial-sum slot)
-  int32_t chunk;    // long rows: chunk | (number of chunks << 16); short rows: 0
+  int32_t chunk;    // long rows: chunk | (chunks << 12) | (wavefront << 24); short: 0
 };
 
 // Host-side term compiler output.

@@ -13,8 +13,9 @@
 // computed by the same code whatever its pack, so results do not depend on
 // the mix.
 //
-// Reduce items: one wavefront per long row, one per eight short rows, in each
-// instance's row order; an item's partial sums go to its own slot so that the
+// Reduce items (one per wavefront): a workgroup's worth per chunk of a long
+// row, one per eight short rows, in each instance's row order, padded to
+// whole workgroups; an item's partial sums go to its own slot so that the
 // per-instance norm / energy sums run in a fixed order.
 #include <algorithm>
 #include <cmath>
@@ -272,11 +273,15 @@ void reduce_items(const Compiled &h, int32_t inst, std::vector<RedItem> *items) 
   for (int64_t q = 0; q < h.n_long_rows; ++q) {
     const int64_t len = h.red_ptr[q + 1] - h.red_ptr[q];
     const int32_t nch = (int32_t)((len + kRowChunk - 1) / kRowChunk);
-    for (int32_t c = 0; c < nch; ++c) items->push_back({inst, (int32_t)q, local++, c | (nch << 16)});
+    for (int32_t c = 0; c < nch; ++c)
+      for (int32_t w = 0; w < kRowWaves; ++w)
+        items->push_back({inst, (int32_t)q, local++, c | (nch << 12) | (w << 24)});
   }
   const int64_t nshort = h.ncs - h.n_long_rows;
   for (int64_t q = 0; q < nshort; q += kShortLanes)
     items->push_back({inst, (int32_t)(h.n_long_rows + q), local++, 0});
+  // whole workgroups: padding items cover no row
+  while (local % kRowWaves) items->push_back({inst, (int32_t)h.ncs, local++, 0});
 }
 
 void build_cache(sg_problem *p) {

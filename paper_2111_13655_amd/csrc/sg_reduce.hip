@@ -166,64 +166,87 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
   int slot = it->local;     // where this item's norm / energy partials go
   bool write_part = true;
   if (it->first < I->nlong) {
+    // one chunk of a long row on the whole workgroup: wavefront `sub` sums
+    // its share, the shares are added in wavefront order through LDS
+    __shared__ double wsum[2][kRowWaves];
     const int q = it->first;
-    const int c = it->chunk & 0xffff, nch = it->chunk >> 16;
+    const int c = it->chunk & 0xfff, nch = (it->chunk >> 12) & 0xfff, sub = it->chunk >> 24;
     const int64_t row = __builtin_amdgcn_readfirstlane(rows[q]);
     const int b = __builtin_amdgcn_readfirstlane(ptr[q]);
     const int e = __builtin_amdgcn_readfirstlane(ptr[q + 1]);
-    const RowIn in = row_inputs(a, I, row);
-    const int cb = b + c * kRowChunk;
+    RowIn in{};
+    if (sub == 0) in = row_inputs(a, I, row);
+    const int cb = b + c * kRowChunk + sub * (kRowChunk / kRowWaves);
     double sr = 0.0, si = 0.0;
-    strided_sum<64, kRowChunk / 64>(col, tm, cb, min(e, cb + kRowChunk), lane, &sr, &si);
+    strided_sum<64, kRowChunk / kRowWaves / 64>(col, tm, cb,
+                                                 min(e, cb + kRowChunk / kRowWaves), lane, &sr,
+                                                 &si);
     sr = group_sum<64>(sr);
     si = group_sum<64>(si);
-    if (nch == 1) {
-      if (lane == 0) row_epilogue(a, I, row, in, sr, si, &pn, &pe);
+    if (lane == 0) {
+      wsum[0][sub] = sr;
+      wsum[1][sub] = si;
+    }
+    __syncthreads();
+    if (sub != 0) {
+      pn = pe = 0.0;     // clears its partial slot
     } else {
-      // publish this chunk's sum, then count arrivals; the last chunk adds the
-      // chunk sums in chunk order (device-scope atomics: chunks run on
-      // different compute units)
-      const int first_slot = it->local - c;
-      int last = 0;
-      if (lane == 0) {
-        __hip_atomic_store(I->rpart + 2 * it->local, sr, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(I->rpart + 2 * it->local + 1, si, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_s_waitcnt(0);
-        const int old = __hip_atomic_fetch_add(I->rcnt + q, 1, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-        last = old == nch - 1;
+      sr = wsum[0][0];
+      si = wsum[1][0];
+#pragma unroll
+      for (int w = 1; w < kRowWaves; ++w) {
+        sr += wsum[0][w];
+        si += wsum[1][w];
       }
-      last = __builtin_amdgcn_readfirstlane(last);
-      if (last) {
-        if (lane == 0) {
-          double tr = 0.0, ti = 0.0;
-          for (int cc = 0; cc < nch; ++cc) {
-            if (cc == c) {
-              tr += sr;
-              ti += si;
-            } else {
-              tr += __hip_atomic_load(I->rpart + 2 * (first_slot + cc), __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-              ti += __hip_atomic_load(I->rpart + 2 * (first_slot + cc) + 1, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-            }
-          }
-          row_epilogue(a, I, row, in, tr, ti, &pn, &pe);
-          __hip_atomic_store(I->rcnt + q, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        // the row's partials go to its first chunk's slot; a later chunk also
-        // clears its own slot
-        slot = first_slot;
-        if (c != 0 && a.mode == 1 && a.k == 1 && a.want_partials && lane == 0) {
-          I->partials[2 * it->local] = 0.0;
-          I->partials[2 * it->local + 1] = 0.0;
-        }
+      if (nch == 1) {
+        if (lane == 0) row_epilogue(a, I, row, in, sr, si, &pn, &pe);
       } else {
-        // chunk 0's slot belongs to the row; other chunks clear their own
-        write_part = c != 0;
-        pn = pe = 0.0;
+        // publish this chunk's sum, then count arrivals; the last chunk adds
+        // the chunk sums in chunk order (device-scope atomics: chunks run on
+        // different compute units)
+        const int first_slot = it->local - kRowWaves * c;
+        int last = 0;
+        if (lane == 0) {
+          __hip_atomic_store(I->rpart + 2 * it->local, sr, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(I->rpart + 2 * it->local + 1, si, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+          __builtin_amdgcn_s_waitcnt(0);
+          const int old = __hip_atomic_fetch_add(I->rcnt + q, 1, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+          last = old == nch - 1;
+        }
+        last = __builtin_amdgcn_readfirstlane(last);
+        if (last) {
+          if (lane == 0) {
+            double tr = 0.0, ti = 0.0;
+            for (int cc = 0; cc < nch; ++cc) {
+              if (cc == c) {
+                tr += sr;
+                ti += si;
+              } else {
+                const int sl = first_slot + kRowWaves * cc;
+                tr += __hip_atomic_load(I->rpart + 2 * sl, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+                ti += __hip_atomic_load(I->rpart + 2 * sl + 1, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+              }
+            }
+            row_epilogue(a, I, row, in, tr, ti, &pn, &pe);
+            __hip_atomic_store(I->rcnt + q, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          // the row's partials go to its first chunk's slot; a later chunk
+          // also clears its own slot
+          slot = first_slot;
+          if (c != 0 && a.mode == 1 && a.k == 1 && a.want_partials && lane == 0) {
+            I->partials[2 * it->local] = 0.0;
+            I->partials[2 * it->local + 1] = 0.0;
+          }
+        } else {
+          // chunk 0's slot belongs to the row; other chunks clear their own
+          write_part = c != 0;
+          pn = pe = 0.0;
+        }
       }
     }
   } else {
@@ -258,10 +281,25 @@ __global__ __launch_bounds__(256) void finalize_kernel(const InstDev *inst) {
   __shared__ double s0[256], s1[256];
   const InstDev *I = inst + blockIdx.x;
   if (!I->active) return;
+  // each thread adds its items in increasing order; the loads of eight are
+  // issued before their adds
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < I->nitems; i += 256) {
-    a += I->partials[2 * i];
-    b += I->partials[2 * i + 1];
+  const int n = I->nitems;
+  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * 256) {
+    double va[8], vb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * 256;
+      va[u] = i < n ? I->partials[2 * i] : 0.0;
+      vb[u] = i < n ? I->partials[2 * i + 1] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (i0 + u * 256 < n) {
+        a += va[u];
+        b += vb[u];
+      }
+    }
   }
   s0[threadIdx.x] = a;
   s1[threadIdx.x] = b;
