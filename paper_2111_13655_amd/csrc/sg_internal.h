@@ -156,6 +156,7 @@ struct PackDev {
   int32_t maxlev;               // highest level of an active mode of the pack's terms
   int32_t pad;
   int64_t scratch_off;          // kPackBlockScratch: byte offset in the plan's scratch
+  const int32_t *mbt[kPackTerms];  // each term's first M^B entry (device), for its gather
 };
 struct PackSet {
   int32_t first = 0;            // index of the first pack

@@ -36,6 +36,7 @@ struct Cand {
   int wave;        // 1: one wavefront can run it
   int64_t ngrid;
   int maxlev;      // highest level of an active mode
+  const int32_t *mbt;  // the term's first M^B entry on the device
 };
 
 // Does every in-place contraction of term T fit the registers of a group of
@@ -61,9 +62,10 @@ bool inplace_fits(const TermDev &T, int n) {
 // One candidate per term of a pack set.  split: the set applies the split
 // operator (no kinetic contractions, so the in-place form applies to the
 // standard size maps); elem: bytes of one complex value.
-Cand make_cand(int32_t inst, int32_t term, const Compiled &h, bool split, int elem) {
+Cand make_cand(int32_t inst, int32_t term, const Compiled &h, bool split, int elem,
+               const int32_t *d_mb) {
   const TermDev &T = h.terms[term];
-  Cand c{inst, term, h.cost[term], 0, 0, 0, T.ngrid, 0};
+  Cand c{inst, term, h.cost[term], 0, 0, 0, T.ngrid, 0, d_mb ? d_mb + T.off : nullptr};
   for (int p = 0; p < T.na; ++p) c.maxlev = std::max<int>(c.maxlev, T.lev[p]);
   const bool std_maps = h.nbA == 1 && h.nbB == 2 && h.nqA == 2 && h.nqB == 2;
   const int64_t one = (int64_t)T.ngrid * elem;
@@ -161,6 +163,7 @@ void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vect
     pk.term[pk.n] = c.term;
     pk.lds_off[pk.n] = (int32_t)bin_bytes[b.id];
     pk.inplace[pk.n] = c.inplace;
+    pk.mbt[pk.n] = c.mbt;
     pk.maxlev = std::max<int32_t>(pk.maxlev, c.maxlev);
     bin_bytes[b.id] += c.slice;
     pk.n += 1;
@@ -178,6 +181,7 @@ void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vect
     pk.inst[0] = c.inst;
     pk.term[0] = c.term;
     pk.inplace[0] = c.inplace;
+    pk.mbt[0] = c.mbt;
     pk.maxlev = c.maxlev;
     if (c.slice <= cap) {
       pk.block = kPackBlockLds;
@@ -291,13 +295,13 @@ void build_cache(sg_problem *p) {
   std::vector<Cand> cg64, cs64, m64, m32;
   c.inst32 = false;
   for (int64_t t = 0; t < h.nterms; ++t) {
-    cg64.push_back(make_cand(0, (int32_t)t, h, false, 16));
-    cs64.push_back(make_cand(0, (int32_t)t, h, true, 16));
+    cg64.push_back(make_cand(0, (int32_t)t, h, false, 16, p->d_mb));
+    cs64.push_back(make_cand(0, (int32_t)t, h, true, 16, p->d_mb));
     if (std::abs(h.coeff[t]) <= h.mixed_max_fp32_coeff) {
-      m32.push_back(make_cand(0, (int32_t)t, h, true, 8));
+      m32.push_back(make_cand(0, (int32_t)t, h, true, 8, p->d_mb));
       c.inst32 = true;
     } else {
-      m64.push_back(make_cand(0, (int32_t)t, h, true, 16));
+      m64.push_back(make_cand(0, (int32_t)t, h, true, 16, p->d_mb));
     }
   }
   const std::vector<Cand> *cs[kPackSets] = {&cg64, &cs64, &m64, &m32};
@@ -361,13 +365,13 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
       for (size_t q = first; q < pl->items.size(); ++q) pl->items[q].inst = (int32_t)i;
     } else {
       for (int64_t t = 0; t < h.nterms; ++t) {
-        cg64.push_back(make_cand((int32_t)i, (int32_t)t, h, false, 16));
-        cs64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16));
+        cg64.push_back(make_cand((int32_t)i, (int32_t)t, h, false, 16, p->d_mb));
+        cs64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16, p->d_mb));
         if (std::abs(h.coeff[t]) <= h.mixed_max_fp32_coeff) {
-          m32.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 8));
+          m32.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 8, p->d_mb));
           inst32 = true;
         } else {
-          m64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16));
+          m64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16, p->d_mb));
         }
       }
       reduce_items(h, (int32_t)i, &pl->items);

@@ -930,6 +930,17 @@ struct Rows {
     if constexpr (kAll) {
 #pragma unroll
       for (int u = 0; u < NO; ++u) body(u, all[u]);
+    } else if constexpr (NO <= 8) {
+      // levels 2 and 3: two rows per iteration, loaded together, so that one
+      // LDS wait serves two rows
+#pragma unroll 1
+      for (int u = 0; u < NO; u += 2) {
+        R ra[NI], rb[NI];
+        ld(u, ra);
+        if (u + 1 < NO) ld(u + 1, rb);
+        body(u, ra);
+        if (u + 1 < NO) body(u + 1, rb);
+      }
     } else {
 #pragma unroll 1
       for (int u = 0; u < NO; ++u) {
