@@ -48,6 +48,7 @@ struct alignas(8) Z32 { float x, y; };
 // What one term's computation reads and writes.
 struct TermCtx {
   glb_p<const int32_t> mb;
+  glb_p<const int32_t> mbt;  // the term's first M^B entry (from the pack)
   glb_p<const Z64> psi;      // the vector H is applied to
   glb_p<Z64> tm;             // term-major contributions
   const void *tab;           // one-mode tables in the arithmetic type
@@ -1074,7 +1075,7 @@ __device__ __forceinline__ void gather_ip(const TermCtx &a, int off, int nfib, l
     for (int j = 0; j < FPT; ++j) {
       if (j >= nj) break;
 #pragma unroll
-      for (int k = 0; k < NI; ++k) idx[j][k] = a.mb[off + fb[j] * NI + k];
+      for (int k = 0; k < NI; ++k) idx[j][k] = a.mbt[fb[j] * NI + k];
     }
     C x[FPT][NI];
 #pragma unroll
@@ -1462,7 +1463,8 @@ __global__ __launch_bounds__(kThreads, 4) void sweep_kernel(SweepArgs a) {
   const int t = P->term[w];
   const cptr<TermDev> T = (cptr<TermDev>)(I->terms + t);
   const TermHdr hdr = load_hdr(T);
-  const TermCtx c = make_ctx<R>(a, I, t);
+  TermCtx c = make_ctx<R>(a, I, t);
+  c.mbt = (glb_p<const int32_t>)P->mbt[w];
   // the standard-map tables into LDS (every wavefront takes part): the
   // exact set at 0, the FP32-rounded FP64 set (if any) at tab_a, levels up to
   // the pack's highest only
