@@ -24,7 +24,8 @@ __all__ = [
     "sg_free", "sg_problem_info", "sg_basis_indices", "sg_term_levels",
     "sg_mapping_table", "sg_init_gaussian", "sg_apply_H", "sg_spectral_bounds",
     "sg_propagate_chebyshev", "sg_set_timing", "sg_get_timing", "sg_set_mixed_threshold",
-    "sg_tune_mixed", "sg_set_operator_form", "sg_eigensolve", "sg_embed_basis",
+    "sg_tune_mixed", "sg_set_operator_form", "sg_set_schedule", "sg_tune_schedule",
+    "sg_eigensolve", "sg_embed_basis",
     "sg_batch_create", "sg_batch_propagate", "sg_batch_free",
     "ServeConfig", "sg_serve_create", "sg_serve_submit", "sg_serve_poll", "sg_serve_cancel",
     "sg_serve_counters", "sg_serve_destroy", "Problem",
@@ -119,6 +120,9 @@ class Result(ctypes.Structure):
 _SIGNATURES = {
     "sg_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "sg_set_operator_form": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "sg_set_schedule": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "sg_tune_schedule": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32), _P]),
     "sg_set_mixed_threshold": (ctypes.c_int, [_P, ctypes.c_int32]),
     "sg_tune_mixed": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int32),
@@ -351,6 +355,20 @@ def sg_tune_mixed(h, psi, tol: float = 1e-6, reps: int = 3, stream=None):
 
 def sg_set_operator_form(h, grid_kinetic: bool) -> None:
     _check(lib().sg_set_operator_form(h, int(grid_kinetic)))
+
+
+def sg_set_schedule(h, block_min_grid: int) -> None:
+    _check(lib().sg_set_schedule(h, int(block_min_grid)))
+
+
+def sg_tune_schedule(h, psi, precision: int = SG_FP64, reps: int = 20, stream=None) -> int:
+    """Returns the chosen block_min_grid (0: terms run on a wavefront whenever
+    one can hold them)."""
+    n_cs = sg_problem_info(h)["n_cs"]
+    ch = ctypes.c_int32()
+    _check(lib().sg_tune_schedule(h, _vec_ptr(psi, n_cs, "psi"), int(precision), int(reps),
+                                  ctypes.byref(ch), _stream_ptr(stream)))
+    return ch.value
 
 
 def sg_set_timing(h, enable: bool) -> None:

@@ -401,6 +401,16 @@ sg_status sg_set_mixed_threshold(sg_problem *p, int32_t max_fp32_coeff) {
   return plan_upload(p->plan, nullptr);
 }
 
+sg_status sg_set_schedule(sg_problem *p, int32_t block_min_grid) {
+  if (!p) return fail(SG_EINVAL, "NULL problem");
+  if (block_min_grid < 0) return fail(SG_EINVAL, "block_min_grid must be >= 0");
+  p->block_grid = block_min_grid;
+  if (p->host_only) return SG_OK;
+  std::string err;
+  sg_status st = plan_build(p->plan, {p}, &err);
+  if (st != SG_OK) return fail(st, err);
+  return plan_upload(p->plan, nullptr);
+}
 sg_status sg_set_operator_form(sg_problem *p, int32_t grid_kinetic) {
   if (!p) return fail(SG_EINVAL, "NULL problem");
   if (grid_kinetic != 0 && grid_kinetic != 1) return fail(SG_EINVAL, "grid_kinetic must be 0 or 1");

@@ -267,7 +267,7 @@ namespace sg {
 // term again.  Built for a fixed mixed threshold and operator form.
 struct PackCache {
   bool valid = false;
-  int32_t thr = -1, grid_kinetic = -1;
+  int32_t thr = -1, grid_kinetic = -1, block_grid = -1;
   std::vector<PackDev> packs[kPackSets];   // inst = 0
   std::vector<double> cost[kPackSets];
   int32_t pack_lds[kPackSets] = {0, 0, 0, 0};   // largest pack, tables excluded
@@ -303,6 +303,8 @@ struct sg_problem {
   int32_t *d_rcnt = nullptr;       // [n_long_rows] chunk arrival counters
   double *d_cheb_a = nullptr;      // [kMaxChebTerms] series coefficients
   int grid_kinetic = 0;            // 1: SG_FP64 applies the kinetic matrices on the grid
+  int32_t block_grid = 0;          // > 0: terms of at least this many grid points run on a
+                                   // whole workgroup even when a wavefront could hold them
   sg::PackCache pcache;            // packs for multi-problem plans
   double *d_result = nullptr;      // 8 doubles
   double *h_result = nullptr;      // pinned host mirror of d_result

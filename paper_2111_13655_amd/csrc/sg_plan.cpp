@@ -63,7 +63,7 @@ bool inplace_fits(const TermDev &T, int n) {
 // operator (no kinetic contractions, so the in-place form applies to the
 // standard size maps); elem: bytes of one complex value.
 Cand make_cand(int32_t inst, int32_t term, const Compiled &h, bool split, int elem,
-               const int32_t *d_mb) {
+               const int32_t *d_mb, int32_t block_grid) {
   const TermDev &T = h.terms[term];
   Cand c{inst, term, h.cost[term], 0, 0, 0, T.ngrid, 0, d_mb ? d_mb + T.off : nullptr};
   for (int p = 0; p < T.na; ++p) c.maxlev = std::max<int>(c.maxlev, T.lev[p]);
@@ -77,7 +77,7 @@ Cand make_cand(int32_t inst, int32_t term, const Compiled &h, bool split, int el
   } else if (split && std_maps && inplace_fits(T, kSweepThreads)) {
     c.inplace = 1;
     c.slice = one + kCoefLdsBytes;
-    c.wave = inplace_fits(T, 64) ? 1 : 0;
+    c.wave = inplace_fits(T, 64) && !(block_grid > 0 && T.ngrid >= block_grid) ? 1 : 0;
   } else {
     c.inplace = 0;
     c.slice = 2 * one;
@@ -291,17 +291,19 @@ void reduce_items(const Compiled &h, int32_t inst, std::vector<RedItem> *items) 
 void build_cache(sg_problem *p) {
   PackCache &c = p->pcache;
   const Compiled &h = p->h;
-  if (c.valid && c.thr == h.mixed_max_fp32_coeff && c.grid_kinetic == p->grid_kinetic) return;
+  if (c.valid && c.thr == h.mixed_max_fp32_coeff && c.grid_kinetic == p->grid_kinetic &&
+      c.block_grid == p->block_grid)
+    return;
   std::vector<Cand> cg64, cs64, m64, m32;
   c.inst32 = false;
   for (int64_t t = 0; t < h.nterms; ++t) {
-    cg64.push_back(make_cand(0, (int32_t)t, h, false, 16, p->d_mb));
-    cs64.push_back(make_cand(0, (int32_t)t, h, true, 16, p->d_mb));
+    cg64.push_back(make_cand(0, (int32_t)t, h, false, 16, p->d_mb, p->block_grid));
+    cs64.push_back(make_cand(0, (int32_t)t, h, true, 16, p->d_mb, p->block_grid));
     if (std::abs(h.coeff[t]) <= h.mixed_max_fp32_coeff) {
-      m32.push_back(make_cand(0, (int32_t)t, h, true, 8, p->d_mb));
+      m32.push_back(make_cand(0, (int32_t)t, h, true, 8, p->d_mb, p->block_grid));
       c.inst32 = true;
     } else {
-      m64.push_back(make_cand(0, (int32_t)t, h, true, 16, p->d_mb));
+      m64.push_back(make_cand(0, (int32_t)t, h, true, 16, p->d_mb, p->block_grid));
     }
   }
   const std::vector<Cand> *cs[kPackSets] = {&cg64, &cs64, &m64, &m32};
@@ -319,6 +321,7 @@ void build_cache(sg_problem *p) {
   reduce_items(h, 0, &c.items);
   c.thr = h.mixed_max_fp32_coeff;
   c.grid_kinetic = p->grid_kinetic;
+  c.block_grid = p->block_grid;
   c.valid = true;
 }
 
@@ -365,13 +368,13 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
       for (size_t q = first; q < pl->items.size(); ++q) pl->items[q].inst = (int32_t)i;
     } else {
       for (int64_t t = 0; t < h.nterms; ++t) {
-        cg64.push_back(make_cand((int32_t)i, (int32_t)t, h, false, 16, p->d_mb));
-        cs64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16, p->d_mb));
+        cg64.push_back(make_cand((int32_t)i, (int32_t)t, h, false, 16, p->d_mb, p->block_grid));
+        cs64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16, p->d_mb, p->block_grid));
         if (std::abs(h.coeff[t]) <= h.mixed_max_fp32_coeff) {
-          m32.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 8, p->d_mb));
+          m32.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 8, p->d_mb, p->block_grid));
           inst32 = true;
         } else {
-          m64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16, p->d_mb));
+          m64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16, p->d_mb, p->block_grid));
         }
       }
       reduce_items(h, (int32_t)i, &pl->items);

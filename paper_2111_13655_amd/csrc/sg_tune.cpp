@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "sg_internal.h"
@@ -105,6 +106,66 @@ sg_status sg_tune_mixed(sg_problem *p, const void *psi, double tol, int32_t reps
   if ((st = sg_set_mixed_threshold(p, best)) != SG_OK) return st;
   if (chosen) *chosen = best;
   if (chosen_error) *chosen_error = best_err;
+  return SG_OK;
+}
+
+
+sg_status sg_tune_schedule(sg_problem *p, const void *psi, int32_t prec, int32_t reps,
+                           int32_t *chosen, void *stream) {
+  if (!p || !psi) return fail(SG_EINVAL, "NULL argument");
+  if (p->host_only) return fail(SG_EINVAL, "handle was built without device tables");
+  if (reps < 1) return fail(SG_EINVAL, "reps must be >= 1");
+  if (prec != SG_FP64 && prec != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = p->h.ncs;
+  double2 *ref = p->d_work + 2 * n, *out = p->d_work + 3 * n;
+  if (psi == ref || psi == out) return fail(SG_EINVAL, "psi aliases work buffers");
+  std::vector<int32_t> cand = {0};
+  for (int32_t g = 64; g <= p->h.max_grid; g *= 2) cand.push_back(g);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(SG_EDEVICE, "hipEventCreate");
+  const int32_t saved = p->block_grid;
+  std::vector<double2> h_ref((size_t)n), h_out((size_t)n);
+  sg_status st = SG_OK;
+  int32_t best = saved;
+  double best_t = 1e300;
+  for (size_t i = 0; i < cand.size() && st == SG_OK; ++i) {
+    if ((st = sg_set_schedule(p, cand[i])) != SG_OK) break;
+    if ((st = sg_apply_H(p, psi, out, (sg_precision)prec, stream)) != SG_OK) break;
+    // every schedule computes each term with the same arithmetic
+    double2 *dst = i == 0 ? h_ref.data() : h_out.data();
+    if (hipMemcpyAsync(dst, out, (size_t)n * sizeof(double2), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      st = fail(SG_EDEVICE, "copy of the tuning result");
+      break;
+    }
+    if (i > 0 && std::memcmp(h_ref.data(), h_out.data(), (size_t)n * sizeof(double2)) != 0) {
+      st = fail(SG_EDEVICE, "schedules disagree bitwise");
+      break;
+    }
+    hipEventRecord(e0, s);
+    for (int r = 0; r < reps && st == SG_OK; ++r)
+      st = sg_apply_H(p, psi, out, (sg_precision)prec, stream);
+    if (st != SG_OK) break;
+    hipEventRecord(e1, s);
+    hipEventSynchronize(e1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_t) {
+      best_t = ms;
+      best = cand[i];
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != SG_OK) {
+    sg_set_schedule(p, saved);
+    return st;
+  }
+  if ((st = sg_set_schedule(p, best)) != SG_OK) return st;
+  if (chosen) *chosen = best;
   return SG_OK;
 }
 

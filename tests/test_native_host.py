@@ -126,3 +126,18 @@ def test_invalid_descriptions_rejected():
         sg.sg_build_terms_host(2, 9, [1.0, 1.0], np.zeros((2, 2)))
     with pytest.raises(sg.SgError):
         sg.sg_build_terms_host(2, 3, [1.0, float("nan")], np.zeros((2, 2)))
+
+
+def test_schedule_setter_host_only():
+    """The term-to-workgroup schedule knob: any non-negative grid size is a
+    valid schedule; a negative one is rejected."""
+    import paper_2111_13655_amd as sg
+    P = sg.Problem.from_instance(sg_inputs.config0(), host_only=True)
+    try:
+        for g in (0, 64, 1 << 20):
+            sg.sg_set_schedule(P.handle, g)
+        with pytest.raises(sg.SgError) as e:
+            sg.sg_set_schedule(P.handle, -1)
+        assert e.value.status == sg.SG_EINVAL
+    finally:
+        P.close()
