@@ -301,21 +301,25 @@ sg_status sg_tune_mixed(sg_problem *p, const void *psi, double tol, int32_t reps
 /* Term-to-workgroup schedule.  A term whose in-place contractions fit the
  * registers of one wavefront runs on one (up to eight such terms share a
  * workgroup), unless block_min_grid > 0 and the term has at least that many
- * grid points: then it runs on a whole workgroup.  0 (the default) never
- * forces a workgroup.  The schedule decides only which threads compute a
- * term; every schedule gives bitwise the same results.  Synchronous; also
- * valid on a host-only handle.  block_min_grid < 0 -> SG_EINVAL. */
-sg_status sg_set_schedule(sg_problem *p, int32_t block_min_grid);
+ * grid points: then it runs on a whole workgroup (0, the default, never
+ * forces one).  When there are fewer wave terms than compute units can take,
+ * they are spread over packs_per_cu workgroups per compute unit (1, the
+ * default, .. 4; at most as many as fit a CU).  The schedule decides only
+ * which threads compute a term; every schedule gives bitwise the same
+ * results.  Synchronous; also valid on a host-only handle.  Out-of-range
+ * arguments -> SG_EINVAL. */
+sg_status sg_set_schedule(sg_problem *p, int32_t block_min_grid, int32_t packs_per_cu);
 
 /* Schedule autotuner.  Times `reps` applies of precision prec on the device
- * vector psi (complex128[N_cs], not modified) for each candidate
- * block_min_grid (0, and each power of two from 64 to the largest term grid)
- * and keeps the fastest.  Every candidate's result is compared bitwise with
- * the first's; a difference returns SG_EDEVICE (the schedule is left as it
- * was).  Writes the choice (nullable).  Synchronises `stream`; uses the
- * handle's work buffers. */
+ * vector psi (complex128[N_cs], not modified) for each candidate schedule
+ * (block_min_grid 0 and each power of two from 64 to the largest term grid,
+ * each with packs_per_cu 1 and 2) and keeps the fastest.  Every candidate's
+ * result is compared bitwise with the first's; a difference returns
+ * SG_EDEVICE (the schedule is left as it was).  Writes the choice (both
+ * nullable).  Synchronises `stream`; uses the handle's work buffers. */
 sg_status sg_tune_schedule(sg_problem *p, const void *psi, int32_t prec, int32_t reps,
-                           int32_t *chosen, void *stream);
+                           int32_t *chosen_block_min_grid, int32_t *chosen_packs_per_cu,
+                           void *stream);
 
 /* Lowest eigenpairs of H_S by block Davidson: the method the paper uses to
  * converge stationary states (Sec. 3, flowchart text), here on sg_apply_H

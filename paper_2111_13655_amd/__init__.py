@@ -120,8 +120,9 @@ class Result(ctypes.Structure):
 _SIGNATURES = {
     "sg_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "sg_set_operator_form": (ctypes.c_int, [_P, ctypes.c_int32]),
-    "sg_set_schedule": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "sg_set_schedule": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "sg_tune_schedule": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32), _P]),
     "sg_set_mixed_threshold": (ctypes.c_int, [_P, ctypes.c_int32]),
     "sg_tune_mixed": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32,
@@ -357,18 +358,18 @@ def sg_set_operator_form(h, grid_kinetic: bool) -> None:
     _check(lib().sg_set_operator_form(h, int(grid_kinetic)))
 
 
-def sg_set_schedule(h, block_min_grid: int) -> None:
-    _check(lib().sg_set_schedule(h, int(block_min_grid)))
+def sg_set_schedule(h, block_min_grid: int = 0, packs_per_cu: int = 1) -> None:
+    _check(lib().sg_set_schedule(h, int(block_min_grid), int(packs_per_cu)))
 
 
-def sg_tune_schedule(h, psi, precision: int = SG_FP64, reps: int = 20, stream=None) -> int:
-    """Returns the chosen block_min_grid (0: terms run on a wavefront whenever
-    one can hold them)."""
+def sg_tune_schedule(h, psi, precision: int = SG_FP64, reps: int = 20, stream=None):
+    """Returns the chosen (block_min_grid, packs_per_cu)."""
     n_cs = sg_problem_info(h)["n_cs"]
-    ch = ctypes.c_int32()
+    g = ctypes.c_int32()
+    s = ctypes.c_int32()
     _check(lib().sg_tune_schedule(h, _vec_ptr(psi, n_cs, "psi"), int(precision), int(reps),
-                                  ctypes.byref(ch), _stream_ptr(stream)))
-    return ch.value
+                                  ctypes.byref(g), ctypes.byref(s), _stream_ptr(stream)))
+    return g.value, s.value
 
 
 def sg_set_timing(h, enable: bool) -> None:

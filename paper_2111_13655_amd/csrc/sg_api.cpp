@@ -401,10 +401,12 @@ sg_status sg_set_mixed_threshold(sg_problem *p, int32_t max_fp32_coeff) {
   return plan_upload(p->plan, nullptr);
 }
 
-sg_status sg_set_schedule(sg_problem *p, int32_t block_min_grid) {
+sg_status sg_set_schedule(sg_problem *p, int32_t block_min_grid, int32_t packs_per_cu) {
   if (!p) return fail(SG_EINVAL, "NULL problem");
   if (block_min_grid < 0) return fail(SG_EINVAL, "block_min_grid must be >= 0");
+  if (packs_per_cu < 1 || packs_per_cu > 4) return fail(SG_EINVAL, "packs_per_cu must be 1..4");
   p->block_grid = block_min_grid;
+  p->packs_per_cu = packs_per_cu;
   if (p->host_only) return SG_OK;
   std::string err;
   sg_status st = plan_build(p->plan, {p}, &err);

@@ -305,6 +305,7 @@ struct sg_problem {
   int grid_kinetic = 0;            // 1: SG_FP64 applies the kinetic matrices on the grid
   int32_t block_grid = 0;          // > 0: terms of at least this many grid points run on a
                                    // whole workgroup even when a wavefront could hold them
+  int32_t packs_per_cu = 1;        // workgroups per compute unit that wave terms spread over
   sg::PackCache pcache;            // packs for multi-problem plans
   double *d_result = nullptr;      // 8 doubles
   double *h_result = nullptr;      // pinned host mirror of d_result

@@ -87,11 +87,13 @@ Cand make_cand(int32_t inst, int32_t term, const Compiled &h, bool split, int el
 }
 
 // dense: as few wave packs as the terms fill (plans over many problems);
-// otherwise enough packs to give every compute unit work.  costs (nullable)
-// receives the estimated cost of each pack appended to out.
+// otherwise enough packs to give every compute unit `spread` workgroups (one
+// by default: the wavefronts of a sparsely filled pack then have their CU's
+// SIMDs to themselves).  costs (nullable) receives the estimated cost of each
+// pack appended to out.
 void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vector<PackDev> *out,
               PackSet *set, int64_t *scratch_bytes, bool dense = false,
-              std::vector<double> *costs = nullptr) {
+              std::vector<double> *costs = nullptr, int spread = 1) {
   set->first = (int32_t)out->size();
   set->count = 0;
   set->lds_bytes = 0;
@@ -109,7 +111,8 @@ void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vect
   int lds = 0;
   const int64_t nsmall = (int64_t)small.size();
   int64_t nbins = (nsmall + kPackTerms - 1) / kPackTerms;
-  const int64_t want = (int64_t)kComputeUnits * per_cu - (int64_t)big.size();
+  const int64_t want = (int64_t)kComputeUnits * std::min(std::max(spread, 1), per_cu) -
+                       (int64_t)big.size();
   if (!dense) nbins = std::max<int64_t>(nbins, std::min<int64_t>(nsmall, want));
   struct Bin {
     double load;
@@ -426,10 +429,15 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
   if (!multi) {
     // the set SG_FP64 launches do not use stays empty
     if (split_all) cg64.clear(); else cs64.clear();
-    pack_set(cg64, 16, tabs[kSetGrid64], &pl->packs, &pl->sets[kSetGrid64], &pl->scratch_bytes);
-    pack_set(cs64, 16, tabs[kSetSplit64], &pl->packs, &pl->sets[kSetSplit64], &pl->scratch_bytes);
-    pack_set(m64, 16, tabs[kSetMixed64], &pl->packs, &pl->sets[kSetMixed64], &pl->scratch_bytes);
-    pack_set(m32, 8, tabs[kSetMixed32], &pl->packs, &pl->sets[kSetMixed32], &pl->scratch_bytes);
+    const int sp = probs[0]->packs_per_cu;
+    pack_set(cg64, 16, tabs[kSetGrid64], &pl->packs, &pl->sets[kSetGrid64], &pl->scratch_bytes,
+             false, nullptr, sp);
+    pack_set(cs64, 16, tabs[kSetSplit64], &pl->packs, &pl->sets[kSetSplit64], &pl->scratch_bytes,
+             false, nullptr, sp);
+    pack_set(m64, 16, tabs[kSetMixed64], &pl->packs, &pl->sets[kSetMixed64], &pl->scratch_bytes,
+             false, nullptr, sp);
+    pack_set(m32, 8, tabs[kSetMixed32], &pl->packs, &pl->sets[kSetMixed32], &pl->scratch_bytes,
+             false, nullptr, sp);
     mark_inplace_sets(pl);
     return SG_OK;
   }

@@ -111,7 +111,8 @@ sg_status sg_tune_mixed(sg_problem *p, const void *psi, double tol, int32_t reps
 
 
 sg_status sg_tune_schedule(sg_problem *p, const void *psi, int32_t prec, int32_t reps,
-                           int32_t *chosen, void *stream) {
+                           int32_t *chosen_block_min_grid, int32_t *chosen_packs_per_cu,
+                           void *stream) {
   if (!p || !psi) return fail(SG_EINVAL, "NULL argument");
   if (p->host_only) return fail(SG_EINVAL, "handle was built without device tables");
   if (reps < 1) return fail(SG_EINVAL, "reps must be >= 1");
@@ -120,18 +121,21 @@ sg_status sg_tune_schedule(sg_problem *p, const void *psi, int32_t prec, int32_t
   const int64_t n = p->h.ncs;
   double2 *ref = p->d_work + 2 * n, *out = p->d_work + 3 * n;
   if (psi == ref || psi == out) return fail(SG_EINVAL, "psi aliases work buffers");
-  std::vector<int32_t> cand = {0};
-  for (int32_t g = 64; g <= p->h.max_grid; g *= 2) cand.push_back(g);
+  std::vector<std::pair<int32_t, int32_t>> cand;
+  for (int32_t spread = 1; spread <= 2; ++spread) {
+    cand.push_back({0, spread});
+    for (int32_t g = 64; g <= p->h.max_grid; g *= 2) cand.push_back({g, spread});
+  }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(SG_EDEVICE, "hipEventCreate");
-  const int32_t saved = p->block_grid;
+  const std::pair<int32_t, int32_t> saved = {p->block_grid, p->packs_per_cu};
   std::vector<double2> h_ref((size_t)n), h_out((size_t)n);
   sg_status st = SG_OK;
-  int32_t best = saved;
+  std::pair<int32_t, int32_t> best = saved;
   double best_t = 1e300;
   for (size_t i = 0; i < cand.size() && st == SG_OK; ++i) {
-    if ((st = sg_set_schedule(p, cand[i])) != SG_OK) break;
+    if ((st = sg_set_schedule(p, cand[i].first, cand[i].second)) != SG_OK) break;
     if ((st = sg_apply_H(p, psi, out, (sg_precision)prec, stream)) != SG_OK) break;
     // every schedule computes each term with the same arithmetic
     double2 *dst = i == 0 ? h_ref.data() : h_out.data();
@@ -161,11 +165,12 @@ sg_status sg_tune_schedule(sg_problem *p, const void *psi, int32_t prec, int32_t
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (st != SG_OK) {
-    sg_set_schedule(p, saved);
+    sg_set_schedule(p, saved.first, saved.second);
     return st;
   }
-  if ((st = sg_set_schedule(p, best)) != SG_OK) return st;
-  if (chosen) *chosen = best;
+  if ((st = sg_set_schedule(p, best.first, best.second)) != SG_OK) return st;
+  if (chosen_block_min_grid) *chosen_block_min_grid = best.first;
+  if (chosen_packs_per_cu) *chosen_packs_per_cu = best.second;
   return SG_OK;
 }
 

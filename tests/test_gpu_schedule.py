@@ -34,8 +34,8 @@ def test_schedules_agree_bitwise(prec):
         x = _random_state(P.n_cs, 3)
         y = torch.empty_like(x)
         outs = []
-        for g in (0, 64, 256, 1024, 4096):
-            sg.sg_set_schedule(P.handle, g)
+        for g, spread in ((0, 1), (0, 2), (64, 1), (256, 2), (1024, 1), (4096, 2)):
+            sg.sg_set_schedule(P.handle, g, spread)
             sg.sg_apply_H(P.handle, x, y, prec)
             outs.append(to_host(y).copy())
         for o in outs[1:]:
@@ -49,8 +49,9 @@ def test_tuned_schedule_matches_oracle():
     say("tuned schedule (4,4) vs oracle")
     with sg.Problem.from_instance(inst) as P:
         x = _random_state(P.n_cs, 4)
-        g = sg.sg_tune_schedule(P.handle, x, sg.SG_FP64, reps=3)
+        g, spread = sg.sg_tune_schedule(P.handle, x, sg.SG_FP64, reps=3)
         assert g == 0 or (g >= 64 and g & (g - 1) == 0)
+        assert spread in (1, 2)
         y = torch.empty_like(x)
         sg.sg_apply_H(P.handle, x, y, sg.SG_FP64)
         got = to_host(y)

@@ -135,9 +135,11 @@ def test_schedule_setter_host_only():
     P = sg.Problem.from_instance(sg_inputs.config0(), host_only=True)
     try:
         for g in (0, 64, 1 << 20):
-            sg.sg_set_schedule(P.handle, g)
-        with pytest.raises(sg.SgError) as e:
-            sg.sg_set_schedule(P.handle, -1)
-        assert e.value.status == sg.SG_EINVAL
+            for spread in (1, 2, 4):
+                sg.sg_set_schedule(P.handle, g, spread)
+        for bad in ((-1, 1), (0, 0), (0, 5)):
+            with pytest.raises(sg.SgError) as e:
+                sg.sg_set_schedule(P.handle, *bad)
+            assert e.value.status == sg.SG_EINVAL
     finally:
         P.close()
