@@ -193,7 +193,10 @@ struct RedItem {
   int32_t inst;
   int32_t first;    // index into the instance's row list
   int32_t local;    // item index inside the instance (partial-sum slot)
-  int32_t chunk;    // long rows: chunk | (chunks << 12) | (wavefront << 24); short: 0
+  int32_t chunk;    // long rows: chunk | (chunks << 12) | (wavefront << 24);
+                    // short rows: how many of the item's rows exist (0 for padding)
+  const int32_t *rows;  // the instance's row list and row bounds at `first`
+  const int32_t *ptr;   // (device), so that they load without the instance record
 };
 
 // Host-side term compiler output.

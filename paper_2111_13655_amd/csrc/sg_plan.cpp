@@ -181,10 +181,12 @@ void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vect
     PackDev pk;
     std::memset(&pk, 0, sizeof(pk));
     pk.n = 1;
-    pk.inst[0] = c.inst;
-    pk.term[0] = c.term;
+    for (int w = 0; w < kPackTerms; ++w) {   // only slot 0 is read; all hold the term
+      pk.inst[w] = c.inst;
+      pk.term[w] = c.term;
+      pk.mbt[w] = c.mbt;
+    }
     pk.inplace[0] = c.inplace;
-    pk.mbt[0] = c.mbt;
     pk.maxlev = c.maxlev;
     if (c.slice <= cap) {
       pk.block = kPackBlockLds;
@@ -204,8 +206,16 @@ void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vect
   std::stable_sort(order.begin(), order.end(),
                    [&](int64_t a, int64_t b) { return bin_load[a] > bin_load[b]; });
   for (int64_t i : order) {
-    if (bins[i].n == 0) continue;
-    out->push_back(bins[i]);
+    PackDev &pk = bins[i];
+    if (pk.n == 0) continue;
+    // every wavefront reads its slot's term record before it tests whether
+    // the slot is used: unused slots repeat slot 0's term (a valid record)
+    for (int w = pk.n; w < kPackTerms; ++w) {
+      pk.inst[w] = pk.inst[0];
+      pk.term[w] = pk.term[0];
+      pk.mbt[w] = pk.mbt[0];
+    }
+    out->push_back(pk);
     if (costs) costs->push_back(bin_load[i]);
     lds = std::max<int>(lds, (int)bin_bytes[i]);
   }
@@ -275,20 +285,27 @@ namespace {
 constexpr int kTabMax64 = ((std_table_base(8) * 8 + 15) / 16) * 16;
 constexpr int kTabMax32 = ((std_table_base(8) * 4 + 15) / 16) * 16;
 
-void reduce_items(const Compiled &h, int32_t inst, std::vector<RedItem> *items) {
+void reduce_items(const sg_problem *p, int32_t inst, std::vector<RedItem> *items) {
+  const Compiled &h = p->h;
+  auto at = [&](int64_t q, const int32_t *base) { return base ? base + q : nullptr; };
   int32_t local = 0;
   for (int64_t q = 0; q < h.n_long_rows; ++q) {
     const int64_t len = h.red_ptr[q + 1] - h.red_ptr[q];
     const int32_t nch = (int32_t)((len + kRowChunk - 1) / kRowChunk);
     for (int32_t c = 0; c < nch; ++c)
       for (int32_t w = 0; w < kRowWaves; ++w)
-        items->push_back({inst, (int32_t)q, local++, c | (nch << 12) | (w << 24)});
+        items->push_back({inst, (int32_t)q, local++, c | (nch << 12) | (w << 24),
+                          at(q, p->d_rows), at(q, p->d_inv_ptr)});
   }
   const int64_t nshort = h.ncs - h.n_long_rows;
-  for (int64_t q = 0; q < nshort; q += kShortLanes)
-    items->push_back({inst, (int32_t)(h.n_long_rows + q), local++, 0});
+  for (int64_t q = 0; q < nshort; q += kShortLanes) {
+    const int64_t first = h.n_long_rows + q;
+    items->push_back({inst, (int32_t)first, local++,
+                      (int32_t)std::min<int64_t>(kShortLanes, h.ncs - first),
+                      at(first, p->d_rows), at(first, p->d_inv_ptr)});
+  }
   // whole workgroups: padding items cover no row
-  while (local % kRowWaves) items->push_back({inst, (int32_t)h.ncs, local++, 0});
+  while (local % kRowWaves) items->push_back({inst, (int32_t)h.ncs, local++, 0, nullptr, nullptr});
 }
 
 void build_cache(sg_problem *p) {
@@ -321,7 +338,7 @@ void build_cache(sg_problem *p) {
     c.pack_lds[k] = ps.count ? ps.lds_bytes - ps.tab_bytes : 0;
   }
   c.items.clear();
-  reduce_items(h, 0, &c.items);
+  reduce_items(p, 0, &c.items);
   c.thr = h.mixed_max_fp32_coeff;
   c.grid_kinetic = p->grid_kinetic;
   c.block_grid = p->block_grid;
@@ -380,7 +397,7 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
           m64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16, p->d_mb, p->block_grid));
         }
       }
-      reduce_items(h, (int32_t)i, &pl->items);
+      reduce_items(p, (int32_t)i, &pl->items);
     }
     pl->inst[i].round32 = inst32 ? 1 : 0;
     pl->any32 = pl->any32 || inst32;
@@ -456,7 +473,7 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
       const int64_t base = pl->scratch_bytes;
       for (size_t q = 0; q < c.packs[k].size(); ++q) {
         PackDev pk = c.packs[k][q];
-        for (int w = 0; w < pk.n; ++w) pk.inst[w] = (int32_t)i;
+        for (int w = 0; w < kPackTerms; ++w) pk.inst[w] = (int32_t)i;   // unused slots too
         if (pk.block == kPackBlockScratch) pk.scratch_off += base;
         all.push_back({c.cost[k][q], pk});
       }

@@ -156,24 +156,42 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
   const int64_t gw = (int64_t)blockIdx.x * (kRedThreads / 64) + wave;
   if (gw >= a.nitems) return;
   const cptr<RedItem> it = a.items + gw;
+  const int chunk = it->chunk;
+  const int nch = (chunk >> 12) & 0xfff;   // long rows: chunks of the row; short rows: 0
+  const glb_p<const int32_t> rowp = (glb_p<const int32_t>)it->rows;
+  const glb_p<const int32_t> ptrp = (glb_p<const int32_t>)it->ptr;
+  // the item's row and bounds load alongside the instance record (both
+  // operands of the test are read, so that neither load waits on the other)
   const cptr<InstDev> I = a.inst + it->inst;
-  if (!I->active || (a.mode == 1 && a.k > I->K - 1)) return;
+  const bool skip = (I->active == 0) | ((a.mode == 1) & (a.k > I->K - 1));
+  // long rows: one row for the workgroup; short rows: one per lane group
+  int lrow = 0, lb = 0, le = 0, row = 0, b = 0, e = 0;
+  const int r = lane / kShortLanes;
+  const bool valid = nch || r < chunk;
+  if (nch) {
+    lrow = __builtin_amdgcn_readfirstlane(rowp[0]);
+    lb = __builtin_amdgcn_readfirstlane(ptrp[0]);
+    le = __builtin_amdgcn_readfirstlane(ptrp[1]);
+  } else if (valid) {
+    row = rowp[r];
+    b = ptrp[r];
+    e = ptrp[r + 1];
+  }
+  if (skip) return;
   const glb_p<const Z64> tm = (glb_p<const Z64>)I->tm;
-  const glb_p<const int32_t> ptr = (glb_p<const int32_t>)I->inv_ptr;
-  const glb_p<const int32_t> rows = (glb_p<const int32_t>)I->rows;
   const glb_p<const int32_t> col = (glb_p<const int32_t>)I->inv_col;
   double pn = 0.0, pe = 0.0;
   int slot = it->local;     // where this item's norm / energy partials go
   bool write_part = true;
-  if (it->first < I->nlong) {
+  if (nch) {
     // one chunk of a long row on the whole workgroup: wavefront `sub` sums
     // its share, the shares are added in wavefront order through LDS
     __shared__ double wsum[2][kRowWaves];
     const int q = it->first;
-    const int c = it->chunk & 0xfff, nch = (it->chunk >> 12) & 0xfff, sub = it->chunk >> 24;
-    const int64_t row = __builtin_amdgcn_readfirstlane(rows[q]);
-    const int b = __builtin_amdgcn_readfirstlane(ptr[q]);
-    const int e = __builtin_amdgcn_readfirstlane(ptr[q + 1]);
+    const int c = chunk & 0xfff, sub = chunk >> 24;
+    row = lrow;
+    b = lb;
+    e = le;
     RowIn in{};
     if (sub == 0) in = row_inputs(a, I, row);
     const int cb = b + c * kRowChunk + sub * (kRowChunk / kRowWaves);
@@ -250,15 +268,10 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
       }
     }
   } else {
-    const int64_t ri = (int64_t)it->first + lane / kShortLanes;
     const int sub = lane % kShortLanes;
-    const bool valid = ri < I->ncs;
     double sr = 0.0, si = 0.0;
-    int64_t row = 0;
     RowIn in{};
     if (valid) {
-      row = rows[ri];
-      const int b = ptr[ri], e = ptr[ri + 1];
       in = row_inputs(a, I, row);
       strided_sum<kShortLanes, kLongRow / kShortLanes>(col, tm, b, e, sub, &sr, &si);
     }

@@ -1453,7 +1453,7 @@ __global__ __launch_bounds__(kThreads, 4) void sweep_kernel(SweepArgs a) {
   extern __shared__ char lds_raw[];
   typedef typename Cx<R>::T C;
   // this wavefront's term (slot 0 of a one-term pack; unused slots of a wave
-  // pack hold instance 0, term 0) and its record header, loaded before the
+  // pack repeat slot 0's term) and its record header, loaded before the
   // table copy so that their latency overlaps it
   const cptr<PackDev> P = a.packs + blockIdx.x;
   const int kind = P->block;
