@@ -192,6 +192,42 @@ sg_status sg_propagate_chebyshev(sg_problem *p, void *psi, double dt,
                                  double *norm_trace, double *energy_trace,
                                  void *stream);
 
+/* The other propagators the paper lists beside the Chebyshev method
+ * (Sec. 3, overview of the program flow; no formulas given there):
+ *   SG_PROP_TAYLOR  order n (1..40): psi <- sum_{k<=n} (-i H dt)^k/k! psi;
+ *                   n applies of H per step.
+ *   SG_PROP_RK      order n (1..4): explicit Runge-Kutta on d psi/dt =
+ *                   -i H psi with the tableaux of Euler, the explicit
+ *                   midpoint rule, Heun's third-order method and the
+ *                   classical fourth-order method; n applies per step.
+ *   SG_PROP_SIL     short iterative Lanczos with Krylov dimension n (1..64,
+ *                   capped at N_cs): Lanczos from psi/|psi| with every new
+ *                   vector orthogonalised twice against the earlier ones,
+ *                   psi <- |psi| V exp(-i T dt) e_1; ends early on an
+ *                   invariant space; up to n applies per step. */
+typedef enum {
+  SG_PROP_TAYLOR = 1,
+  SG_PROP_RK = 2,
+  SG_PROP_SIL = 3
+} sg_propagator;
+
+/* Propagates psi (in place, device complex128[N_cs]) over nsteps steps of dt
+ * with `method` of order (Krylov dimension) `order`.  Allocates its work
+ * vectors (up to order + 2 vectors of N_cs) for the call and synchronises
+ * `stream` on return.  At the first step, every `check_every` steps (0 =
+ * first and last only) and at the end the norm and energy are computed in
+ * FP64 (one extra apply each); if the norm drifts from its first value by
+ * more than tol (> 0) the call stops and returns SG_ETOL (Taylor and
+ * Runge-Kutta are not unitary: their drift measures the step's error).
+ * stats: cheb_terms holds `order`, applies counts every apply including the
+ * checks, emin/emax are NaN.  Traces as in sg_propagate_chebyshev.  Bad
+ * method, order, dt or precision -> SG_EINVAL. */
+sg_status sg_propagate(sg_problem *p, void *psi, double dt, int32_t nsteps,
+                       int32_t method, int32_t order, double tol,
+                       sg_precision prec, int32_t check_every,
+                       sg_prop_stats *stats, double *norm_trace,
+                       double *energy_trace, void *stream);
+
 /* Batched propagation of independent problems (same device).  Every
  * Chebyshev term of every instance runs in one term-sweep launch and one
  * reduce launch: the terms of all instances are packed together into

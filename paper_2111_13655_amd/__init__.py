@@ -23,7 +23,8 @@ __all__ = [
     "library_path", "sg_count_sizes", "sg_build_terms", "sg_build_terms_host",
     "sg_free", "sg_problem_info", "sg_basis_indices", "sg_term_levels",
     "sg_mapping_table", "sg_init_gaussian", "sg_apply_H", "sg_spectral_bounds",
-    "sg_propagate_chebyshev", "sg_set_timing", "sg_get_timing", "sg_set_mixed_threshold",
+    "sg_propagate_chebyshev", "sg_propagate", "SG_PROP_TAYLOR", "SG_PROP_RK", "SG_PROP_SIL",
+    "sg_set_timing", "sg_get_timing", "sg_set_mixed_threshold",
     "sg_tune_mixed", "sg_set_operator_form", "sg_set_schedule", "sg_tune_schedule",
     "sg_eigensolve", "sg_embed_basis",
     "sg_batch_create", "sg_batch_propagate", "sg_batch_free",
@@ -34,6 +35,7 @@ __all__ = [
 SG_OK, SG_EINVAL, SG_ENOMEM, SG_EDEVICE = 0, -1, -2, -3
 SG_EAGAIN, SG_ENOTFOUND, SG_ECANCELED, SG_ETOL = -4, -5, -6, -7
 SG_FP64, SG_MIXED = 0, 1
+SG_PROP_TAYLOR, SG_PROP_RK, SG_PROP_SIL = 1, 2, 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -151,6 +153,10 @@ _SIGNATURES = {
                                               ctypes.POINTER(PropStats),
                                               ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_double), _P]),
+    "sg_propagate": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_double, ctypes.c_int, ctypes.c_int32,
+                                    ctypes.POINTER(PropStats), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double), _P]),
     "sg_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)]),
     "sg_batch_propagate": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_double),
                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -331,6 +337,26 @@ def sg_propagate_chebyshev(h, psi, dt: float, nsteps: int, emin=math.nan, emax=m
     et = np.zeros(ntr)
     status = lib().sg_propagate_chebyshev(
         h, _vec_ptr(psi, n_cs, "psi"), float(dt), int(nsteps), float(emin), float(emax),
+        float(tol), int(precision), int(check_every), ctypes.byref(st), _dptr(nt), _dptr(et),
+        _stream_ptr(stream))
+    if status not in (SG_OK, SG_ETOL):
+        _check(status)
+    d = st.as_dict()
+    n = min(ntr, (d["steps_done"] // check_every + 2) if check_every > 0 else 2)
+    return status, d, nt[:n], et[:n]
+
+
+def sg_propagate(h, psi, dt: float, nsteps: int, method: int, order: int, tol: float = 0.0,
+                 precision: int = SG_FP64, check_every: int = 0, stream=None):
+    """Taylor / Runge-Kutta / short-iterative-Lanczos propagation in place.
+    Returns (status, stats dict, norm trace, energy trace)."""
+    n_cs = sg_problem_info(h)["n_cs"]
+    st = PropStats()
+    ntr = max((nsteps // check_every + 2) if check_every > 0 else 2, 2)
+    nt = np.zeros(ntr)
+    et = np.zeros(ntr)
+    status = lib().sg_propagate(
+        h, _vec_ptr(psi, n_cs, "psi"), float(dt), int(nsteps), int(method), int(order),
         float(tol), int(precision), int(check_every), ctypes.byref(st), _dptr(nt), _dptr(et),
         _stream_ptr(stream))
     if status not in (SG_OK, SG_ETOL):

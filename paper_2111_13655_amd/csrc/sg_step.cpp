@@ -1,0 +1,305 @@
+// Taylor, Runge-Kutta and short-iterative-Lanczos propagation on the operator
+// action (the other propagators the paper lists beside the Chebyshev method,
+// Sec. 3 overview of the program flow; it gives no formulas).  With hbar = 1
+// and d psi/dt = -i H psi:
+//
+//   Taylor, order n:  psi <- sum_{k<=n} (-i H dt)^k / k! psi, built term by
+//     term (term_k = (-i dt / k) H term_{k-1}).
+//   Runge-Kutta, order n = 1..4: explicit tableaux (Euler; explicit
+//     midpoint; Heun's third-order method; the classical fourth-order
+//     method).  Stage i applies H to psi + dt sum_j A_ij k_j with
+//     k_j = -i H y_j; the -i is folded into the complex coefficients.
+//   Short iterative Lanczos, Krylov dimension m (Park and Light, 1986):
+//     Lanczos from psi/|psi|, every new vector orthogonalised against all
+//     earlier ones twice; T = tridiag(alpha, beta); psi <- |psi| V
+//     exp(-i T dt) e_1, with exp(-i T dt) from the eigenpairs of T (host).
+//     The recurrence ends early on an invariant space (norm below 1e-13 of
+//     |psi|).
+//
+// Every H application is one term sweep plus one reduce; vector updates run
+// in the library's vector kernels; the state never leaves the device.  Only
+// Lanczos coefficients and checked norms and energies are read back.
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "sg_internal.h"
+
+using namespace sg;
+
+namespace {
+
+constexpr int kMaxTaylorOrder = 40;
+constexpr int kMaxKrylov = 64;
+
+struct Buffers {
+  double2 *v = nullptr;        // vectors, n each
+  double *partials = nullptr;  // multi-dot partial sums
+  double *dots = nullptr;      // multi-dot results (re, im)
+  double *coef = nullptr;      // multi-axpy coefficients (re, im)
+  ~Buffers() {
+    hipFree(v);
+    hipFree(partials);
+    hipFree(dots);
+    hipFree(coef);
+  }
+};
+
+// explicit tableaux: strictly lower A (row-major, 4 x 4) and weights b
+struct Tableau {
+  int s;
+  double A[4][4];
+  double b[4];
+};
+const Tableau kRK[4] = {
+    {1, {{0}}, {1.0}},
+    {2, {{0, 0}, {0.5, 0}}, {0.0, 1.0}},
+    {3, {{0, 0, 0}, {1.0 / 3.0, 0, 0}, {0, 2.0 / 3.0, 0}}, {0.25, 0.0, 0.75}},
+    {4, {{0, 0, 0, 0}, {0.5, 0, 0, 0}, {0, 0.5, 0, 0}, {0, 0, 1.0, 0}},
+     {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0}},
+};
+
+sg_status read2(sg_problem *p, hipStream_t s, double *a, double *b) {
+  hipError_t e = hipMemcpyAsync(p->h_result, p->d_result, 2 * sizeof(double),
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "read reduction result");
+  *a = p->h_result[0];
+  *b = p->h_result[1];
+  return SG_OK;
+}
+
+// out[j] = conj(V_j)^T w for j < m (host, synchronises)
+sg_status vdots(const Buffers &B, const double2 *V, int64_t n, int m, const double2 *w,
+                std::vector<std::complex<double>> *out, hipStream_t s) {
+  std::vector<double> h(2 * (size_t)m);
+  hipError_t e = launch_multi_dot(V, n, m, w, n, B.partials, B.dots, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h.data(), B.dots, h.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "Lanczos projections");
+  out->resize(m);
+  for (int j = 0; j < m; ++j) (*out)[j] = {h[2 * j], h[2 * j + 1]};
+  return SG_OK;
+}
+
+// x = beta x + sum_j c_j V_j (synchronises: the coefficient buffer is reused)
+sg_status combine(const Buffers &B, double2 *x, double beta, const double2 *V, int64_t n,
+                  const std::vector<std::complex<double>> &c, hipStream_t s) {
+  std::vector<double> h(2 * c.size());
+  for (size_t j = 0; j < c.size(); ++j) {
+    h[2 * j] = c[j].real();
+    h[2 * j + 1] = c[j].imag();
+  }
+  hipError_t e = hipMemcpyAsync(B.coef, h.data(), h.size() * sizeof(double),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_multi_axpy(x, beta, V, n, (int)c.size(), B.coef, n, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "Lanczos combination");
+  return SG_OK;
+}
+
+sg_status taylor_step(sg_problem *p, double2 *psi, double dt, int order, sg_precision prec,
+                      double2 *term, double2 *hv, hipStream_t s, void *stream) {
+  const int64_t n = p->h.ncs;
+  hipError_t e = hipMemcpyAsync(term, psi, n * sizeof(double2), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "copy");
+  for (int k = 1; k <= order; ++k) {
+    sg_status st = sg_apply_H(p, term, hv, prec, stream);
+    if (st != SG_OK) return st;
+    // term = (-i dt / k) H term ; psi += term
+    if ((e = launch_axpby(n, term, hv, 0.0, -dt / k, 0.0, s)) != hipSuccess ||
+        (e = launch_axpby(n, psi, term, 1.0, 0.0, 1.0, s)) != hipSuccess)
+      return hip_fail(e, "axpby");
+  }
+  return SG_OK;
+}
+
+sg_status rk_step(sg_problem *p, double2 *psi, double dt, const Tableau &T, sg_precision prec,
+                  double2 *y, double2 *const hk[4], hipStream_t s, void *stream) {
+  const int64_t n = p->h.ncs;
+  hipError_t e;
+  for (int i = 0; i < T.s; ++i) {
+    const double2 *in = psi;
+    bool any = false;
+    for (int j = 0; j < i; ++j) any = any || T.A[i][j] != 0.0;
+    if (any) {
+      if ((e = hipMemcpyAsync(y, psi, n * sizeof(double2), hipMemcpyDeviceToDevice, s)) !=
+          hipSuccess)
+        return hip_fail(e, "copy");
+      // y += dt A_ij k_j,  k_j = -i H y_j
+      for (int j = 0; j < i; ++j)
+        if (T.A[i][j] != 0.0 &&
+            (e = launch_axpby(n, y, hk[j], 0.0, -dt * T.A[i][j], 1.0, s)) != hipSuccess)
+          return hip_fail(e, "axpby");
+      in = y;
+    }
+    sg_status st = sg_apply_H(p, in, hk[i], prec, stream);
+    if (st != SG_OK) return st;
+  }
+  for (int i = 0; i < T.s; ++i)
+    if (T.b[i] != 0.0 && (e = launch_axpby(n, psi, hk[i], 0.0, -dt * T.b[i], 1.0, s)) != hipSuccess)
+      return hip_fail(e, "axpby");
+  return SG_OK;
+}
+
+// V holds m + 1 vectors of n (zero-filled once); returns the Krylov size used
+sg_status sil_step(sg_problem *p, double2 *psi, double dt, int m, sg_precision prec,
+                   const Buffers &B, hipStream_t s, void *stream, int *used) {
+  const int64_t n = p->h.ncs;
+  double2 *V = B.v;
+  hipError_t e = launch_dot(p, psi, psi, s);
+  if (e != hipSuccess) return hip_fail(e, "dot");
+  double nn, ni;
+  sg_status st = read2(p, s, &nn, &ni);
+  if (st != SG_OK) return st;
+  const double beta0 = std::sqrt(std::max(nn, 0.0));
+  *used = 0;
+  if (!(beta0 > 0.0)) return SG_OK;  // the zero state stays zero
+  if ((e = launch_axpby(n, V, psi, 1.0 / beta0, 0.0, 0.0, s)) != hipSuccess)
+    return hip_fail(e, "axpby");
+  std::vector<double> alpha, beta;
+  std::vector<std::complex<double>> c;
+  for (int j = 0; j < m; ++j) {
+    double2 *w = V + (size_t)(j + 1) * n;
+    if ((st = sg_apply_H(p, V + (size_t)j * n, w, prec, stream)) != SG_OK) return st;
+    double a = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      if ((st = vdots(B, V, n, j + 1, w, &c, s)) != SG_OK) return st;
+      a += c[j].real();
+      for (auto &x : c) x = -x;
+      if ((st = combine(B, w, 1.0, V, n, c, s)) != SG_OK) return st;
+    }
+    alpha.push_back(a);
+    if (j == m - 1) break;
+    if ((e = launch_dot(p, w, w, s)) != hipSuccess) return hip_fail(e, "dot");
+    double bb, bi;
+    if ((st = read2(p, s, &bb, &bi)) != SG_OK) return st;
+    const double b = std::sqrt(std::max(bb, 0.0));
+    if (b < 1e-13 * beta0) break;
+    beta.push_back(b);
+    if ((e = launch_axpby(n, w, w, 1.0 / b, 0.0, 0.0, s)) != hipSuccess)
+      return hip_fail(e, "axpby");
+  }
+  const int k = (int)alpha.size();
+  std::vector<double> T((size_t)k * k, 0.0), ev, U;
+  for (int i = 0; i < k; ++i) {
+    T[(size_t)i * k + i] = alpha[i];
+    if (i + 1 < k) T[(size_t)i * k + i + 1] = T[(size_t)(i + 1) * k + i] = beta[i];
+  }
+  jacobi_eigen(T, k, &ev, &U);
+  // coefficients of psi(t + dt) in V: beta0 U exp(-i ev dt) U^T e_1
+  // (U row-major, eigenvectors in columns)
+  std::vector<std::complex<double>> coef(k, 0.0);
+  for (int q = 0; q < k; ++q) {
+    const std::complex<double> ph = std::polar(1.0, -ev[q] * dt) * (beta0 * U[(size_t)0 * k + q]);
+    for (int i = 0; i < k; ++i) coef[i] += U[(size_t)i * k + q] * ph;
+  }
+  if ((st = combine(B, psi, 0.0, V, n, coef, s)) != SG_OK) return st;
+  *used = k;
+  return SG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, int32_t method,
+                       int32_t order, double tol, sg_precision prec, int32_t check_every,
+                       sg_prop_stats *stats, double *norm_trace, double *energy_trace,
+                       void *stream) {
+  if (!p || !psi_v) return fail(SG_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt) || nsteps < 0 || check_every < 0)
+    return fail(SG_EINVAL, "dt must be > 0, nsteps and check_every >= 0");
+  if (prec != SG_FP64 && prec != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
+  if (method == SG_PROP_TAYLOR) {
+    if (order < 1 || order > kMaxTaylorOrder) return fail(SG_EINVAL, "Taylor order must be 1..40");
+  } else if (method == SG_PROP_RK) {
+    if (order < 1 || order > 4) return fail(SG_EINVAL, "Runge-Kutta order must be 1..4");
+  } else if (method == SG_PROP_SIL) {
+    if (order < 1 || order > kMaxKrylov) return fail(SG_EINVAL, "Krylov dimension must be 1..64");
+  } else {
+    return fail(SG_EINVAL, "unknown propagator");
+  }
+  if (p->host_only) return fail(SG_EINVAL, "handle was built without device tables");
+  hipStream_t s = (hipStream_t)stream;
+  double2 *psi = (double2 *)psi_v;
+  const int64_t n = p->h.ncs;
+  const int m = method == SG_PROP_SIL ? (int)std::min<int64_t>(order, n) : 0;
+  // work vectors: Taylor 2, Runge-Kutta 1 + stages, Lanczos m + 1; one more
+  // for the checks
+  const int nvec = method == SG_PROP_TAYLOR ? 2 : method == SG_PROP_RK ? 1 + order : m + 1;
+  Buffers B;
+  hipError_t e = hipMalloc((void **)&B.v, (size_t)(nvec + 1) * n * sizeof(double2));
+  if (e == hipSuccess && method == SG_PROP_SIL) {
+    const size_t mm = (size_t)m + 1;
+    e = hipMalloc((void **)&B.partials, 2 * mm * dot_partials_per_vector() * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&B.dots, 2 * mm * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&B.coef, 2 * mm * sizeof(double));
+  }
+  if (e != hipSuccess) return fail(SG_ENOMEM, "propagator work vectors");
+  // zero-filled: vector updates read their destination
+  if ((e = hipMemsetAsync(B.v, 0, (size_t)(nvec + 1) * n * sizeof(double2), s)) != hipSuccess)
+    return hip_fail(e, "clear work vectors");
+  double2 *check_buf = B.v + (size_t)nvec * n;
+
+  sg_prop_stats st{};
+  st.cheb_terms = order;
+  st.emin = st.emax = std::nan("");
+  int ntrace = 0;
+  bool have0 = false;
+  sg_status ret = SG_OK;
+  auto check = [&]() -> sg_status {
+    sg_status as = sg_apply_H(p, psi, check_buf, prec, stream);
+    if (as != SG_OK) return as;
+    double nr, ni, er, ei;
+    if ((e = launch_dot(p, psi, psi, s)) != hipSuccess) return hip_fail(e, "dot");
+    if ((as = read2(p, s, &nr, &ni)) != SG_OK) return as;
+    if ((e = launch_dot(p, psi, check_buf, s)) != hipSuccess) return hip_fail(e, "dot");
+    if ((as = read2(p, s, &er, &ei)) != SG_OK) return as;
+    st.applies += 1;
+    const double nrm = std::sqrt(nr), E = nr > 0.0 ? er / nr : 0.0;
+    if (!have0) {
+      st.norm0 = nrm;
+      st.energy0 = E;
+      have0 = true;
+    }
+    st.norm_last = nrm;
+    st.energy_last = E;
+    st.max_norm_drift = std::max(st.max_norm_drift, std::fabs(nrm - st.norm0));
+    st.max_energy_drift = std::max(st.max_energy_drift, std::fabs(E - st.energy0));
+    if (norm_trace) norm_trace[ntrace] = nrm;
+    if (energy_trace) energy_trace[ntrace] = E;
+    ++ntrace;
+    if (tol > 0.0 && std::fabs(nrm - st.norm0) > tol) ret = SG_ETOL;
+    return SG_OK;
+  };
+  double2 *hk[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int i = 0; i < 4 && method == SG_PROP_RK && i < order; ++i) hk[i] = B.v + (size_t)(1 + i) * n;
+  sg_status rs = SG_OK;
+  for (int step = 0; step < nsteps && ret == SG_OK; ++step) {
+    if ((step == 0 || (check_every > 0 && step % check_every == 0)) && (rs = check()) != SG_OK)
+      return rs;
+    if (ret != SG_OK) break;
+    if (method == SG_PROP_TAYLOR) {
+      rs = taylor_step(p, psi, dt, order, prec, B.v, B.v + n, s, stream);
+      st.applies += order;
+    } else if (method == SG_PROP_RK) {
+      rs = rk_step(p, psi, dt, kRK[order - 1], prec, B.v, hk, s, stream);
+      st.applies += order;
+    } else {
+      int used = 0;
+      rs = sil_step(p, psi, dt, m, prec, B, s, stream, &used);
+      st.applies += used;
+    }
+    if (rs != SG_OK) return rs;
+    st.steps_done = step + 1;
+  }
+  if (ret == SG_OK && (rs = check()) != SG_OK) return rs;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "propagation");
+  if (stats) *stats = st;
+  if (ret == SG_ETOL) return fail(SG_ETOL, "norm drift beyond tolerance");
+  return SG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+"""GPU Taylor, Runge-Kutta and short-iterative-Lanczos propagation against
+the oracle's propagators (same method, order, step and start state) in FP64,
+element by element; mixed precision against the GPU's own FP64."""
+import numpy as np
+import pytest
+
+import sg_inputs
+from oracle.action import Oracle, galerkin_masked_matrix
+from oracle.propagate import coherent_coefficients
+from oracle.stepping import propagate, taylor_factor
+from tests.gpu_util import rand_state, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+METHODS = {"taylor": 1, "rk": 2, "sil": 3}
+
+
+def _sg():
+    import paper_2111_13655_amd as sg
+    return sg
+
+
+def _run(sg, inst, psi0, method, order, dt, nsteps, precision=None, check_every=0, tol=0.0):
+    precision = sg.SG_FP64 if precision is None else precision
+    with sg.Problem.from_instance(inst) as P:
+        x = to_dev(psi0)
+        status, st, nt, et = sg.sg_propagate(P.handle, x, dt, nsteps, METHODS[method], order,
+                                             tol=tol, precision=precision,
+                                             check_every=check_every)
+        return status, st, nt, et, to_host(x)
+
+
+CASES = [("taylor", 4), ("taylor", 12), ("rk", 1), ("rk", 2), ("rk", 3), ("rk", 4), ("sil", 1),
+         ("sil", 6), ("sil", 16)]
+
+
+@pytest.mark.parametrize("method,order", CASES)
+def test_config0_vs_oracle(method, order):
+    """(D, L) = (2, 4) coupled, displaced Gaussian, 6 steps of 0.05."""
+    sg = _sg()
+    inst = sg_inputs.config0()
+    say(f"stepping config0 {method} {order}")
+    O = Oracle(inst)
+    psi0, _ = coherent_coefficients(O.S.compact, inst.shift)
+    ref = propagate(method, O.apply_literal, psi0, 0.05, 6, order)
+    status, st, nt, et, got = _run(sg, inst, psi0, method, order, 0.05, 6)
+    assert status == sg.SG_OK
+    assert st["steps_done"] == 6
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    if method != "sil":
+        assert st["applies"] == 6 * order + 2
+
+
+@pytest.mark.parametrize("method,order", [("taylor", 8), ("rk", 4), ("sil", 10)])
+def test_small_4d_vs_oracle(method, order):
+    """(D, L) = (4, 4) with cubic couplings: many terms and packs, random
+    complex start state."""
+    sg = _sg()
+    inst = sg_inputs.small_instance(4, 4, seed=11)
+    say(f"stepping d4l4 {method} {order}")
+    O = Oracle(inst)
+    psi0 = rand_state(O.S.n_cs, 5)
+    ref = propagate(method, O.apply_literal, psi0, 0.03, 3, order)
+    status, st, nt, et, got = _run(sg, inst, psi0, method, order, 0.03, 3)
+    assert status == sg.SG_OK
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("method,order", [("rk", 4), ("sil", 12)])
+def test_config1_vs_oracle(method, order):
+    """(D, L) = (6, 6), 2 steps; the oracle applies the masked-Galerkin
+    matrix (equal to the literal per-term action, pinned elsewhere)."""
+    sg = _sg()
+    inst = sg_inputs.config1()
+    say(f"stepping config1 {method} {order}")
+    H = galerkin_masked_matrix(inst).tocsr()
+    O = Oracle(inst)
+    psi0, _ = coherent_coefficients(O.S.compact, inst.shift)
+    ref = propagate(method, lambda v: H @ v, psi0, 0.05, 2, order)
+    status, st, nt, et, got = _run(sg, inst, psi0, method, order, 0.05, 2)
+    assert status == sg.SG_OK
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_uncoupled_closed_forms():
+    """c = k = 0: every eigencomponent gets the truncated exponential series
+    (Taylor, Runge-Kutta) or the exact phase (Lanczos with enough vectors)."""
+    sg = _sg()
+    inst = sg_inputs.small_instance(3, 3, seed=2)
+    inst.c[:] = 0.0
+    inst.k[:] = 0.0
+    O = Oracle(inst)
+    E = (inst.omega[None, :] * (O.S.compact + 0.5)).sum(axis=1)
+    psi0, _ = coherent_coefficients(O.S.compact, inst.shift)
+    dt = 0.07
+    for method, order in [("taylor", 5), ("rk", 3)]:
+        _, _, _, _, got = _run(sg, inst, psi0, method, order, dt, 1)
+        ref = np.array([taylor_factor(-1j * e * dt, order) for e in E]) * psi0
+        assert np.linalg.norm(got - ref) < 1e-13
+    # a start state on five basis functions: five energies, so a Krylov space
+    # of seven holds them all
+    v = np.zeros_like(psi0)
+    v[[0, 3, 7, 12, 20]] = np.array([1, 1j, -1, 0.5, 2]) / np.sqrt(7.25)
+    _, st, _, _, got = _run(sg, inst, v, "sil", 7, 0.3, 1)
+    assert np.linalg.norm(got - np.exp(-1j * E * 0.3) * v) < 1e-12
+    # one eigenvector: the space is invariant after one vector (one apply
+    # in the step, plus the two checks)
+    u = np.zeros_like(psi0)
+    u[3] = 2.0
+    _, st, _, _, got = _run(sg, inst, u, "sil", 8, 0.4, 1)
+    assert np.linalg.norm(got - np.exp(-1j * E * 0.4) * u) < 1e-13
+    assert st["applies"] == 1 + 2
+
+
+def test_sil_norm_energy_trace_and_mixed():
+    sg = _sg()
+    inst = sg_inputs.config1()
+    say("stepping config1 sil traces, mixed")
+    O = Oracle(inst)
+    psi0, _ = coherent_coefficients(O.S.compact, inst.shift)
+    status, st, nt, et, g64 = _run(sg, inst, psi0, "sil", 10, 0.05, 20, check_every=5, tol=1e-9)
+    assert status == sg.SG_OK
+    assert len(nt) >= 4
+    assert np.abs(nt[:5] - 1.0).max() < 1e-12
+    assert np.abs(et[:5] - et[0]).max() < 1e-10
+    assert st["max_norm_drift"] < 1e-12
+    status, st, _, _, gmx = _run(sg, inst, psi0, "sil", 10, 0.05, 20, precision=sg.SG_MIXED)
+    assert status == sg.SG_OK
+    assert np.linalg.norm(gmx - g64) <= 1e-6 * np.linalg.norm(g64)
+
+
+def test_tolerance_and_bad_arguments():
+    sg = _sg()
+    inst = sg_inputs.config0()
+    O = Oracle(inst)
+    psi0, _ = coherent_coefficients(O.S.compact, inst.shift)
+    # first-order Taylor (explicit Euler) grows the norm: a tight tol stops it
+    status, st, _, _, _ = _run(sg, inst, psi0, "taylor", 1, 0.1, 50, check_every=1, tol=1e-6)
+    assert status == sg.SG_ETOL and st["steps_done"] < 50
+    with sg.Problem.from_instance(inst) as P:
+        x = to_dev(psi0)
+        for method, order, dt in [(0, 4, 0.1), (4, 4, 0.1), (1, 0, 0.1), (1, 41, 0.1),
+                                  (2, 5, 0.1), (3, 0, 0.1), (3, 65, 0.1), (2, 4, 0.0),
+                                  (2, 4, -1.0)]:
+            with pytest.raises(sg.SgError):
+                sg.sg_propagate(P.handle, x, dt, 1, method, order)
