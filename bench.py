@@ -158,6 +158,46 @@ def mixed_vs_fp64(sg, reps=20):
             "grid_pts_per_s_active_mixed": t32 * info["grid_active"]}
 
 
+def propagators(sg, steps=40, dt=0.05):
+    """(D, L) = (6, 6), FP64: the Taylor, Runge-Kutta and short-iterative-
+    Lanczos propagators against Chebyshev over the same time span, from the
+    displaced Gaussian: wall time, applies, and the distance of each final
+    state from the Chebyshev one (converged to 1e-16 per step)."""
+    import time
+    import torch
+    import sg_inputs
+    inst = sg_inputs.config1()
+    P = sg.Problem.from_instance(inst)
+    n = P.n_cs
+    psi0 = torch.empty(n, dtype=torch.complex128, device="cuda")
+    sg.sg_init_gaussian(P.handle, inst.shift, psi0)
+
+    def run(fn):
+        x = psi0.clone()
+        fn(x)   # warm-up, same work
+        x = psi0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = fn(x)
+        torch.cuda.synchronize()
+        return x, time.perf_counter() - t0, st
+
+    lo, hi = sg.sg_spectral_bounds(P.handle, 40)
+    ref, t_ref, st_ref = run(lambda x: sg.sg_propagate_chebyshev(P.handle, x, dt, steps,
+                                                                 lo, hi)[1])
+    out = {"workload": f"D=6 L=6, FP64, {steps} steps of dt={dt}",
+           "chebyshev": {"seconds": t_ref, "applies": st_ref["applies"],
+                         "applies_per_s": st_ref["applies"] / t_ref}}
+    for name, method, order in [("taylor_12", sg.SG_PROP_TAYLOR, 12), ("rk_4", sg.SG_PROP_RK, 4),
+                                ("sil_12", sg.SG_PROP_SIL, 12)]:
+        x, t, st = run(lambda x: sg.sg_propagate(P.handle, x, dt, steps, method, order)[1])
+        out[name] = {"seconds": t, "applies": st["applies"], "applies_per_s": st["applies"] / t,
+                     "rel_diff_vs_chebyshev": float(torch.linalg.norm(x - ref) /
+                                                    torch.linalg.norm(ref))}
+    P.close()
+    return out
+
+
 def batched(sg, steps):
     """64 independent instances (D ~ U{4..10}, L ~ U{4..7}) advanced together
     in mixed precision: instance-applies/s over a bounded number of steps."""
@@ -393,6 +433,9 @@ def main():
         log("[bench] mixed vs fp64 (D=12, L=6)")
         out["mixed_vs_fp64"] = mixed_vs_fp64(sg)
         log(f"[bench] {out['mixed_vs_fp64']}")
+        log("[bench] propagators (D=6, L=6)")
+        out["propagators"] = propagators(sg)
+        log(f"[bench] {out['propagators']}")
         log("[bench] batched (64 instances)")
         out["batched"] = batched(sg, args.batch_steps)
         log(f"[bench] {out['batched']}")
