@@ -203,8 +203,11 @@ sg_status sg_propagate_chebyshev(sg_problem *p, void *psi, double dt,
  *   SG_PROP_SIL     short iterative Lanczos with Krylov dimension n (1..64,
  *                   capped at N_cs): Lanczos from psi/|psi| with every new
  *                   vector orthogonalised twice against the earlier ones,
- *                   psi <- |psi| V exp(-i T dt) e_1; ends early on an
- *                   invariant space; up to n applies per step. */
+ *                   psi <- |psi| V exp(-i T dt) e_1; T is cut at the
+ *                   first new vector whose norm is below 1e-13 |psi| (an
+ *                   invariant space); n applies per step, the Krylov
+ *                   recurrence runs on the device and a step reads its
+ *                   coefficients back once. */
 typedef enum {
   SG_PROP_TAYLOR = 1,
   SG_PROP_RK = 2,

@@ -112,7 +112,56 @@ int grid_for(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 4096));
 }
 
+// Lanczos on the device (no host round trip per Krylov vector).
+// coef = -dots[0..m); alpha = (accumulate ? alpha : 0) + Re dots[m-1]
+__global__ void lanczos_project_kernel(const double *dots, int m, double *coef, double *alpha,
+                                       int accumulate) {
+  const int j = threadIdx.x;
+  if (j < m) {
+    coef[2 * j] = -dots[2 * j];
+    coef[2 * j + 1] = -dots[2 * j + 1];
+  }
+  if (j == m - 1) *alpha = (accumulate ? *alpha : 0.0) + dots[2 * j];
+}
+
+// beta = |w| from nrm2 = <w|w>, kept (scale = 1/beta) unless below
+// thr * beta0 (beta0 null: unless zero); a dropped vector gets beta = 0 and
+// scale 0, which zeroes it and every later Krylov vector
+__global__ void lanczos_norm_kernel(const double *nrm2, double *beta, const double *beta0,
+                                    double thr, double *scale) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double b = sqrt(fmax(nrm2[0], 0.0));
+  const bool keep = beta0 ? !(b < thr * beta0[0]) : b > 0.0;
+  beta[0] = keep ? b : 0.0;
+  scale[0] = keep ? 1.0 / b : 0.0;
+}
+
+// dst = scale[0] * src (dst may be src)
+__global__ __launch_bounds__(kBlasThreads) void scale_copy_kernel(double2 *dst, const double2 *src,
+                                                                  const double *scale, int64_t n) {
+  const double c = scale[0];
+  for (int64_t i = (int64_t)blockIdx.x * kBlasThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlasThreads) {
+    const double2 v = src[i];
+    dst[i] = make_double2(c * v.x, c * v.y);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_lanczos_project(const double *dots, int m, double *coef, double *alpha,
+                                  bool accumulate, hipStream_t s) {
+  if (m < 1 || m > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(lanczos_project_kernel, dim3(1), dim3(64), 0, s, dots, m, coef, alpha,
+                     accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_lanczos_norm(const double *nrm2, double *beta, const double *beta0, double thr,
+                               double *scale, hipStream_t s) {
+  hipLaunchKernelGGL(lanczos_norm_kernel, dim3(1), dim3(64), 0, s, nrm2, beta, beta0, thr, scale);
+  return hipGetLastError();
+}
 
 int dot_partials_per_vector() { return kDotBlocks; }
 
@@ -137,6 +186,13 @@ hipError_t launch_precondition(double2 *t, const double2 *r, const double *d, do
                                int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(precondition_kernel, dim3(grid_for(n)), dim3(kBlasThreads), 0, s, t, r, d,
                      theta, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(double2 *dst, const double2 *src, const double *scale, int64_t n,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(scale_copy_kernel, dim3(grid_for(n)), dim3(kBlasThreads), 0, s, dst, src,
+                     scale, n);
   return hipGetLastError();
 }
 

@@ -13,8 +13,8 @@
 //     Lanczos from psi/|psi|, every new vector orthogonalised against all
 //     earlier ones twice; T = tridiag(alpha, beta); psi <- |psi| V
 //     exp(-i T dt) e_1, with exp(-i T dt) from the eigenpairs of T (host).
-//     The recurrence ends early on an invariant space (norm below 1e-13 of
-//     |psi|).
+//     T is cut at the first new vector whose norm is below 1e-13 |psi| (an
+//     invariant space).
 //
 // Every H application is one term sweep plus one reduce; vector updates run
 // in the library's vector kernels; the state never leaves the device.  Only
@@ -37,8 +37,10 @@ struct Buffers {
   double *partials = nullptr;  // multi-dot partial sums
   double *dots = nullptr;      // multi-dot results (re, im)
   double *coef = nullptr;      // multi-axpy coefficients (re, im)
+  double *lz = nullptr;        // Lanczos scalars on the device
   ~Buffers() {
     hipFree(v);
+    hipFree(lz);
     hipFree(partials);
     hipFree(dots);
     hipFree(coef);
@@ -66,20 +68,6 @@ sg_status read2(sg_problem *p, hipStream_t s, double *a, double *b) {
   if (e != hipSuccess) return hip_fail(e, "read reduction result");
   *a = p->h_result[0];
   *b = p->h_result[1];
-  return SG_OK;
-}
-
-// out[j] = conj(V_j)^T w for j < m (host, synchronises)
-sg_status vdots(const Buffers &B, const double2 *V, int64_t n, int m, const double2 *w,
-                std::vector<std::complex<double>> *out, hipStream_t s) {
-  std::vector<double> h(2 * (size_t)m);
-  hipError_t e = launch_multi_dot(V, n, m, w, n, B.partials, B.dots, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(h.data(), B.dots, h.size() * sizeof(double), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(e, "Lanczos projections");
-  out->resize(m);
-  for (int j = 0; j < m; ++j) (*out)[j] = {h[2 * j], h[2 * j + 1]};
   return SG_OK;
 }
 
@@ -143,56 +131,61 @@ sg_status rk_step(sg_problem *p, double2 *psi, double dt, const Tableau &T, sg_p
   return SG_OK;
 }
 
-// V holds m + 1 vectors of n (zero-filled once); returns the Krylov size used
+// V holds m + 1 vectors of n (zero-filled once); lz holds 2m + 1 doubles:
+// beta0, alpha[m], beta[m - 1], a scale slot.  The Krylov vectors, their
+// projections and norms stay on the device; the step reads alpha and beta
+// back once.  A vector whose norm falls below 1e-13 |psi| is dropped with
+// beta = 0 (it and every later vector are zero), and the host cuts T there.
+// Returns the Krylov size used.
 sg_status sil_step(sg_problem *p, double2 *psi, double dt, int m, sg_precision prec,
-                   const Buffers &B, hipStream_t s, void *stream, int *used) {
+                   const Buffers &B, double *lz, hipStream_t s, void *stream, int *used) {
   const int64_t n = p->h.ncs;
   double2 *V = B.v;
+  double *beta0 = lz, *alpha = lz + 1, *beta = lz + 1 + m, *scale = lz + 2 * m;
   hipError_t e = launch_dot(p, psi, psi, s);
-  if (e != hipSuccess) return hip_fail(e, "dot");
-  double nn, ni;
-  sg_status st = read2(p, s, &nn, &ni);
-  if (st != SG_OK) return st;
-  const double beta0 = std::sqrt(std::max(nn, 0.0));
-  *used = 0;
-  if (!(beta0 > 0.0)) return SG_OK;  // the zero state stays zero
-  if ((e = launch_axpby(n, V, psi, 1.0 / beta0, 0.0, 0.0, s)) != hipSuccess)
-    return hip_fail(e, "axpby");
-  std::vector<double> alpha, beta;
-  std::vector<std::complex<double>> c;
+  if (e == hipSuccess) e = launch_lanczos_norm(p->d_result, beta0, nullptr, 0.0, scale, s);
+  if (e == hipSuccess) e = launch_scale_copy(V, psi, scale, n, s);
+  if (e != hipSuccess) return hip_fail(e, "Lanczos start");
+  sg_status st;
   for (int j = 0; j < m; ++j) {
     double2 *w = V + (size_t)(j + 1) * n;
     if ((st = sg_apply_H(p, V + (size_t)j * n, w, prec, stream)) != SG_OK) return st;
-    double a = 0.0;
-    for (int pass = 0; pass < 2; ++pass) {
-      if ((st = vdots(B, V, n, j + 1, w, &c, s)) != SG_OK) return st;
-      a += c[j].real();
-      for (auto &x : c) x = -x;
-      if ((st = combine(B, w, 1.0, V, n, c, s)) != SG_OK) return st;
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+      e = launch_multi_dot(V, n, j + 1, w, n, B.partials, B.dots, s);
+      if (e == hipSuccess) e = launch_lanczos_project(B.dots, j + 1, B.coef, alpha + j, pass > 0, s);
+      if (e == hipSuccess) e = launch_multi_axpy(w, 1.0, V, n, j + 1, B.coef, n, s);
     }
-    alpha.push_back(a);
-    if (j == m - 1) break;
-    if ((e = launch_dot(p, w, w, s)) != hipSuccess) return hip_fail(e, "dot");
-    double bb, bi;
-    if ((st = read2(p, s, &bb, &bi)) != SG_OK) return st;
-    const double b = std::sqrt(std::max(bb, 0.0));
-    if (b < 1e-13 * beta0) break;
-    beta.push_back(b);
-    if ((e = launch_axpby(n, w, w, 1.0 / b, 0.0, 0.0, s)) != hipSuccess)
-      return hip_fail(e, "axpby");
+    if (e == hipSuccess && j < m - 1) {
+      e = launch_dot(p, w, w, s);
+      if (e == hipSuccess) e = launch_lanczos_norm(p->d_result, beta + j, beta0, 1e-13, scale, s);
+      if (e == hipSuccess) e = launch_scale_copy(w, w, scale, n, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "Lanczos step");
   }
-  const int k = (int)alpha.size();
+  std::vector<double> h(2 * (size_t)m);
+  e = hipMemcpyAsync(h.data(), lz, (2 * (size_t)m) * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "read Lanczos coefficients");
+  const double b0 = h[0];
+  *used = 0;
+  if (!(b0 > 0.0)) return SG_OK;  // the zero state stays zero
+  int k = m;
+  for (int j = 0; j + 1 < m; ++j)
+    if (h[1 + m + j] == 0.0) {
+      k = j + 1;
+      break;
+    }
   std::vector<double> T((size_t)k * k, 0.0), ev, U;
   for (int i = 0; i < k; ++i) {
-    T[(size_t)i * k + i] = alpha[i];
-    if (i + 1 < k) T[(size_t)i * k + i + 1] = T[(size_t)(i + 1) * k + i] = beta[i];
+    T[(size_t)i * k + i] = h[1 + i];
+    if (i + 1 < k) T[(size_t)i * k + i + 1] = T[(size_t)(i + 1) * k + i] = h[1 + m + i];
   }
   jacobi_eigen(T, k, &ev, &U);
   // coefficients of psi(t + dt) in V: beta0 U exp(-i ev dt) U^T e_1
   // (U row-major, eigenvectors in columns)
   std::vector<std::complex<double>> coef(k, 0.0);
   for (int q = 0; q < k; ++q) {
-    const std::complex<double> ph = std::polar(1.0, -ev[q] * dt) * (beta0 * U[(size_t)0 * k + q]);
+    const std::complex<double> ph = std::polar(1.0, -ev[q] * dt) * (b0 * U[(size_t)0 * k + q]);
     for (int i = 0; i < k; ++i) coef[i] += U[(size_t)i * k + q] * ph;
   }
   if ((st = combine(B, psi, 0.0, V, n, coef, s)) != SG_OK) return st;
@@ -236,6 +229,7 @@ sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, in
     e = hipMalloc((void **)&B.partials, 2 * mm * dot_partials_per_vector() * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&B.dots, 2 * mm * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&B.coef, 2 * mm * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&B.lz, (2 * mm + 1) * sizeof(double));
   }
   if (e != hipSuccess) return fail(SG_ENOMEM, "propagator work vectors");
   // zero-filled: vector updates read their destination
@@ -288,9 +282,9 @@ sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, in
       rs = rk_step(p, psi, dt, kRK[order - 1], prec, B.v, hk, s, stream);
       st.applies += order;
     } else {
-      int used = 0;
-      rs = sil_step(p, psi, dt, m, prec, B, s, stream, &used);
-      st.applies += used;
+      int used = 0;   // every step applies H m times, dropped vectors included
+      rs = sil_step(p, psi, dt, m, prec, B, B.lz, s, stream, &used);
+      st.applies += m;
     }
     if (rs != SG_OK) return rs;
     st.steps_done = step + 1;

@@ -47,8 +47,7 @@ def test_config0_vs_oracle(method, order):
     assert status == sg.SG_OK
     assert st["steps_done"] == 6
     assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
-    if method != "sil":
-        assert st["applies"] == 6 * order + 2
+    assert st["applies"] == 6 * order + 2
 
 
 @pytest.mark.parametrize("method,order", [("taylor", 8), ("rk", 4), ("sil", 10)])
@@ -103,13 +102,16 @@ def test_uncoupled_closed_forms():
     v[[0, 3, 7, 12, 20]] = np.array([1, 1j, -1, 0.5, 2]) / np.sqrt(7.25)
     _, st, _, _, got = _run(sg, inst, v, "sil", 7, 0.3, 1)
     assert np.linalg.norm(got - np.exp(-1j * E * 0.3) * v) < 1e-12
-    # one eigenvector: the space is invariant after one vector (one apply
-    # in the step, plus the two checks)
+    # one eigenvector: the space is invariant after one vector; the later
+    # Krylov vectors are dropped (zero), the step is still exact
     u = np.zeros_like(psi0)
     u[3] = 2.0
     _, st, _, _, got = _run(sg, inst, u, "sil", 8, 0.4, 1)
     assert np.linalg.norm(got - np.exp(-1j * E * 0.4) * u) < 1e-13
-    assert st["applies"] == 1 + 2
+    assert st["applies"] == 8 + 2
+    # the zero state stays zero
+    _, st, _, _, got = _run(sg, inst, np.zeros_like(psi0), "sil", 4, 0.4, 2)
+    assert np.abs(got).max() == 0.0
 
 
 def test_sil_norm_energy_trace_and_mixed():
