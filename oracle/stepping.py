@@ -1,4 +1,4 @@
-"""Taylor, Runge-Kutta and short-iterative-Lanczos propagation.
+"""Taylor, Runge-Kutta, Bulirsch-Stoer and short-iterative-Lanczos propagation.
 
 Oracle (test infrastructure only).
 
@@ -13,6 +13,11 @@ d psi / dt = -i H psi (hbar = 1):
   (A, b), stages k_i = f(psi + dt sum_{j<i} A_ij k_j), psi += dt sum_i b_i k_i,
   f(y) = -i H y.  Tableaux: Euler (1), explicit midpoint (2), Heun's
   third-order method (3), the classical fourth-order method (4).
+* Bulirsch-Stoer with k extrapolation columns: the modified midpoint rule
+  over n_i = 2i substeps (i = 1..k) of the step, each result extrapolated to
+  zero substep size by the Aitken-Neville recursion in h^2 (the textbook
+  form, e.g. Stoer and Bulirsch, Introduction to Numerical Analysis).
+  Fixed k and fixed step: no error control.
 * Short iterative Lanczos with Krylov dimension m (Park and Light, 1986):
   Lanczos from psi / |psi| builds an orthonormal basis V of the Krylov space
   (each new vector orthogonalised against all earlier ones, twice) and the
@@ -65,6 +70,28 @@ def rk_step(apply, psi: np.ndarray, dt: float, order: int) -> np.ndarray:
     return out
 
 
+def modified_midpoint(apply, psi: np.ndarray, H: float, nsub: int) -> np.ndarray:
+    f = lambda y: -1j * apply(y)
+    h = H / nsub
+    z0 = np.asarray(psi, dtype=np.complex128)
+    z1 = z0 + h * f(z0)
+    for _ in range(1, nsub):
+        z0, z1 = z1, z0 + 2.0 * h * f(z1)
+    return 0.5 * (z1 + z0 + h * f(z1))
+
+
+def bs_step(apply, psi: np.ndarray, dt: float, k: int) -> np.ndarray:
+    ns = [2 * (i + 1) for i in range(k)]
+    rows = []
+    for i, n in enumerate(ns):
+        row = [modified_midpoint(apply, psi, dt, n)]
+        for j in range(1, i + 1):
+            r = (ns[i] / ns[i - j]) ** 2
+            row.append(row[j - 1] + (row[j - 1] - rows[i - 1][j - 1]) / (r - 1.0))
+        rows.append(row)
+    return rows[-1][-1]
+
+
 def lanczos_basis(apply, psi: np.ndarray, m: int):
     """Krylov basis V (columns), the tridiagonal T and |psi|."""
     psi = np.asarray(psi, dtype=np.complex128)
@@ -99,7 +126,7 @@ def sil_step(apply, psi: np.ndarray, dt: float, m: int) -> np.ndarray:
 
 
 def propagate(method: str, apply, psi0: np.ndarray, dt: float, nsteps: int, order: int):
-    step = {"taylor": taylor_step, "rk": rk_step, "sil": sil_step}[method]
+    step = {"taylor": taylor_step, "rk": rk_step, "sil": sil_step, "bs": bs_step}[method]
     psi = np.asarray(psi0, dtype=np.complex128)
     for _ in range(nsteps):
         psi = step(apply, psi, dt, order)

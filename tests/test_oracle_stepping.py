@@ -1,7 +1,8 @@
-"""Pins of the oracle's Taylor, Runge-Kutta and short-iterative-Lanczos
-propagators: the uncoupled closed form (each eigencomponent is multiplied by
-a known polynomial or phase), a dense matrix exponential of the coupled
-operator, and the convergence order of the Runge-Kutta tableaux."""
+"""Pins of the oracle's Taylor, Runge-Kutta, Bulirsch-Stoer and
+short-iterative-Lanczos propagators: the uncoupled closed form (each
+eigencomponent is multiplied by a known polynomial or phase), a dense matrix
+exponential of the coupled operator, and the convergence orders of the
+Runge-Kutta tableaux and of the extrapolation."""
 import numpy as np
 import pytest
 from scipy.linalg import expm
@@ -121,3 +122,44 @@ def test_sil_stops_on_invariant_space():
     assert V.shape[1] == 1 and abs(T[0, 0] - E[3]) < 1e-13 and b0 == 2.0
     got = sil_step(O.apply_literal, v, 0.4, 8)
     assert np.linalg.norm(got - np.exp(-1j * E[3] * 0.4) * v) < 1e-13
+
+
+def test_bs_one_column_closed_form():
+    """One column (two midpoint substeps, no extrapolation) multiplies an
+    eigencomponent by 1 + X + X^2/2 + X^3/8, X = -i E dt (worked out by hand
+    from the midpoint recurrence on y' = lambda y)."""
+    from oracle.stepping import bs_step
+    O, E, psi0 = _uncoupled()
+    dt = 0.06
+    got = bs_step(O.apply_literal, psi0, dt, 1)
+    X = -1j * E * dt
+    ref = (1 + X + X ** 2 / 2 + X ** 3 / 8) * psi0
+    assert np.linalg.norm(got - ref) < 1e-14
+
+
+@pytest.mark.parametrize("k,ratio", [(2, 16.0), (3, 64.0)])
+def test_bs_global_order(k, ratio):
+    """k columns over the substep counts 2, 4, .., 2k: global order 2k."""
+    from oracle.stepping import bs_step
+    inst = sg_inputs.config0()
+    H = galerkin_masked_matrix(inst).toarray()
+    O = Oracle(inst)
+    psi0, _ = coherent_coefficients(O.S.compact, inst.shift)
+    t = 1.0
+    exact = expm(-1j * H * t) @ psi0
+    errs = []
+    for n in (10, 20):
+        got = propagate("bs", lambda v: H @ v, psi0, t / n, n, k)
+        errs.append(np.linalg.norm(got - exact))
+    r = errs[0] / errs[1]
+    assert 0.75 * ratio < r < 1.3 * ratio, errs
+
+
+def test_bs_converged_vs_dense_exponential():
+    inst = sg_inputs.config0()
+    H = galerkin_masked_matrix(inst).toarray()
+    O = Oracle(inst)
+    psi0, _ = coherent_coefficients(O.S.compact, inst.shift)
+    got = propagate("bs", O.apply_literal, psi0, 0.02, 10, 5)
+    ref = expm(-1j * H * 0.2) @ psi0
+    assert np.linalg.norm(got - ref) < 1e-12
