@@ -159,8 +159,8 @@ def mixed_vs_fp64(sg, reps=20):
 
 
 def propagators(sg, steps=40, dt=0.05):
-    """(D, L) = (6, 6), FP64: the Taylor, Runge-Kutta and short-iterative-
-    Lanczos propagators against Chebyshev over the same time span, from the
+    """(D, L) = (6, 6), FP64: the Taylor, Runge-Kutta, short-iterative-Lanczos
+    and Bulirsch-Stoer propagators against Chebyshev over the same span, from the
     displaced Gaussian: wall time, applies, and the distance of each final
     state from the Chebyshev one (converged to 1e-16 per step)."""
     import time
@@ -189,7 +189,7 @@ def propagators(sg, steps=40, dt=0.05):
            "chebyshev": {"seconds": t_ref, "applies": st_ref["applies"],
                          "applies_per_s": st_ref["applies"] / t_ref}}
     for name, method, order in [("taylor_12", sg.SG_PROP_TAYLOR, 12), ("rk_4", sg.SG_PROP_RK, 4),
-                                ("sil_12", sg.SG_PROP_SIL, 12)]:
+                                ("sil_12", sg.SG_PROP_SIL, 12), ("bs_4", sg.SG_PROP_BS, 4)]:
         x, t, st = run(lambda x: sg.sg_propagate(P.handle, x, dt, steps, method, order)[1])
         out[name] = {"seconds": t, "applies": st["applies"], "applies_per_s": st["applies"] / t,
                      "rel_diff_vs_chebyshev": float(torch.linalg.norm(x - ref) /

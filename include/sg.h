@@ -200,6 +200,10 @@ sg_status sg_propagate_chebyshev(sg_problem *p, void *psi, double dt,
  *                   -i H psi with the tableaux of Euler, the explicit
  *                   midpoint rule, Heun's third-order method and the
  *                   classical fourth-order method; n applies per step.
+ *   SG_PROP_BS      Bulirsch-Stoer with n extrapolation columns (1..8): the
+ *                   modified midpoint rule over 2, 4, .., 2n substeps of
+ *                   the step, extrapolated to zero substep size (polynomial
+ *                   in h^2); 1 + n(n+1) applies per step, global order 2n.
  *   SG_PROP_SIL     short iterative Lanczos with Krylov dimension n (1..64,
  *                   capped at N_cs): Lanczos from psi/|psi| with every new
  *                   vector orthogonalised twice against the earlier ones,
@@ -211,7 +215,8 @@ sg_status sg_propagate_chebyshev(sg_problem *p, void *psi, double dt,
 typedef enum {
   SG_PROP_TAYLOR = 1,
   SG_PROP_RK = 2,
-  SG_PROP_SIL = 3
+  SG_PROP_SIL = 3,
+  SG_PROP_BS = 4
 } sg_propagator;
 
 /* Propagates psi (in place, device complex128[N_cs]) over nsteps steps of dt

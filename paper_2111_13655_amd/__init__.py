@@ -24,6 +24,7 @@ __all__ = [
     "sg_free", "sg_problem_info", "sg_basis_indices", "sg_term_levels",
     "sg_mapping_table", "sg_init_gaussian", "sg_apply_H", "sg_spectral_bounds",
     "sg_propagate_chebyshev", "sg_propagate", "SG_PROP_TAYLOR", "SG_PROP_RK", "SG_PROP_SIL",
+    "SG_PROP_BS",
     "sg_set_timing", "sg_get_timing", "sg_set_mixed_threshold",
     "sg_tune_mixed", "sg_set_operator_form", "sg_set_schedule", "sg_tune_schedule",
     "sg_eigensolve", "sg_embed_basis",
@@ -35,7 +36,7 @@ __all__ = [
 SG_OK, SG_EINVAL, SG_ENOMEM, SG_EDEVICE = 0, -1, -2, -3
 SG_EAGAIN, SG_ENOTFOUND, SG_ECANCELED, SG_ETOL = -4, -5, -6, -7
 SG_FP64, SG_MIXED = 0, 1
-SG_PROP_TAYLOR, SG_PROP_RK, SG_PROP_SIL = 1, 2, 3
+SG_PROP_TAYLOR, SG_PROP_RK, SG_PROP_SIL, SG_PROP_BS = 1, 2, 3, 4
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -348,7 +349,8 @@ def sg_propagate_chebyshev(h, psi, dt: float, nsteps: int, emin=math.nan, emax=m
 
 def sg_propagate(h, psi, dt: float, nsteps: int, method: int, order: int, tol: float = 0.0,
                  precision: int = SG_FP64, check_every: int = 0, stream=None):
-    """Taylor / Runge-Kutta / short-iterative-Lanczos propagation in place.
+    """Taylor / Runge-Kutta / short-iterative-Lanczos / Bulirsch-Stoer
+    propagation in place.
     Returns (status, stats dict, norm trace, energy trace)."""
     n_cs = sg_problem_info(h)["n_cs"]
     st = PropStats()

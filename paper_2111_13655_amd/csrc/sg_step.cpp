@@ -1,4 +1,5 @@
-// Taylor, Runge-Kutta and short-iterative-Lanczos propagation on the operator
+// Taylor, Runge-Kutta, Bulirsch-Stoer and short-iterative-Lanczos propagation
+// on the operator
 // action (the other propagators the paper lists beside the Chebyshev method,
 // Sec. 3 overview of the program flow; it gives no formulas).  With hbar = 1
 // and d psi/dt = -i H psi:
@@ -9,6 +10,12 @@
 //     midpoint; Heun's third-order method; the classical fourth-order
 //     method).  Stage i applies H to psi + dt sum_j A_ij k_j with
 //     k_j = -i H y_j; the -i is folded into the complex coefficients.
+//   Bulirsch-Stoer, k columns (1..8): the modified midpoint rule over
+//     n_i = 2i substeps of the step (i = 1..k; H psi is shared by all of
+//     them), extrapolated to zero substep size.  The extrapolated value is
+//     the interpolating polynomial in h^2 at 0, formed here in Lagrange form,
+//     sum_i c_i T_i with c_i = prod_{j != i} i^2 / (i^2 - j^2), in one
+//     vector combination.
 //   Short iterative Lanczos, Krylov dimension m (Park and Light, 1986):
 //     Lanczos from psi/|psi|, every new vector orthogonalised against all
 //     earlier ones twice; T = tridiag(alpha, beta); psi <- |psi| V
@@ -19,8 +26,10 @@
 // Every H application is one term sweep plus one reduce; vector updates run
 // in the library's vector kernels; the state never leaves the device.  Only
 // Lanczos coefficients and checked norms and energies are read back.
+#include <algorithm>
 #include <cmath>
 #include <complex>
+#include <utility>
 #include <vector>
 
 #include "sg_internal.h"
@@ -31,6 +40,7 @@ namespace {
 
 constexpr int kMaxTaylorOrder = 40;
 constexpr int kMaxKrylov = 64;
+constexpr int kMaxColumns = 8;
 
 struct Buffers {
   double2 *v = nullptr;        // vectors, n each
@@ -131,6 +141,43 @@ sg_status rk_step(sg_problem *p, double2 *psi, double dt, const Tableau &T, sg_p
   return SG_OK;
 }
 
+// w: H psi, the two midpoint iterates, H z, then the k midpoint results;
+// coef (device) holds the k extrapolation weights
+sg_status bs_step(sg_problem *p, double2 *psi, double dt, int k, sg_precision prec, double2 *w,
+                  const double *coef, hipStream_t s, void *stream) {
+  const int64_t n = p->h.ncs;
+  double2 *hy = w, *zp = w + n, *z = w + 2 * n, *f = w + 3 * n, *T = w + 4 * n;
+  sg_status st = sg_apply_H(p, psi, hy, prec, stream);
+  if (st != SG_OK) return st;
+  hipError_t e = hipSuccess;
+  for (int i = 1; i <= k; ++i) {
+    const int nsub = 2 * i;
+    const double h = dt / nsub;
+    double2 *a = zp, *b = z;   // z_{m-1}, z_m
+    e = hipMemcpyAsync(a, psi, n * sizeof(double2), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b, psi, n * sizeof(double2), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_axpby(n, b, hy, 0.0, -h, 1.0, s);   // z_1 = z_0 - i h H z_0
+    if (e != hipSuccess) return hip_fail(e, "midpoint start");
+    for (int m = 1; m < nsub; ++m) {
+      if ((st = sg_apply_H(p, b, f, prec, stream)) != SG_OK) return st;
+      // z_{m+1} = z_{m-1} - 2 i h H z_m, written over z_{m-1}
+      if ((e = launch_axpby(n, a, f, 0.0, -2.0 * h, 1.0, s)) != hipSuccess)
+        return hip_fail(e, "midpoint");
+      std::swap(a, b);
+    }
+    if ((st = sg_apply_H(p, b, f, prec, stream)) != SG_OK) return st;
+    // T_i = (z_n + z_{n-1} - i h H z_n) / 2
+    double2 *Ti = T + (size_t)(i - 1) * n;
+    e = launch_axpby(n, Ti, b, 0.5, 0.0, 0.0, s);
+    if (e == hipSuccess) e = launch_axpby(n, Ti, a, 0.5, 0.0, 1.0, s);
+    if (e == hipSuccess) e = launch_axpby(n, Ti, f, 0.0, -0.5 * h, 1.0, s);
+    if (e != hipSuccess) return hip_fail(e, "midpoint end");
+  }
+  if ((e = launch_multi_axpy(psi, 0.0, T, n, k, coef, n, s)) != hipSuccess)
+    return hip_fail(e, "extrapolation");
+  return SG_OK;
+}
+
 // V holds m + 1 vectors of n (zero-filled once); lz holds 2m + 1 doubles:
 // beta0, alpha[m], beta[m - 1], a scale slot.  The Krylov vectors, their
 // projections and norms stay on the device; the step reads alpha and beta
@@ -211,6 +258,8 @@ sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, in
     if (order < 1 || order > 4) return fail(SG_EINVAL, "Runge-Kutta order must be 1..4");
   } else if (method == SG_PROP_SIL) {
     if (order < 1 || order > kMaxKrylov) return fail(SG_EINVAL, "Krylov dimension must be 1..64");
+  } else if (method == SG_PROP_BS) {
+    if (order < 1 || order > kMaxColumns) return fail(SG_EINVAL, "Bulirsch-Stoer columns must be 1..8");
   } else {
     return fail(SG_EINVAL, "unknown propagator");
   }
@@ -219,9 +268,12 @@ sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, in
   double2 *psi = (double2 *)psi_v;
   const int64_t n = p->h.ncs;
   const int m = method == SG_PROP_SIL ? (int)std::min<int64_t>(order, n) : 0;
-  // work vectors: Taylor 2, Runge-Kutta 1 + stages, Lanczos m + 1; one more
-  // for the checks
-  const int nvec = method == SG_PROP_TAYLOR ? 2 : method == SG_PROP_RK ? 1 + order : m + 1;
+  // work vectors: Taylor 2, Runge-Kutta 1 + stages, Lanczos m + 1,
+  // Bulirsch-Stoer 4 + columns; one more for the checks
+  const int nvec = method == SG_PROP_TAYLOR ? 2
+                   : method == SG_PROP_RK   ? 1 + order
+                   : method == SG_PROP_BS   ? 4 + order
+                                            : m + 1;
   Buffers B;
   hipError_t e = hipMalloc((void **)&B.v, (size_t)(nvec + 1) * n * sizeof(double2));
   if (e == hipSuccess && method == SG_PROP_SIL) {
@@ -231,7 +283,23 @@ sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, in
     if (e == hipSuccess) e = hipMalloc((void **)&B.coef, 2 * mm * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&B.lz, (2 * mm + 1) * sizeof(double));
   }
+  if (e == hipSuccess && method == SG_PROP_BS)
+    e = hipMalloc((void **)&B.coef, 2 * (size_t)order * sizeof(double));
   if (e != hipSuccess) return fail(SG_ENOMEM, "propagator work vectors");
+  std::vector<double> bs_w(2 * (size_t)std::max(order, 1), 0.0);
+  if (method == SG_PROP_BS) {
+    // extrapolation to h = 0 of the midpoint results at h_i = dt / (2i):
+    // Lagrange weights in x = h^2, prod_{j != i} x_j / (x_j - x_i)
+    for (int i = 1; i <= order; ++i) {
+      double c = 1.0;
+      for (int j = 1; j <= order; ++j)
+        if (j != i) c *= (double)(i * i) / (double)(i * i - j * j);
+      bs_w[2 * (i - 1)] = c;
+    }
+    if ((e = hipMemcpyAsync(B.coef, bs_w.data(), bs_w.size() * sizeof(double),
+                            hipMemcpyHostToDevice, s)) != hipSuccess)
+      return hip_fail(e, "upload extrapolation weights");
+  }
   // zero-filled: vector updates read their destination
   if ((e = hipMemsetAsync(B.v, 0, (size_t)(nvec + 1) * n * sizeof(double2), s)) != hipSuccess)
     return hip_fail(e, "clear work vectors");
@@ -281,6 +349,9 @@ sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, in
     } else if (method == SG_PROP_RK) {
       rs = rk_step(p, psi, dt, kRK[order - 1], prec, B.v, hk, s, stream);
       st.applies += order;
+    } else if (method == SG_PROP_BS) {
+      rs = bs_step(p, psi, dt, order, prec, B.v, B.coef, s, stream);
+      st.applies += 1 + order * (order + 1);
     } else {
       int used = 0;   // every step applies H m times, dropped vectors included
       rs = sil_step(p, psi, dt, m, prec, B, B.lz, s, stream, &used);

@@ -1,4 +1,4 @@
-"""GPU Taylor, Runge-Kutta and short-iterative-Lanczos propagation against
+"""GPU Taylor, Runge-Kutta, Bulirsch-Stoer and short-iterative-Lanczos propagation against
 the oracle's propagators (same method, order, step and start state) in FP64,
 element by element; mixed precision against the GPU's own FP64."""
 import numpy as np
@@ -12,7 +12,7 @@ from tests.gpu_util import rand_state, say, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-METHODS = {"taylor": 1, "rk": 2, "sil": 3}
+METHODS = {"taylor": 1, "rk": 2, "sil": 3, "bs": 4}
 
 
 def _sg():
@@ -31,7 +31,7 @@ def _run(sg, inst, psi0, method, order, dt, nsteps, precision=None, check_every=
 
 
 CASES = [("taylor", 4), ("taylor", 12), ("rk", 1), ("rk", 2), ("rk", 3), ("rk", 4), ("sil", 1),
-         ("sil", 6), ("sil", 16)]
+         ("sil", 6), ("sil", 16), ("bs", 1), ("bs", 2), ("bs", 4)]
 
 
 @pytest.mark.parametrize("method,order", CASES)
@@ -47,10 +47,11 @@ def test_config0_vs_oracle(method, order):
     assert status == sg.SG_OK
     assert st["steps_done"] == 6
     assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
-    assert st["applies"] == 6 * order + 2
+    per_step = 1 + order * (order + 1) if method == "bs" else order
+    assert st["applies"] == 6 * per_step + 2
 
 
-@pytest.mark.parametrize("method,order", [("taylor", 8), ("rk", 4), ("sil", 10)])
+@pytest.mark.parametrize("method,order", [("taylor", 8), ("rk", 4), ("sil", 10), ("bs", 3)])
 def test_small_4d_vs_oracle(method, order):
     """(D, L) = (4, 4) with cubic couplings: many terms and packs, random
     complex start state."""
@@ -65,7 +66,7 @@ def test_small_4d_vs_oracle(method, order):
     assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("method,order", [("rk", 4), ("sil", 12)])
+@pytest.mark.parametrize("method,order", [("rk", 4), ("sil", 12), ("bs", 2)])
 def test_config1_vs_oracle(method, order):
     """(D, L) = (6, 6), 2 steps; the oracle applies the masked-Galerkin
     matrix (equal to the literal per-term action, pinned elsewhere)."""
@@ -96,6 +97,10 @@ def test_uncoupled_closed_forms():
         _, _, _, _, got = _run(sg, inst, psi0, method, order, dt, 1)
         ref = np.array([taylor_factor(-1j * e * dt, order) for e in E]) * psi0
         assert np.linalg.norm(got - ref) < 1e-13
+    # one Bulirsch-Stoer column: 1 + X + X^2/2 + X^3/8, X = -i E dt
+    _, _, _, _, got = _run(sg, inst, psi0, "bs", 1, dt, 1)
+    X = -1j * E * dt
+    assert np.linalg.norm(got - (1 + X + X ** 2 / 2 + X ** 3 / 8) * psi0) < 1e-13
     # a start state on five basis functions: five energies, so a Krylov space
     # of seven holds them all
     v = np.zeros_like(psi0)
@@ -141,8 +146,8 @@ def test_tolerance_and_bad_arguments():
     assert status == sg.SG_ETOL and st["steps_done"] < 50
     with sg.Problem.from_instance(inst) as P:
         x = to_dev(psi0)
-        for method, order, dt in [(0, 4, 0.1), (4, 4, 0.1), (1, 0, 0.1), (1, 41, 0.1),
-                                  (2, 5, 0.1), (3, 0, 0.1), (3, 65, 0.1), (2, 4, 0.0),
-                                  (2, 4, -1.0)]:
+        for method, order, dt in [(0, 4, 0.1), (5, 4, 0.1), (1, 0, 0.1), (1, 41, 0.1),
+                                  (2, 5, 0.1), (3, 0, 0.1), (3, 65, 0.1), (4, 0, 0.1),
+                                  (4, 9, 0.1), (2, 4, 0.0), (2, 4, -1.0)]:
             with pytest.raises(sg.SgError):
                 sg.sg_propagate(P.handle, x, dt, 1, method, order)

@@ -154,13 +154,14 @@ def test_propagate_rejects_bad_arguments_host_only():
     dummy = ctypes.c_void_p(16)
     try:
         L = sg.lib()
-        for method, order, dt, prec in [(0, 4, 0.1, 0), (4, 4, 0.1, 0), (1, 0, 0.1, 0),
+        for method, order, dt, prec in [(0, 4, 0.1, 0), (5, 4, 0.1, 0), (1, 0, 0.1, 0),
                                         (1, 41, 0.1, 0), (2, 5, 0.1, 0), (3, 65, 0.1, 0),
+                                        (4, 0, 0.1, 0), (4, 9, 0.1, 0),
                                         (2, 4, 0.0, 0), (2, 4, float("nan"), 0), (2, 4, 0.1, 7)]:
             st = L.sg_propagate(P.handle, dummy, dt, 1, method, order, 0.0, prec, 0,
                                 None, None, None, None)
             assert st == sg.SG_EINVAL, (method, order, dt, prec)
-        for method, order in [(1, 1), (1, 40), (2, 1), (2, 4), (3, 1), (3, 64)]:
+        for method, order in [(1, 1), (1, 40), (2, 1), (2, 4), (3, 1), (3, 64), (4, 1), (4, 8)]:
             st = L.sg_propagate(P.handle, dummy, 0.1, 1, method, order, 0.0, 0, 0,
                                 None, None, None, None)
             assert st == sg.SG_EINVAL   # no device tables
