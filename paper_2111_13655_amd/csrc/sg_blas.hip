@@ -113,15 +113,71 @@ int grid_for(int64_t n) {
 }
 
 // Lanczos on the device (no host round trip per Krylov vector).
-// coef = -dots[0..m); alpha = (accumulate ? alpha : 0) + Re dots[m-1]
-__global__ void lanczos_project_kernel(const double *dots, int m, double *coef, double *alpha,
+// coef[j] = -sum_b partials[j][b] (block order, as multi_dot_finish) for
+// j < m; alpha = (accumulate ? alpha : 0) + the real part of the last sum
+__global__ void lanczos_project_kernel(const double *partials, int m, double *coef, double *alpha,
                                        int accumulate) {
   const int j = threadIdx.x;
-  if (j < m) {
-    coef[2 * j] = -dots[2 * j];
-    coef[2 * j + 1] = -dots[2 * j + 1];
+  if (j >= m) return;
+  double re = 0.0, im = 0.0;
+  for (int b = 0; b < kDotBlocks; ++b) {
+    re += partials[((size_t)j * kDotBlocks + b) * 2];
+    im += partials[((size_t)j * kDotBlocks + b) * 2 + 1];
   }
-  if (j == m - 1) *alpha = (accumulate ? *alpha : 0.0) + dots[2 * j];
+  coef[2 * j] = -re;
+  coef[2 * j + 1] = -im;
+  if (j == m - 1) *alpha = (accumulate ? *alpha : 0.0) + re;
+}
+
+// x += sum_j c_j V_j (c complex, j in order), and npart[block] = the block's
+// sum of |x_new|^2 (tree order)
+__global__ __launch_bounds__(kBlasThreads) void multi_axpy_norm_kernel(double2 *x, const double2 *V,
+                                                                       int64_t ld, int m,
+                                                                       const double *c, int64_t n,
+                                                                       double *npart) {
+  __shared__ double s0[kBlasThreads];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlasThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlasThreads) {
+    double re = x[i].x, im = x[i].y;
+    for (int j = 0; j < m; ++j) {
+      const double2 v = V[(size_t)j * ld + i];
+      const double cr = c[2 * j], ci = c[2 * j + 1];
+      re += cr * v.x - ci * v.y;
+      im += cr * v.y + ci * v.x;
+    }
+    x[i] = make_double2(re, im);
+    acc += re * re + im * im;
+  }
+  s0[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kBlasThreads / 2; s >= 1; s >>= 1) {
+    if (threadIdx.x < s) s0[threadIdx.x] += s0[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) npart[blockIdx.x] = s0[0];
+}
+
+// beta from multi_axpy_norm's block sums (fixed order), as lanczos_norm_kernel
+__global__ __launch_bounds__(256) void lanczos_norm_partials_kernel(const double *npart, int nb,
+                                                                    double *beta,
+                                                                    const double *beta0,
+                                                                    double thr, double *scale) {
+  __shared__ double s0[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) a += npart[i];
+  s0[threadIdx.x] = a;
+  __syncthreads();
+  for (int s = 128; s >= 1; s >>= 1) {
+    if (threadIdx.x < s) s0[threadIdx.x] += s0[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double b = sqrt(fmax(s0[0], 0.0));
+    const bool keep = !(b < thr * beta0[0]);
+    beta[0] = keep ? b : 0.0;
+    scale[0] = keep ? 1.0 / b : 0.0;
+  }
 }
 
 // beta = |w| from nrm2 = <w|w>, kept (scale = 1/beta) unless below
@@ -149,11 +205,31 @@ __global__ __launch_bounds__(kBlasThreads) void scale_copy_kernel(double2 *dst, 
 
 }  // namespace
 
-hipError_t launch_lanczos_project(const double *dots, int m, double *coef, double *alpha,
+hipError_t launch_lanczos_project(const double2 *V, int64_t ld, int m, const double2 *w,
+                                  int64_t n, double *partials, double *coef, double *alpha,
                                   bool accumulate, hipStream_t s) {
   if (m < 1 || m > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(lanczos_project_kernel, dim3(1), dim3(64), 0, s, dots, m, coef, alpha,
-                     accumulate ? 1 : 0);
+  hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, m), dim3(kBlasThreads), 0, s, V, ld, w, n,
+                     partials);
+  hipLaunchKernelGGL(lanczos_project_kernel, dim3(1), dim3(64), 0, s, (const double *)partials, m,
+                     coef, alpha, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+int lanczos_norm_partials() { return 4096; }
+
+hipError_t launch_multi_axpy_norm(double2 *x, const double2 *V, int64_t ld, int m,
+                                  const double *c, int64_t n, double *npart, hipStream_t s) {
+  hipLaunchKernelGGL(multi_axpy_norm_kernel, dim3(grid_for(n)), dim3(kBlasThreads), 0, s, x, V,
+                     ld, m, c, n, npart);
+  return hipGetLastError();
+}
+
+hipError_t launch_lanczos_norm_partials(const double *npart, int64_t n, double *beta,
+                                        const double *beta0, double thr, double *scale,
+                                        hipStream_t s) {
+  hipLaunchKernelGGL(lanczos_norm_partials_kernel, dim3(1), dim3(256), 0, s, npart, grid_for(n),
+                     beta, beta0, thr, scale);
   return hipGetLastError();
 }
 

@@ -409,12 +409,22 @@ hipError_t launch_multi_axpy(double2 *x, double beta, const double2 *V, int64_t 
 hipError_t launch_precondition(double2 *t, const double2 *r, const double *d, double theta,
                                int64_t n, hipStream_t s);
 hipError_t launch_zero(double2 *y, int64_t n, hipStream_t s);
-// Lanczos steps on the device (sg_blas.hip): coef = -dots[0..m) and
-// alpha (+)= Re dots[m-1] (m <= 64); beta = sqrt(nrm2[0]) with scale = 1/beta,
-// or both 0 when beta < thr * beta0[0] (beta0 null: when beta is 0);
-// dst = scale[0] * src.
-hipError_t launch_lanczos_project(const double *dots, int m, double *coef, double *alpha,
+// Lanczos steps on the device (sg_blas.hip).  project: coef = -conj(V_j)^T w
+// for j < m (m <= 64; partials as launch_multi_dot) and alpha (+)= the real
+// part of the last.  norm: beta = sqrt(nrm2[0]) with scale = 1/beta, or both
+// 0 when beta < thr * beta0[0] (beta0 null: when beta is 0).  multi_axpy_norm:
+// x += sum_j c_j V_j, with npart (lanczos_norm_partials() doubles) holding
+// block sums of |x|^2 for norm_partials, which then acts as norm.
+// scale_copy: dst = scale[0] * src.
+hipError_t launch_lanczos_project(const double2 *V, int64_t ld, int m, const double2 *w,
+                                  int64_t n, double *partials, double *coef, double *alpha,
                                   bool accumulate, hipStream_t s);
+int lanczos_norm_partials();
+hipError_t launch_multi_axpy_norm(double2 *x, const double2 *V, int64_t ld, int m,
+                                  const double *c, int64_t n, double *npart, hipStream_t s);
+hipError_t launch_lanczos_norm_partials(const double *npart, int64_t n, double *beta,
+                                        const double *beta0, double thr, double *scale,
+                                        hipStream_t s);
 hipError_t launch_lanczos_norm(const double *nrm2, double *beta, const double *beta0, double thr,
                                double *scale, hipStream_t s);
 hipError_t launch_scale_copy(double2 *dst, const double2 *src, const double *scale, int64_t n,

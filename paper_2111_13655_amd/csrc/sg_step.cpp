@@ -45,14 +45,14 @@ constexpr int kMaxColumns = 8;
 struct Buffers {
   double2 *v = nullptr;        // vectors, n each
   double *partials = nullptr;  // multi-dot partial sums
-  double *dots = nullptr;      // multi-dot results (re, im)
   double *coef = nullptr;      // multi-axpy coefficients (re, im)
   double *lz = nullptr;        // Lanczos scalars on the device
+  double *npart = nullptr;     // block sums of |w|^2
   ~Buffers() {
     hipFree(v);
+    hipFree(npart);
     hipFree(lz);
     hipFree(partials);
-    hipFree(dots);
     hipFree(coef);
   }
 };
@@ -197,14 +197,17 @@ sg_status sil_step(sg_problem *p, double2 *psi, double dt, int m, sg_precision p
   for (int j = 0; j < m; ++j) {
     double2 *w = V + (size_t)(j + 1) * n;
     if ((st = sg_apply_H(p, V + (size_t)j * n, w, prec, stream)) != SG_OK) return st;
+    // two projection passes; the second also sums |w|^2 for beta
     for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
-      e = launch_multi_dot(V, n, j + 1, w, n, B.partials, B.dots, s);
-      if (e == hipSuccess) e = launch_lanczos_project(B.dots, j + 1, B.coef, alpha + j, pass > 0, s);
-      if (e == hipSuccess) e = launch_multi_axpy(w, 1.0, V, n, j + 1, B.coef, n, s);
+      e = launch_lanczos_project(V, n, j + 1, w, n, B.partials, B.coef, alpha + j, pass > 0, s);
+      if (e != hipSuccess) break;
+      if (pass == 0 || j == m - 1)
+        e = launch_multi_axpy(w, 1.0, V, n, j + 1, B.coef, n, s);
+      else
+        e = launch_multi_axpy_norm(w, V, n, j + 1, B.coef, n, B.npart, s);
     }
     if (e == hipSuccess && j < m - 1) {
-      e = launch_dot(p, w, w, s);
-      if (e == hipSuccess) e = launch_lanczos_norm(p->d_result, beta + j, beta0, 1e-13, scale, s);
+      e = launch_lanczos_norm_partials(B.npart, n, beta + j, beta0, 1e-13, scale, s);
       if (e == hipSuccess) e = launch_scale_copy(w, w, scale, n, s);
     }
     if (e != hipSuccess) return hip_fail(e, "Lanczos step");
@@ -279,9 +282,10 @@ sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, in
   if (e == hipSuccess && method == SG_PROP_SIL) {
     const size_t mm = (size_t)m + 1;
     e = hipMalloc((void **)&B.partials, 2 * mm * dot_partials_per_vector() * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void **)&B.dots, 2 * mm * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&B.coef, 2 * mm * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&B.lz, (2 * mm + 1) * sizeof(double));
+    if (e == hipSuccess)
+      e = hipMalloc((void **)&B.npart, (size_t)lanczos_norm_partials() * sizeof(double));
   }
   if (e == hipSuccess && method == SG_PROP_BS)
     e = hipMalloc((void **)&B.coef, 2 * (size_t)order * sizeof(double));
