@@ -151,3 +151,33 @@ def test_tolerance_and_bad_arguments():
                                   (4, 9, 0.1), (2, 4, 0.0), (2, 4, -1.0)]:
             with pytest.raises(sg.SgError):
                 sg.sg_propagate(P.handle, x, dt, 1, method, order)
+
+
+def test_zero_steps_and_full_krylov_space():
+    """nsteps = 0 leaves psi alone (one check apply); a Krylov dimension at
+    or above N_cs spans the whole space, so one step is exp(-i H dt)."""
+    from scipy.linalg import expm
+    sg = _sg()
+    inst = sg_inputs.config0()
+    O = Oracle(inst)
+    psi0, _ = coherent_coefficients(O.S.compact, inst.shift)
+    status, st, nt, et, got = _run(sg, inst, psi0, "rk", 4, 0.1, 0)
+    assert status == sg.SG_OK and st["steps_done"] == 0 and st["applies"] == 1
+    assert np.array_equal(got, psi0)
+    H = galerkin_masked_matrix(inst).toarray()
+    _, st, _, _, got = _run(sg, inst, psi0, "sil", 64, 0.4, 1)
+    assert np.linalg.norm(got - expm(-1j * H * 0.4) @ psi0) < 1e-12
+    assert st["applies"] == O.S.n_cs + 2      # the dimension is capped at N_cs
+
+
+@pytest.mark.parametrize("method,order", [("taylor", 10), ("rk", 4), ("bs", 3), ("sil", 8)])
+def test_mixed_precision_vs_fp64(method, order):
+    sg = _sg()
+    inst = sg_inputs.config1()
+    say(f"stepping config1 mixed {method} {order}")
+    O = Oracle(inst)
+    psi0, _ = coherent_coefficients(O.S.compact, inst.shift)
+    _, _, _, _, g64 = _run(sg, inst, psi0, method, order, 0.05, 4)
+    status, _, _, _, gmx = _run(sg, inst, psi0, method, order, 0.05, 4, precision=sg.SG_MIXED)
+    assert status == sg.SG_OK
+    assert np.linalg.norm(gmx - g64) <= 1e-6 * np.linalg.norm(g64)
