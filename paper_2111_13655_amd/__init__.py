@@ -364,7 +364,14 @@ def sg_propagate(h, psi, dt: float, nsteps: int, method: int, order: int, tol: f
     if status not in (SG_OK, SG_ETOL):
         _check(status)
     d = st.as_dict()
-    n = min(ntr, (d["steps_done"] // check_every + 2) if check_every > 0 else 2)
+    done = d["steps_done"]
+    if done < nsteps:
+        # stopped by the drift check at step `done`: checks at 0, ce, .., done
+        n = 1 + (done // check_every if check_every > 0 else 0)
+    else:
+        # checks inside the loop, then the final one
+        n = (0 if nsteps == 0 else 1 + ((nsteps - 1) // check_every if check_every > 0 else 0)) + 1
+    n = min(n, ntr)
     return status, d, nt[:n], et[:n]
 
 

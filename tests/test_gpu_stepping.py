@@ -127,9 +127,9 @@ def test_sil_norm_energy_trace_and_mixed():
     psi0, _ = coherent_coefficients(O.S.compact, inst.shift)
     status, st, nt, et, g64 = _run(sg, inst, psi0, "sil", 10, 0.05, 20, check_every=5, tol=1e-9)
     assert status == sg.SG_OK
-    assert len(nt) >= 4
-    assert np.abs(nt[:5] - 1.0).max() < 1e-12
-    assert np.abs(et[:5] - et[0]).max() < 1e-10
+    assert len(nt) == len(et) == 5          # steps 0, 5, 10, 15 and the end
+    assert np.abs(nt - 1.0).max() < 1e-12
+    assert np.abs(et - et[0]).max() < 1e-10
     assert st["max_norm_drift"] < 1e-12
     status, st, _, _, gmx = _run(sg, inst, psi0, "sil", 10, 0.05, 20, precision=sg.SG_MIXED)
     assert status == sg.SG_OK
@@ -142,8 +142,9 @@ def test_tolerance_and_bad_arguments():
     O = Oracle(inst)
     psi0, _ = coherent_coefficients(O.S.compact, inst.shift)
     # first-order Taylor (explicit Euler) grows the norm: a tight tol stops it
-    status, st, _, _, _ = _run(sg, inst, psi0, "taylor", 1, 0.1, 50, check_every=1, tol=1e-6)
+    status, st, nt, _, _ = _run(sg, inst, psi0, "taylor", 1, 0.1, 50, check_every=1, tol=1e-6)
     assert status == sg.SG_ETOL and st["steps_done"] < 50
+    assert len(nt) == st["steps_done"] + 1 and abs(nt[-1] - nt[0]) > 1e-6
     with sg.Problem.from_instance(inst) as P:
         x = to_dev(psi0)
         for method, order, dt in [(0, 4, 0.1), (5, 4, 0.1), (1, 0, 0.1), (1, 41, 0.1),
