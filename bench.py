@@ -127,9 +127,10 @@ def _throughput(sg, P, prec, reps):
     return reps / (e0.elapsed_time(e1) * 1e-3)
 
 
-def mixed_vs_fp64(sg, reps=20):
+def mixed_vs_fp64(sg, reps=20, prop_steps=20):
     """(D, L) = (12, 6): the precision autotuner's choice at the 1e-6 bar, its
-    measured error against the FP64 apply, and both throughputs."""
+    measured error against the FP64 apply, both throughputs, and the error of
+    a mixed-precision propagation against the FP64 one after every step."""
     import torch
     import sg_inputs
     inst = sg_inputs.config2()
@@ -149,12 +150,34 @@ def mixed_vs_fp64(sg, reps=20):
     err = float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64))
     t64 = _throughput(sg, P, sg.SG_FP64, reps)
     t32 = _throughput(sg, P, sg.SG_MIXED, reps)
+    # propagation from the displaced Gaussian in both precisions, step by
+    # step: relative distance of the mixed state from the FP64 one
+    lo, hi = sg.sg_spectral_bounds(P.handle, 40)
+
+    def prop_errors():
+        a64, a32 = psi.clone(), psi.clone()
+        errs = []
+        for _ in range(prop_steps):
+            sg.sg_propagate_chebyshev(P.handle, a64, 0.05, 1, lo, hi, tol=0.0)
+            sg.sg_propagate_chebyshev(P.handle, a32, 0.05, 1, lo, hi, tol=0.0,
+                                      precision=sg.SG_MIXED)
+            errs.append(float(torch.linalg.norm(a32 - a64) / torch.linalg.norm(a64)))
+        return errs
+
+    step_err = prop_errors()
+    # the same with every |D_l| = 1 term in FP32 (the tuner's bar aside)
+    sg.sg_set_mixed_threshold(P.handle, 1)
+    step_err_1 = prop_errors()
+    sg.sg_set_mixed_threshold(P.handle, thr)
     info = sg.sg_problem_info(P.handle)
     P.close()
     return {"workload": "D=12 L=6 coupled anharmonic (same family), one apply",
             "fp64_applies_per_s": t64, "mixed_applies_per_s": t32, "speedup": t32 / t64,
             "mixed_threshold": thr, "rel_err_vs_fp64_tuning_state": err_tuned,
             "rel_err_vs_fp64_random_state": err, "tol": 1e-6,
+            "propagation_dt": 0.05, "propagation_rel_err_per_step": step_err,
+            "propagation_max_rel_err": max(step_err) if step_err else 0.0,
+            "propagation_rel_err_per_step_threshold_1": step_err_1,
             "grid_pts_per_s_active_mixed": t32 * info["grid_active"]}
 
 
