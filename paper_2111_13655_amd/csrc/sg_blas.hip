@@ -203,7 +203,54 @@ __global__ __launch_bounds__(kBlasThreads) void scale_copy_kernel(double2 *dst, 
   }
 }
 
+// y = c0 x0 + c1 x1 (+ c2 x2 when x2 is not null), complex coefficients;
+// y may be one of the x
+__global__ __launch_bounds__(kBlasThreads) void comb3_kernel(int64_t n, double2 *y,
+                                                             const double2 *x0, double2 c0,
+                                                             const double2 *x1, double2 c1,
+                                                             const double2 *x2, double2 c2) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlasThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlasThreads) {
+    const double2 u = x0[i], v = x1[i];
+    double re = c0.x * u.x - c0.y * u.y + (c1.x * v.x - c1.y * v.y);
+    double im = c0.x * u.y + c0.y * u.x + (c1.x * v.y + c1.y * v.x);
+    if (x2) {
+      const double2 w = x2[i];
+      re += c2.x * w.x - c2.y * w.y;
+      im += c2.x * w.y + c2.y * w.x;
+    }
+    y[i] = make_double2(re, im);
+  }
+}
+
+// t = c x, then acc += t (one pass; the Taylor term and its sum)
+__global__ __launch_bounds__(kBlasThreads) void scale_accumulate_kernel(int64_t n, double2 *t,
+                                                                        const double2 *x,
+                                                                        double2 c, double2 *acc) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlasThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlasThreads) {
+    const double2 u = x[i], a = acc[i];
+    const double re = c.x * u.x - c.y * u.y, im = c.x * u.y + c.y * u.x;
+    t[i] = make_double2(re, im);
+    acc[i] = make_double2(a.x + re, a.y + im);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_comb3(int64_t n, double2 *y, const double2 *x0, double2 c0, const double2 *x1,
+                        double2 c1, const double2 *x2, double2 c2, hipStream_t s) {
+  hipLaunchKernelGGL(comb3_kernel, dim3(grid_for(n)), dim3(kBlasThreads), 0, s, n, y, x0, c0, x1,
+                     c1, x2, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_accumulate(int64_t n, double2 *t, const double2 *x, double2 c,
+                                   double2 *acc, hipStream_t s) {
+  hipLaunchKernelGGL(scale_accumulate_kernel, dim3(grid_for(n)), dim3(kBlasThreads), 0, s, n, t,
+                     x, c, acc);
+  return hipGetLastError();
+}
 
 hipError_t launch_lanczos_project(const double2 *V, int64_t ld, int m, const double2 *w,
                                   int64_t n, double *partials, double *coef, double *alpha,

@@ -429,6 +429,13 @@ hipError_t launch_lanczos_norm(const double *nrm2, double *beta, const double *b
                                double *scale, hipStream_t s);
 hipError_t launch_scale_copy(double2 *dst, const double2 *src, const double *scale, int64_t n,
                              hipStream_t s);
+// Propagator vector updates (sg_blas.hip), complex coefficients:
+// comb3: y = c0 x0 + c1 x1 (+ c2 x2 if x2), y may alias an x;
+// scale_accumulate: t = c x, acc += t.
+hipError_t launch_comb3(int64_t n, double2 *y, const double2 *x0, double2 c0, const double2 *x1,
+                        double2 c1, const double2 *x2, double2 c2, hipStream_t s);
+hipError_t launch_scale_accumulate(int64_t n, double2 *t, const double2 *x, double2 c,
+                                   double2 *acc, hipStream_t s);
 hipError_t launch_embed(const double2 *x, const int32_t *map, int64_t nx, double2 *y, int64_t ny,
                         hipStream_t s);
 

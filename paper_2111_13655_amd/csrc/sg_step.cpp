@@ -106,22 +106,32 @@ sg_status taylor_step(sg_problem *p, double2 *psi, double dt, int order, sg_prec
     sg_status st = sg_apply_H(p, term, hv, prec, stream);
     if (st != SG_OK) return st;
     // term = (-i dt / k) H term ; psi += term
-    if ((e = launch_axpby(n, term, hv, 0.0, -dt / k, 0.0, s)) != hipSuccess ||
-        (e = launch_axpby(n, psi, term, 1.0, 0.0, 1.0, s)) != hipSuccess)
-      return hip_fail(e, "axpby");
+    if ((e = launch_scale_accumulate(n, term, hv, make_double2(0.0, -dt / k), psi, s)) !=
+        hipSuccess)
+      return hip_fail(e, "Taylor update");
   }
   return SG_OK;
 }
 
+// hk: the stage vectors H y_i, contiguous; wcoef (device): -i dt b_i
 sg_status rk_step(sg_problem *p, double2 *psi, double dt, const Tableau &T, sg_precision prec,
-                  double2 *y, double2 *const hk[4], hipStream_t s, void *stream) {
+                  double2 *y, double2 *const hk[4], const double *wcoef, hipStream_t s,
+                  void *stream) {
   const int64_t n = p->h.ncs;
   hipError_t e;
   for (int i = 0; i < T.s; ++i) {
     const double2 *in = psi;
-    bool any = false;
-    for (int j = 0; j < i; ++j) any = any || T.A[i][j] != 0.0;
-    if (any) {
+    int nz = 0, jz = -1;
+    for (int j = 0; j < i; ++j)
+      if (T.A[i][j] != 0.0) ++nz, jz = j;
+    if (nz == 1) {
+      // y = psi + dt A_ij k_j,  k_j = -i H y_j  (the tableaux here have one)
+      if ((e = launch_comb3(n, y, psi, make_double2(1.0, 0.0), hk[jz],
+                            make_double2(0.0, -dt * T.A[i][jz]), nullptr, make_double2(0.0, 0.0),
+                            s)) != hipSuccess)
+        return hip_fail(e, "stage input");
+      in = y;
+    } else if (nz > 1) {
       if ((e = hipMemcpyAsync(y, psi, n * sizeof(double2), hipMemcpyDeviceToDevice, s)) !=
           hipSuccess)
         return hip_fail(e, "copy");
@@ -135,9 +145,9 @@ sg_status rk_step(sg_problem *p, double2 *psi, double dt, const Tableau &T, sg_p
     sg_status st = sg_apply_H(p, in, hk[i], prec, stream);
     if (st != SG_OK) return st;
   }
-  for (int i = 0; i < T.s; ++i)
-    if (T.b[i] != 0.0 && (e = launch_axpby(n, psi, hk[i], 0.0, -dt * T.b[i], 1.0, s)) != hipSuccess)
-      return hip_fail(e, "axpby");
+  // psi += sum_i (-i dt b_i) H y_i
+  if ((e = launch_multi_axpy(psi, 1.0, hk[0], n, T.s, wcoef, n, s)) != hipSuccess)
+    return hip_fail(e, "Runge-Kutta update");
   return SG_OK;
 }
 
@@ -155,8 +165,10 @@ sg_status bs_step(sg_problem *p, double2 *psi, double dt, int k, sg_precision pr
     const double h = dt / nsub;
     double2 *a = zp, *b = z;   // z_{m-1}, z_m
     e = hipMemcpyAsync(a, psi, n * sizeof(double2), hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(b, psi, n * sizeof(double2), hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = launch_axpby(n, b, hy, 0.0, -h, 1.0, s);   // z_1 = z_0 - i h H z_0
+    // z_1 = z_0 - i h H z_0
+    if (e == hipSuccess)
+      e = launch_comb3(n, b, psi, make_double2(1.0, 0.0), hy, make_double2(0.0, -h), nullptr,
+                       make_double2(0.0, 0.0), s);
     if (e != hipSuccess) return hip_fail(e, "midpoint start");
     for (int m = 1; m < nsub; ++m) {
       if ((st = sg_apply_H(p, b, f, prec, stream)) != SG_OK) return st;
@@ -168,10 +180,9 @@ sg_status bs_step(sg_problem *p, double2 *psi, double dt, int k, sg_precision pr
     if ((st = sg_apply_H(p, b, f, prec, stream)) != SG_OK) return st;
     // T_i = (z_n + z_{n-1} - i h H z_n) / 2
     double2 *Ti = T + (size_t)(i - 1) * n;
-    e = launch_axpby(n, Ti, b, 0.5, 0.0, 0.0, s);
-    if (e == hipSuccess) e = launch_axpby(n, Ti, a, 0.5, 0.0, 1.0, s);
-    if (e == hipSuccess) e = launch_axpby(n, Ti, f, 0.0, -0.5 * h, 1.0, s);
-    if (e != hipSuccess) return hip_fail(e, "midpoint end");
+    if ((e = launch_comb3(n, Ti, b, make_double2(0.5, 0.0), a, make_double2(0.5, 0.0), f,
+                          make_double2(0.0, -0.5 * h), s)) != hipSuccess)
+      return hip_fail(e, "midpoint end");
   }
   if ((e = launch_multi_axpy(psi, 0.0, T, n, k, coef, n, s)) != hipSuccess)
     return hip_fail(e, "extrapolation");
@@ -287,10 +298,10 @@ sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, in
     if (e == hipSuccess)
       e = hipMalloc((void **)&B.npart, (size_t)lanczos_norm_partials() * sizeof(double));
   }
-  if (e == hipSuccess && method == SG_PROP_BS)
+  if (e == hipSuccess && (method == SG_PROP_BS || method == SG_PROP_RK))
     e = hipMalloc((void **)&B.coef, 2 * (size_t)order * sizeof(double));
   if (e != hipSuccess) return fail(SG_ENOMEM, "propagator work vectors");
-  std::vector<double> bs_w(2 * (size_t)std::max(order, 1), 0.0);
+  std::vector<double> wts(2 * (size_t)std::max(order, 1), 0.0);
   if (method == SG_PROP_BS) {
     // extrapolation to h = 0 of the midpoint results at h_i = dt / (2i):
     // Lagrange weights in x = h^2, prod_{j != i} x_j / (x_j - x_i)
@@ -298,11 +309,20 @@ sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, in
       double c = 1.0;
       for (int j = 1; j <= order; ++j)
         if (j != i) c *= (double)(i * i) / (double)(i * i - j * j);
-      bs_w[2 * (i - 1)] = c;
+      wts[2 * (i - 1)] = c;
     }
-    if ((e = hipMemcpyAsync(B.coef, bs_w.data(), bs_w.size() * sizeof(double),
+    if ((e = hipMemcpyAsync(B.coef, wts.data(), wts.size() * sizeof(double),
                             hipMemcpyHostToDevice, s)) != hipSuccess)
       return hip_fail(e, "upload extrapolation weights");
+  } else if (method == SG_PROP_RK) {
+    // Runge-Kutta weights as coefficients of H y_i: -i dt b_i
+    for (int i = 0; i < order; ++i) {
+      wts[2 * i] = 0.0;
+      wts[2 * i + 1] = -dt * kRK[order - 1].b[i];
+    }
+    if ((e = hipMemcpyAsync(B.coef, wts.data(), wts.size() * sizeof(double),
+                            hipMemcpyHostToDevice, s)) != hipSuccess)
+      return hip_fail(e, "upload Runge-Kutta weights");
   }
   // zero-filled: vector updates read their destination
   if ((e = hipMemsetAsync(B.v, 0, (size_t)(nvec + 1) * n * sizeof(double2), s)) != hipSuccess)
@@ -351,7 +371,7 @@ sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, in
       rs = taylor_step(p, psi, dt, order, prec, B.v, B.v + n, s, stream);
       st.applies += order;
     } else if (method == SG_PROP_RK) {
-      rs = rk_step(p, psi, dt, kRK[order - 1], prec, B.v, hk, s, stream);
+      rs = rk_step(p, psi, dt, kRK[order - 1], prec, B.v, hk, B.coef, s, stream);
       st.applies += order;
     } else if (method == SG_PROP_BS) {
       rs = bs_step(p, psi, dt, order, prec, B.v, B.coef, s, stream);
