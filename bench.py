@@ -329,8 +329,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                                   "described in DESIGN.md but not implemented",
+        print(json.dumps({"error": "the library runs on one GPU; term sharding across GPUs "
+                                   "is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
