@@ -355,9 +355,11 @@ sg_status sg_tune_mixed(sg_problem *p, const void *psi, double tol, int32_t reps
 sg_status sg_set_schedule(sg_problem *p, int32_t block_min_grid, int32_t packs_per_cu);
 
 /* Schedule autotuner.  Times `reps` applies of precision prec on the device
- * vector psi (complex128[N_cs], not modified) for each candidate schedule
- * (block_min_grid 0 and each power of two from 64 to the largest term grid,
- * each with packs_per_cu 1 and 2) and keeps the fastest.  Every candidate's
+ * vector psi (complex128[N_cs], not modified), best of three rounds, for each
+ * candidate schedule (block_min_grid 0 and each power of two from 64 to the
+ * largest term grid, each with packs_per_cu 1 and 2).  It keeps the default
+ * (0, 1) unless another candidate is faster by more than 1%, and each later
+ * replacement must beat the current choice by as much.  Every candidate's
  * result is compared bitwise with the first's; a difference returns
  * SG_EDEVICE (the schedule is left as it was).  Writes the choice (both
  * nullable).  Synchronises `stream`; uses the handle's work buffers. */

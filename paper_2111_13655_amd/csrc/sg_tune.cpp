@@ -149,16 +149,23 @@ sg_status sg_tune_schedule(sg_problem *p, const void *psi, int32_t prec, int32_t
       st = fail(SG_EDEVICE, "schedules disagree bitwise");
       break;
     }
-    hipEventRecord(e0, s);
-    for (int r = 0; r < reps && st == SG_OK; ++r)
-      st = sg_apply_H(p, psi, out, (sg_precision)prec, stream);
+    // best of three timed rounds
+    double t = 1e300;
+    for (int round = 0; round < 3 && st == SG_OK; ++round) {
+      hipEventRecord(e0, s);
+      for (int r = 0; r < reps && st == SG_OK; ++r)
+        st = sg_apply_H(p, psi, out, (sg_precision)prec, stream);
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      t = std::min(t, (double)ms);
+    }
     if (st != SG_OK) break;
-    hipEventRecord(e1, s);
-    hipEventSynchronize(e1);
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best_t) {
-      best_t = ms;
+    // the default schedule (the first candidate) stays unless another one is
+    // faster by more than the timing noise
+    if (i == 0 || t < 0.99 * best_t) {
+      best_t = t;
       best = cand[i];
     }
   }
