@@ -149,11 +149,21 @@ __device__ __forceinline__ void row_epilogue(const ReduceArgs &a, cptr<InstDev> 
   }
 }
 
+// Workgroups are dealt to the eight XCDs in turn (workgroup i to XCD i mod
+// 8).  The item groups are renumbered so that each XCD takes a contiguous run:
+// neighbouring rows, whose contributions share cache lines, then meet in one
+// L2.  A bijection on [0, nb).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t x = b % kXcds, q = nb / kXcds, r = nb % kXcds;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + b / kXcds;
+}
+
 // step 5 (second half): compact[r] = sum of its term-major contributions
 __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t gw = (int64_t)blockIdx.x * (kRedThreads / 64) + wave;
+  const int64_t gw = xcd_block(blockIdx.x, gridDim.x) * (kRedThreads / 64) + wave;
   if (gw >= a.nitems) return;
   const cptr<RedItem> it = a.items + gw;
   const int chunk = it->chunk;
