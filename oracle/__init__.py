@@ -13,7 +13,7 @@ Modules
 smolyak    term set R(l), combination coefficients D_l, compact basis, M^B,
            size counts (Sec. 2, Sec. 3, Tables 1 and 2)
 hermite    Hermite-function basis and Gauss-Hermite grid tables (Sec. 2,
-           eq_g_to_b / eq_b_to_g; "Hm" primitive basis of Sec. 4.5)
+           eq_g_to_b / eq_b_to_g; "Hm" primitive basis of the Example subsection of Sec. 4)
 action     Route 1: Alg. 1 taken literally for every term; Route 2: the
            masked-Galerkin closed form; a brute-force direct-product check
 propagate  initial displaced Gaussian, Chebyshev propagator, energy/norm

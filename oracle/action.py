@@ -192,6 +192,67 @@ def galerkin_masked_matrix(inst, ranker: CompactRanker | None = None,
     return H
 
 
+def galerkin_masked_apply(inst, psi: np.ndarray, compact: np.ndarray) -> np.ndarray:
+    """Route 2 applied without assembling the matrix: the same sums as
+    galerkin_masked_matrix, H_S[n, m] = <n|H|m> [sum_i max(g(n_i), g(m_i)) <= L],
+    taken row-wise over the coupling's pair shifts.  A shifted tuple's column
+    is found by binary search of its base-(nmax+1) code among the codes of
+    the compact tuples, which increase in the lexicographic compact order.
+    compact: [N_cs, D] tuples in compact order."""
+    D, L = inst.D, inst.L
+    N = np.asarray(compact, dtype=np.int64)
+    ncs = N.shape[0]
+    nmax = int(N.max()) if ncs else 0
+    base = nmax + 1
+    weights = base ** np.arange(D - 1, -1, -1, dtype=np.int64)
+    codes = N @ weights
+    if ncs > 1 and not np.all(np.diff(codes) > 0):
+        raise ValueError("compact tuples are not in lexicographic order")
+    Q1, Q2 = position_matrices(nmax + 2)
+    g = lowest_level(np.arange(nmax + 3), inst.nb_A, inst.nb_B)
+    gsum = g[N].sum(axis=1)
+    psi = np.asarray(psi, dtype=np.complex128)
+    out = (inst.omega[None, :] * (N + 0.5)).sum(axis=1) * psi
+    # per mode and shift d: is n_i + d a one-mode index, the rise of the
+    # joint level max(g(n_i), g(n_i + d)) - g(n_i), and <n_i|Q|n_i+d>,
+    # <n_i|Q^2|n_i+d>
+    shifts = (-2, -1, 0, 1, 2)
+    ok, rise, q1, q2 = {}, {}, {}, {}
+    for i in range(D):
+        ni = N[:, i]
+        for d in shifts:
+            m = ni + d
+            v = (m >= 0) & (m <= nmax)
+            mc = np.clip(m, 0, nmax)
+            ok[i, d] = v
+            rise[i, d] = np.maximum(g[ni], g[mc]) - g[ni]
+            q1[i, d] = np.where(v, Q1[ni, mc], 0.0)
+            q2[i, d] = np.where(v, Q2[ni, mc], 0.0)
+    ar = np.arange(ncs)
+
+    def add_pair(i, j, di, dj, coef, qi, qj):
+        keep = ok[i, di] & ok[j, dj] & (gsum + rise[i, di] + rise[j, dj] <= L)
+        if not keep.any():
+            return
+        r = ar[keep]
+        c = codes[r] + di * weights[i] + dj * weights[j]
+        cols = np.searchsorted(codes, c)
+        assert np.array_equal(codes[cols], c)
+        out[r] += coef * qi[i, di][r] * qj[j, dj][r] * psi[cols]
+
+    for i in range(D):
+        for j in range(i + 1, D):
+            if inst.c[i, j] != 0.0:
+                for di in (-2, 0, 2):
+                    for dj in (-2, 0, 2):
+                        add_pair(i, j, di, dj, inst.c[i, j], q2, q2)
+            if inst.k[i, j] != 0.0:
+                for di in (-2, 0, 2):
+                    for dj in (-1, 1):
+                        add_pair(i, j, di, dj, inst.k[i, j], q2, q1)
+    return out
+
+
 def galerkin_rows(inst, ranker: CompactRanker, tuples: np.ndarray):
     """Rows of H_S for a few compact tuples (for sampled checks at full size):
     returns a list of (cols, vals)."""

@@ -3,7 +3,7 @@
 Oracle (test infrastructure only).
 
 The paper's worked example uses the "Hm" primitive basis (harmonic-oscillator
-Hermite functions centred at Q0=0 with scaleQ=1, Sec. 4.5) and the
+Hermite functions centred at Q0=0 with scaleQ=1, Example subsection of Sec. 4) and the
 basis<->grid transforms eq_b_to_g and eq_g_to_b of Sec. 2, where the grid
 transform weights each point by w_u b_k(Q_u).  Reading of the weight
 convention: the Gauss-Hermite weights w_u integrate f(x) e^{-x^2}; the

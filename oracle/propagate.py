@@ -112,6 +112,3 @@ def exact_propagator(H: np.ndarray, psi0: np.ndarray, t: float) -> np.ndarray:
     ev, V = np.linalg.eigh(np.asarray(H))
     return V @ (np.exp(-1j * ev * t) * (V.T @ psi0))
 
-
-def energy(apply, psi: np.ndarray) -> float:
-    return float(np.real(np.vdot(psi, apply(psi))) / np.real(np.vdot(psi, psi)))

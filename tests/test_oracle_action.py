@@ -9,8 +9,8 @@ import numpy as np
 import pytest
 
 import sg_inputs
-from oracle.action import (Oracle, brute_force_masked, galerkin_masked_matrix,
-                           galerkin_rows)
+from oracle.action import (Oracle, brute_force_masked, galerkin_masked_apply,
+                           galerkin_masked_matrix, galerkin_rows)
 from oracle.quadrature import smolyak_integrate_monomial
 from oracle.smolyak import CompactRanker
 
@@ -115,6 +115,28 @@ def test_galerkin_rows_match_matrix():
         row = np.zeros(len(E))
         np.add.at(row, cols, vals)
         assert np.abs(row - H[i]).max() < 1e-14
+
+
+@pytest.mark.parametrize("D,L,seed", [(2, 4, 1), (4, 3, 2), (5, 3, 3), (3, 5, 4)])
+def test_masked_apply_matches_route1_and_matrix(D, L, seed):
+    """The matrix-free Route 2 equals the literal Alg. 1 (Route 1) and the
+    assembled masked matrix on the same state."""
+    inst = sg_inputs.small_instance(D, L, seed=seed)
+    O = Oracle(inst)
+    psi = _rand(O.S.n_cs, seed)
+    r1 = O.apply_literal(psi)
+    r2 = galerkin_masked_matrix(inst) @ psi
+    r3 = galerkin_masked_apply(inst, psi, O.S.compact)
+    assert np.linalg.norm(r3 - r1) / np.linalg.norm(r1) < 1e-13
+    assert np.abs(r3 - r2).max() < 1e-13 * np.abs(r2).max()
+
+
+def test_masked_apply_rejects_unordered_basis():
+    inst = sg_inputs.small_instance(2, 2, seed=1)
+    rk = CompactRanker(2, 2, 1, 2)
+    E = rk.enumerate()[::-1]
+    with pytest.raises(ValueError):
+        galerkin_masked_apply(inst, np.ones(len(E)), E)
 
 
 def _exact_monomial(alpha):

@@ -54,8 +54,15 @@ def test_uncoupled_closed_form():
     psi0, _ = coherent_coefficients(O.S.compact, inst.shift)
     lo, hi = E.min(), E.max()
     pad = 0.05 * (hi - lo)
-    psi, _ = propagate(O.apply_literal, psi0, 0.05, 40, lo - pad, hi + pad)
+    psi, rec = propagate(O.apply_literal, psi0, 0.05, 40, lo - pad, hi + pad, check_every=8)
     ref = np.exp(-1j * E * 40 * 0.05) * psi0
+    # the energy each step records (from phi_1) is the closed form
+    # <psi|H|psi> = sum_n |c_n|^2 E_n of the uncoupled operator
+    e_closed = float(np.sum(np.abs(psi0) ** 2 * E))
+    assert len(rec) == 5
+    for _, nrm, e in rec:
+        assert abs(nrm - 1.0) < 1e-13
+        assert abs(e - e_closed) < 1e-12
     assert np.linalg.norm(psi - ref) < 1e-12
     # autocorrelation C(t) = sum |c_n|^2 e^{-i E_n t}
     C = np.vdot(psi0, psi)

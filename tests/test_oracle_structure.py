@@ -1,5 +1,6 @@
 """Pins of the oracle's Smolyak structure against the paper's printed values
 (Tables 1 and 2) and against closed-form identities."""
+import itertools
 import math
 import os
 
@@ -115,3 +116,24 @@ def test_ranker_roundtrip():
     # lexicographic, mode 1 slowest
     keys = [tuple(r) for r in E.tolist()]
     assert keys == sorted(keys)
+
+
+def test_ranker_contains_rejects_non_members():
+    """The compact set is {n : 0 <= n_i <= nmax, sum_i g(n_i) <= L} (the union
+    of the term bases, Sec. 3 and Table 2).  Tuples just past the level budget,
+    with a negative entry or with an entry above the largest one-mode index are
+    outside it; brute force over a box decides every tuple."""
+    D, L = 3, 3
+    rk = CompactRanker(D, L, 1, 2)
+    g = lambda n: (n + 1) // 2          # lowest level holding index n (nb = 2l+1)
+    nmax = 2 * L
+    box = np.array(list(itertools.product(range(-1, nmax + 2), repeat=D)), dtype=np.int64)
+    want = np.array([all(0 <= x <= nmax for x in t) and sum(g(x) for x in t) <= L
+                     for t in box.tolist()])
+    got = rk.contains(box)
+    assert np.array_equal(got, want)
+    assert (~want).sum() > 0 and want.sum() == rk.size
+    # level budget L + 1 exactly: rejected
+    assert not rk.contains(np.array([[3, 2, 2], [6, 1, 0], [0, 0, 7]])).any()
+    assert not rk.contains(np.array([[-1, 0, 0], [0, -2, 1]])).any()
+    assert rk.contains(np.array([[2, 2, 1], [6, 0, 0], [0, 0, 5]])).all()
