@@ -22,7 +22,7 @@
  *       + sum_{i<j} c_ij Q_i^2 Q_j^2 + sum_{i<j} k_ij Q_i^2 Q_j
  *
  * Primitive basis per mode: orthonormal Hermite functions ("Hm", Q0 = 0,
- * scaleQ = 1, Sec. 4.5) with N^b_l = nb_A + nb_B l functions and
+ * scaleQ = 1, Example subsection of Sec. 4) with N^b_l = nb_A + nb_B l functions and
  * N^q_l = nq_A + nq_B l Gauss-Hermite points at level l (N_l = A + B l,
  * Sec. 2).  Term set R(l): l_i >= 0, L-D+1 <= |l| <= L, with
  * D_l = (-1)^(L-|l|) C(D-1, L-|l|) (Sec. 2).
@@ -68,15 +68,19 @@ typedef enum {
 } sg_status;
 
 typedef enum {
-  /* Alg. 1 as stated: per term, the potential and the kinetic second-
-   * derivative matrices are applied on the term's grid; all FP64. */
+  /* All FP64.  Alg. 1 per term: gather, basis -> grid, operator on the grid,
+   * grid -> basis, scatter-add.  By default the separable harmonic part
+   * sum_i omega_i (n_i + 1/2) is split off and applied exactly as a diagonal
+   * on the compact basis, and only the coupling potential goes through the
+   * term grids (the same operator: every term's quadrature integrates the
+   * separable part exactly and the D_l of the terms holding a basis function
+   * sum to 1).  sg_set_operator_form(p, 1) selects the literal form, with
+   * the kinetic second-derivative matrices applied on every term grid. */
   SG_FP64 = 0,
-  /* Mixed: the separable harmonic part sum_i omega_i (n_i + 1/2) is applied
-   * exactly in FP64 on the compact basis (each term's quadrature reproduces it
-   * exactly and the D_l of the terms holding a basis function sum to 1), the
-   * coupling goes through the term grids with FP32 contractions on the
-   * matrix cores (FP32 accumulation), and the Smolyak sum, the Chebyshev state
-   * and all reductions stay FP64. */
+  /* Mixed: the split form above, with the grid contractions of the terms
+   * with |D_l| <= a threshold (sg_set_mixed_threshold, sg_tune_mixed) in
+   * FP32 on the vector ALUs with FP32 accumulation, and the other terms,
+   * the Smolyak sum, the Chebyshev state and all reductions in FP64. */
   SG_MIXED = 1
 } sg_precision;
 
@@ -112,6 +116,13 @@ typedef struct {
   int64_t device_bytes;    /* device memory held by the handle                 */
   int32_t fp64_split;      /* 1: SG_FP64 applies the split form                */
   int32_t pad;
+  double sweep_bytes;      /* HBM bytes the term sweep of one SG_FP64 apply must
+                              move as designed: psi read once, M^B, the
+                              term-major results written, term records and the
+                              per-fiber potential coefficients it reads        */
+  double reduce_bytes;     /* ... the reduce: term-major results and inverse map
+                              read, row lists, psi and the diagonal read, the
+                              result written                                   */
 } sg_info;
 
 /* Sizes of a problem without building it: out[0] = N_st, out[1] = N_s,
@@ -247,14 +258,20 @@ sg_status sg_propagate(sg_problem *p, void *psi, double dt, int32_t nsteps,
  * reduction).  The batch references the problems; they must outlive it. */
 typedef struct sg_batch sg_batch;
 sg_status sg_batch_create(sg_problem *const *problems, int32_t n, sg_batch **out);
-/* psi[i]: device complex128[N_cs(i)] of instance i, propagated in place by
- * nsteps steps of dt[i].  emin/emax: per-instance bounds (NaN: estimated by
+/* Number of instances of a batch and, if n_cs is not NULL, each instance's
+ * N_cs (n_cs: caller array of that many entries). */
+sg_status sg_batch_size(const sg_batch *b, int32_t *n, int64_t *n_cs);
+/* n: number of entries of psi and dt, which must equal the batch's number
+ * of instances (SG_EINVAL otherwise).  psi[i]: device complex128[N_cs(i)] of
+ * instance i (the library cannot check its length: a shorter buffer is read
+ * and written past its end), propagated in place by nsteps steps of dt[i].  emin/emax: per-instance bounds (NaN: estimated by
  * sg_spectral_bounds).  check_every as in sg_propagate_chebyshev (norms and
  * energies of all instances are reduced together).  stats: nullable array of
  * n.  use_graph != 0 replays each step from a captured hipGraph (on a stream
  * the library owns, ordered after and before `stream` by events).  Returns
  * SG_ETOL if any instance drifts beyond tol. */
-sg_status sg_batch_propagate(sg_batch *b, void *const *psi, const double *dt, int32_t nsteps,
+sg_status sg_batch_propagate(sg_batch *b, void *const *psi, int32_t n, const double *dt,
+                             int32_t nsteps,
                              const double *emin, const double *emax, double tol,
                              sg_precision prec, int32_t check_every, int32_t use_graph,
                              sg_prop_stats *stats, void *stream);

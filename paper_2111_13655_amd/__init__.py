@@ -28,7 +28,7 @@ __all__ = [
     "sg_set_timing", "sg_get_timing", "sg_set_mixed_threshold",
     "sg_tune_mixed", "sg_set_operator_form", "sg_set_schedule", "sg_tune_schedule",
     "sg_eigensolve", "sg_embed_basis",
-    "sg_batch_create", "sg_batch_propagate", "sg_batch_free",
+    "sg_batch_create", "sg_batch_size", "sg_batch_propagate", "sg_batch_free",
     "ServeConfig", "sg_serve_create", "sg_serve_submit", "sg_serve_poll", "sg_serve_cancel",
     "sg_serve_counters", "sg_serve_destroy", "Problem",
 ]
@@ -70,7 +70,8 @@ class Info(ctypes.Structure):
                 ("flops_mixed", ctypes.c_double), ("sweep_flops_fp64", ctypes.c_double),
                 ("sweep_flops_mixed", ctypes.c_double), ("bytes_fp64", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("fp64_split", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("pad", ctypes.c_int32), ("sweep_bytes", ctypes.c_double),
+                ("reduce_bytes", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -159,7 +160,10 @@ _SIGNATURES = {
                                     ctypes.POINTER(PropStats), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double), _P]),
     "sg_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)]),
-    "sg_batch_propagate": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_double),
+    "sg_batch_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int64)]),
+    "sg_batch_propagate": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_double),
                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_double,
                                           ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
@@ -352,12 +356,17 @@ def sg_propagate(h, psi, dt: float, nsteps: int, method: int, order: int, tol: f
     """Taylor / Runge-Kutta / short-iterative-Lanczos / Bulirsch-Stoer
     propagation in place.
     Returns (status, stats dict, norm trace, energy trace)."""
+    return _propagate("sg_propagate", h, psi, dt, nsteps, method, order, tol, precision,
+                      check_every, stream)
+
+
+def _propagate(entry, h, psi, dt, nsteps, method, order, tol, precision, check_every, stream):
     n_cs = sg_problem_info(h)["n_cs"]
     st = PropStats()
     ntr = max((nsteps // check_every + 2) if check_every > 0 else 2, 2)
     nt = np.zeros(ntr)
     et = np.zeros(ntr)
-    status = lib().sg_propagate(
+    status = getattr(lib(), entry)(
         h, _vec_ptr(psi, n_cs, "psi"), float(dt), int(nsteps), int(method), int(order),
         float(tol), int(precision), int(check_every), ctypes.byref(st), _dptr(nt), _dptr(et),
         _stream_ptr(stream))
@@ -459,14 +468,27 @@ def sg_batch_create(handles) -> ctypes.c_void_p:
     return b
 
 
+def sg_batch_size(b):
+    """(number of instances, list of their N_cs)."""
+    n = ctypes.c_int32(0)
+    _check(lib().sg_batch_size(b, ctypes.byref(n), None))
+    ncs = (ctypes.c_int64 * max(n.value, 1))()
+    _check(lib().sg_batch_size(b, ctypes.byref(n), ncs))
+    return n.value, [int(ncs[i]) for i in range(n.value)]
+
+
 def sg_batch_propagate(b, psis, dts, nsteps: int, emins=None, emaxs=None, tol: float = 1e-8,
                        precision: int = SG_FP64, check_every: int = 0, use_graph: bool = False,
                        stream=None):
-    """psis: list of device complex128 tensors (the instances' states, in place).
-    Returns (status, list of stats dicts)."""
+    """psis: list of device complex128 tensors, one per instance in batch order,
+    each of that instance's N_cs (propagated in place).  Returns (status, list
+    of stats dicts)."""
+    n_inst, n_cs = sg_batch_size(b)
     n = len(psis)
-    for t in psis:
-        _vec_ptr(t, t.numel(), "psi")
+    if n != n_inst:
+        raise ValueError(f"{n} states for a batch of {n_inst} instances")
+    for i, t in enumerate(psis):
+        _vec_ptr(t, n_cs[i], f"psi[{i}]")
     ptrs = (_P * n)(*[t.data_ptr() for t in psis])
     dt = np.ascontiguousarray(dts, dtype=np.float64).reshape(n)
     lo = None if emins is None else np.ascontiguousarray(emins, dtype=np.float64).reshape(n)
@@ -474,7 +496,7 @@ def sg_batch_propagate(b, psis, dts, nsteps: int, emins=None, emaxs=None, tol: f
     null = ctypes.POINTER(ctypes.c_double)()
     st = (PropStats * n)()
     status = lib().sg_batch_propagate(
-        b, ptrs, _dptr(dt), int(nsteps), _dptr(lo) if lo is not None else null,
+        b, ptrs, n, _dptr(dt), int(nsteps), _dptr(lo) if lo is not None else null,
         _dptr(hi) if hi is not None else null, float(tol), int(precision), int(check_every),
         1 if use_graph else 0, st, _stream_ptr(stream))
     if status not in (SG_OK, SG_ETOL):

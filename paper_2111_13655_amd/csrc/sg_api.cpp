@@ -99,7 +99,6 @@ void release(sg_problem *p) {
   hipFree(p->d_partials);
   hipFree(p->d_abc);
   hipFree(p->d_rpart);
-  hipFree(p->d_rcnt);
   hipFree(p->d_cheb_a);
   hipFree(p->d_result);
   if (p->h_result) hipHostFree(p->h_result);
@@ -161,7 +160,7 @@ int64_t estimate_device_bytes(const Compiled &h) {
   const int64_t ns = (int64_t)h.MB.size();
   return (int64_t)h.terms.size() * (int64_t)sizeof(TermDev) + (int64_t)h.pairs.size() * 8 + (int64_t)h.potc.size() * 8 +
          ns * 4 * 2 + (h.ncs + 1) * 4 + h.ncs * 4 + h.ncs * 8 + ns * 16 + 4 * h.ncs * 16 +
-         4 * std::max<int64_t>(h.n_items, 256) * 8 + 4 * std::max<int64_t>(h.n_long_rows, 1) +
+         4 * std::max<int64_t>(h.n_items, 256) * 8 +
          6 * std::max<int64_t>(h.nfib, 1) * 8 +
          (int64_t)h.tables.size() * 20 +
          (int64_t)sizeof(double) * (kMaxChebTerms + 8);
@@ -218,14 +217,6 @@ sg_status upload_problem(sg_problem *p, sg_problem **out) {
   e = hipMalloc((void **)&p->d_rpart, 2 * (size_t)npart * sizeof(double));
   if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
   bytes += 2 * npart * (int64_t)sizeof(double);
-  {
-    const size_t cnt_bytes = (size_t)std::max<int64_t>(h.n_long_rows, 1) * sizeof(int32_t);
-    e = hipMalloc((void **)&p->d_rcnt, cnt_bytes);
-    if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
-    e = hipMemset(p->d_rcnt, 0, cnt_bytes);
-    if (e != hipSuccess) { release(p); return hip_fail(e, "clear the row counters"); }
-    bytes += (int64_t)cnt_bytes;
-  }
   e = hipMalloc((void **)&p->d_cheb_a, kMaxChebTerms * sizeof(double));
   if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
   e = hipMalloc((void **)&p->d_result, 8 * sizeof(double));
@@ -312,6 +303,11 @@ sg_status sg_problem_info(const sg_problem *p, sg_info *out) {
   out->device_bytes = p->device_bytes;
   out->fp64_split = split ? 1 : 0;
   out->pad = 0;
+  const double ns = (double)h.MB.size(), ncs = (double)h.ncs;
+  out->sweep_bytes = 16.0 * ncs + 4.0 * ns + 16.0 * ns +
+                     4.0 * kTermHdrDwords * (double)h.nterms + (split ? 24.0 * (double)h.nfib : 0.0);
+  out->reduce_bytes = 16.0 * ns + 4.0 * ns + 8.0 * ncs + 16.0 * ncs + (split ? 8.0 * ncs : 0.0) +
+                      16.0 * ncs;
   return SG_OK;
 }
 
@@ -390,15 +386,33 @@ sg_status sg_apply_H(sg_problem *p, const void *psi_in, void *psi_out, sg_precis
   return SG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Rebuilds and re-uploads a problem's launch plan after a setting changed.
+// The device is synchronised first: launches still in flight on any stream
+// read the plan's packs and items, which the upload overwrites in place.
+sg_status rebuild_plan(sg_problem *p) {
+  if (p->host_only) return SG_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "synchronise before the plan upload");
+  std::string err;
+  sg_status st = plan_build(p->plan, {p}, &err);
+  if (st != SG_OK) return fail(st, err);
+  st = plan_upload(p->plan, nullptr);
+  if (st != SG_OK) return st;
+  e = hipStreamSynchronize(nullptr);
+  return e == hipSuccess ? SG_OK : hip_fail(e, "plan upload");
+}
+}  // namespace
+
+extern "C" {
+
 sg_status sg_set_mixed_threshold(sg_problem *p, int32_t max_fp32_coeff) {
   if (!p) return fail(SG_EINVAL, "NULL problem");
   if (max_fp32_coeff < 0) return fail(SG_EINVAL, "threshold must be >= 0");
   p->h.mixed_max_fp32_coeff = max_fp32_coeff;
-  if (p->host_only) return SG_OK;
-  std::string err;
-  sg_status st = plan_build(p->plan, {p}, &err);
-  if (st != SG_OK) return fail(st, err);
-  return plan_upload(p->plan, nullptr);
+  return rebuild_plan(p);
 }
 
 sg_status sg_set_schedule(sg_problem *p, int32_t block_min_grid, int32_t packs_per_cu) {
@@ -407,21 +421,13 @@ sg_status sg_set_schedule(sg_problem *p, int32_t block_min_grid, int32_t packs_p
   if (packs_per_cu < 1 || packs_per_cu > 4) return fail(SG_EINVAL, "packs_per_cu must be 1..4");
   p->block_grid = block_min_grid;
   p->packs_per_cu = packs_per_cu;
-  if (p->host_only) return SG_OK;
-  std::string err;
-  sg_status st = plan_build(p->plan, {p}, &err);
-  if (st != SG_OK) return fail(st, err);
-  return plan_upload(p->plan, nullptr);
+  return rebuild_plan(p);
 }
 sg_status sg_set_operator_form(sg_problem *p, int32_t grid_kinetic) {
   if (!p) return fail(SG_EINVAL, "NULL problem");
   if (grid_kinetic != 0 && grid_kinetic != 1) return fail(SG_EINVAL, "grid_kinetic must be 0 or 1");
   p->grid_kinetic = grid_kinetic;
-  if (p->host_only) return SG_OK;
-  std::string err;
-  sg_status st = plan_build(p->plan, {p}, &err);
-  if (st != SG_OK) return fail(st, err);
-  return plan_upload(p->plan, nullptr);
+  return rebuild_plan(p);
 }
 
 sg_status sg_set_timing(sg_problem *p, int32_t enable) {

@@ -91,11 +91,21 @@ sg_status sg_batch_free(sg_batch *b) {
   return SG_OK;
 }
 
-sg_status sg_batch_propagate(sg_batch *b, void *const *psi, const double *dt, int32_t nsteps,
-                             const double *emin, const double *emax, double tol,
+sg_status sg_batch_size(const sg_batch *b, int32_t *n, int64_t *n_cs) {
+  if (!b || !n) return fail(SG_EINVAL, "NULL argument");
+  *n = (int32_t)b->probs.size();
+  if (n_cs)
+    for (size_t i = 0; i < b->probs.size(); ++i) n_cs[i] = b->probs[i]->h.ncs;
+  return SG_OK;
+}
+
+sg_status sg_batch_propagate(sg_batch *b, void *const *psi, int32_t n_psi, const double *dt,
+                             int32_t nsteps, const double *emin, const double *emax, double tol,
                              sg_precision prec, int32_t check_every, int32_t use_graph,
                              sg_prop_stats *stats, void *stream) {
   if (!b || !psi || !dt) return fail(SG_EINVAL, "NULL argument");
+  if (n_psi != (int32_t)b->probs.size())
+    return fail(SG_EINVAL, "the number of states must equal the batch's number of instances");
   if (nsteps < 0 || check_every < 0) return fail(SG_EINVAL, "nsteps, check_every must be >= 0");
   if (prec != SG_FP64 && prec != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
   hipStream_t s = (hipStream_t)stream;

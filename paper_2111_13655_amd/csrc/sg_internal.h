@@ -115,8 +115,7 @@ struct InstDev {
   double2 *x0, *x1;         // apply: x0 -> x1.  Chebyshev: phi buffers, x0 = psi
   double2 *acc;             // Chebyshev running sum
   double *partials;         // [2 * nitems] norm / energy partial sums
-  double *rpart;            // [2 * nitems] partial sums of split long rows
-  int32_t *rcnt;            // [nlong] arrival counters of split long rows (kept at 0)
+  double *rpart;            // [2 * nitems] chunk sums of long rows of several chunks
   double *result;           // [2] finalised sums
   const double *cheb_a;     // [K] series coefficients (2 - delta_k0) J_k(R)
   int64_t ncs;
@@ -188,6 +187,15 @@ constexpr int kLongRow = 64;
 constexpr int kRowWaves = 4;
 constexpr int kRowChunk = 1024;
 constexpr int kShortLanes = 8;
+// A long row of several chunks: its chunks leave their sums in rpart (at
+// first_slot + kRowWaves c for chunk c), and a second kernel adds them in
+// chunk order and runs the row's epilogue.
+struct FinItem {
+  int32_t inst;
+  int32_t row;          // compact row
+  int32_t first_slot;   // reduce-item slot of the row's chunk 0
+  int32_t nch;          // chunks
+};
 // One reduce work item = one wavefront: a long row, or 8 short rows.
 struct RedItem {
   int32_t inst;
@@ -276,6 +284,7 @@ struct PackCache {
   int32_t pack_lds[kPackSets] = {0, 0, 0, 0};   // largest pack, tables excluded
   int64_t scratch[kPackSets] = {0, 0, 0, 0};    // scratch bytes of each set
   std::vector<RedItem> items;              // inst = 0
+  std::vector<FinItem> fin;                // inst = 0
   bool inst32 = false;
 };
 }  // namespace sg
@@ -303,7 +312,6 @@ struct sg_problem {
   double2 *d_work = nullptr;       // 4 * N_cs: Chebyshev phi, ACC, spares
   double *d_partials = nullptr;    // [2 * n_items] reduction partials
   double *d_rpart = nullptr;       // [2 * n_items] chunk sums of long rows
-  int32_t *d_rcnt = nullptr;       // [n_long_rows] chunk arrival counters
   double *d_cheb_a = nullptr;      // [kMaxChebTerms] series coefficients
   int grid_kinetic = 0;            // 1: SG_FP64 applies the kinetic matrices on the grid
   int32_t block_grid = 0;          // > 0: terms of at least this many grid points run on a
@@ -338,12 +346,15 @@ struct Plan {
   std::vector<PackDev> packs;
   PackSet sets[kPackSets];
   std::vector<RedItem> items;
+  std::vector<FinItem> fin;        // long rows of several chunks
   InstDev *d_inst = nullptr;
   PackDev *d_packs = nullptr;
   RedItem *d_items = nullptr;
+  FinItem *d_fin = nullptr;
   char *d_scratch = nullptr;
   int64_t scratch_bytes = 0;
-  int64_t packs_capacity = 0, items_capacity = 0, inst_capacity = 0, scratch_capacity = 0;
+  int64_t packs_capacity = 0, items_capacity = 0, inst_capacity = 0, scratch_capacity = 0,
+          fin_capacity = 0;
   bool any32 = false;              // some term of some instance runs in FP32
   bool fp64_split = false;         // SG_FP64 launches use the split form
   bool any_round32 = false;        // some instance's FP64 terms use rounded tables
@@ -455,4 +466,31 @@ void release_problem(sg_problem *p);
 
 // Chebyshev series for one instance: K and coefficients for R = dE dt / 2.
 int chebyshev_series(double R, std::vector<double> *a);
+
+// Work buffers of one sg_propagate call (sg_step.cpp): allocated for the call
+// (owned), or carved out of a region the caller provides (not owned).
+struct PropBuffers {
+  double2 *v = nullptr;        // vectors, n each
+  double *partials = nullptr;  // multi-dot partial sums
+  double *coef = nullptr;      // multi-axpy coefficients (re, im)
+  double *lz = nullptr;        // Lanczos scalars on the device
+  double *npart = nullptr;     // block sums of |w|^2
+  bool owned = true;
+  ~PropBuffers();
+};
+// Argument checks and work sizes (m: Krylov dimension used; nvec: work
+// vectors besides the check vector).
+sg_status propagate_check(sg_problem *p, void *psi, double dt, int32_t nsteps, int32_t method,
+                          int32_t order, sg_precision prec, int32_t check_every, int *m,
+                          int *nvec);
+// Byte offsets (256-byte aligned) of v, partials, coef, lz, npart in one
+// region; returns the region's size.
+int64_t propagate_layout(int64_t n, int32_t method, int32_t order, int m, int nvec,
+                         int64_t off[5]);
+// The propagation on prepared buffers; zero_kernel clears the work vectors
+// with a fill kernel instead of hipMemsetAsync.
+sg_status propagate_run(sg_problem *p, void *psi, double dt, int32_t nsteps, int32_t method,
+                        int32_t order, int m, int nvec, double tol, sg_precision prec,
+                        int32_t check_every, sg_prop_stats *stats, double *norm_trace,
+                        double *energy_trace, void *stream, PropBuffers &B, bool zero_kernel);
 }  // namespace sg

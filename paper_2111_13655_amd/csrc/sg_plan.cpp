@@ -264,7 +264,6 @@ void inst_from_problem(const sg_problem *p, InstDev *d) {
   d->abc = p->d_abc;
   d->nfib = p->h.nfib;
   d->rpart = p->d_rpart;
-  d->rcnt = p->d_rcnt;
   d->result = p->d_result;
   d->cheb_a = p->d_cheb_a;
   d->ncs = h.ncs;
@@ -285,13 +284,15 @@ namespace {
 constexpr int kTabMax64 = ((std_table_base(8) * 8 + 15) / 16) * 16;
 constexpr int kTabMax32 = ((std_table_base(8) * 4 + 15) / 16) * 16;
 
-void reduce_items(const sg_problem *p, int32_t inst, std::vector<RedItem> *items) {
+void reduce_items(const sg_problem *p, int32_t inst, std::vector<RedItem> *items,
+                  std::vector<FinItem> *fin) {
   const Compiled &h = p->h;
   auto at = [&](int64_t q, const int32_t *base) { return base ? base + q : nullptr; };
   int32_t local = 0;
   for (int64_t q = 0; q < h.n_long_rows; ++q) {
     const int64_t len = h.red_ptr[q + 1] - h.red_ptr[q];
     const int32_t nch = (int32_t)((len + kRowChunk - 1) / kRowChunk);
+    if (nch > 1) fin->push_back({inst, h.rows[q], local, nch});
     for (int32_t c = 0; c < nch; ++c)
       for (int32_t w = 0; w < kRowWaves; ++w)
         items->push_back({inst, (int32_t)q, local++, c | (nch << 12) | (w << 24),
@@ -338,7 +339,8 @@ void build_cache(sg_problem *p) {
     c.pack_lds[k] = ps.count ? ps.lds_bytes - ps.tab_bytes : 0;
   }
   c.items.clear();
-  reduce_items(p, 0, &c.items);
+  c.fin.clear();
+  reduce_items(p, 0, &c.items, &c.fin);
   c.thr = h.mixed_max_fp32_coeff;
   c.grid_kinetic = p->grid_kinetic;
   c.block_grid = p->block_grid;
@@ -368,6 +370,7 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
   pl->inst.assign(probs.size(), InstDev{});
   pl->packs.clear();
   pl->items.clear();
+  pl->fin.clear();
   pl->scratch_bytes = 0;
   pl->any32 = false;
   pl->fp64_split = false;
@@ -386,6 +389,9 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
       const size_t first = pl->items.size();
       pl->items.insert(pl->items.end(), p->pcache.items.begin(), p->pcache.items.end());
       for (size_t q = first; q < pl->items.size(); ++q) pl->items[q].inst = (int32_t)i;
+      const size_t ffirst = pl->fin.size();
+      pl->fin.insert(pl->fin.end(), p->pcache.fin.begin(), p->pcache.fin.end());
+      for (size_t q = ffirst; q < pl->fin.size(); ++q) pl->fin[q].inst = (int32_t)i;
     } else {
       for (int64_t t = 0; t < h.nterms; ++t) {
         cg64.push_back(make_cand((int32_t)i, (int32_t)t, h, false, 16, p->d_mb, p->block_grid));
@@ -397,7 +403,7 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
           m64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16, p->d_mb, p->block_grid));
         }
       }
-      reduce_items(p, (int32_t)i, &pl->items);
+      reduce_items(p, (int32_t)i, &pl->items, &pl->fin);
     }
     pl->inst[i].round32 = inst32 ? 1 : 0;
     pl->any32 = pl->any32 || inst32;
@@ -503,6 +509,12 @@ sg_status plan_upload(Plan *pl, hipStream_t s) {
     return fail(SG_ENOMEM, "device allocation of reduce items failed");
   if ((e = ensure(&pl->d_scratch, &pl->scratch_capacity, pl->scratch_bytes, nullptr)) != hipSuccess)
     return fail(SG_ENOMEM, "device allocation of sweep scratch failed");
+  if ((e = ensure(&pl->d_fin, &pl->fin_capacity, (int64_t)pl->fin.size(), nullptr)) != hipSuccess)
+    return fail(SG_ENOMEM, "device allocation of long-row items failed");
+  if (!pl->fin.empty() &&
+      (e = hipMemcpyAsync(pl->d_fin, pl->fin.data(), pl->fin.size() * sizeof(FinItem),
+                          hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(e, "upload long-row items");
   if (!pl->packs.empty() &&
       (e = hipMemcpyAsync(pl->d_packs, pl->packs.data(), pl->packs.size() * sizeof(PackDev),
                           hipMemcpyHostToDevice, s)) != hipSuccess)
@@ -553,6 +565,7 @@ void plan_free(Plan *pl) {
   hipFree(pl->d_inst);
   hipFree(pl->d_packs);
   hipFree(pl->d_items);
+  hipFree(pl->d_fin);
   hipFree(pl->d_scratch);
   hipFree(pl->d_stab64);
   hipFree(pl->d_stab32r);
@@ -563,8 +576,10 @@ void plan_free(Plan *pl) {
   pl->d_inst = nullptr;
   pl->d_packs = nullptr;
   pl->d_items = nullptr;
+  pl->d_fin = nullptr;
   pl->d_scratch = nullptr;
   pl->inst_capacity = pl->packs_capacity = pl->items_capacity = pl->scratch_capacity = 0;
+  pl->fin_capacity = 0;
 }
 
 }  // namespace sg

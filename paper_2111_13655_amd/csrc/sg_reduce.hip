@@ -191,19 +191,16 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
   const glb_p<const Z64> tm = (glb_p<const Z64>)I->tm;
   const glb_p<const int32_t> col = (glb_p<const int32_t>)I->inv_col;
   double pn = 0.0, pe = 0.0;
-  int slot = it->local;     // where this item's norm / energy partials go
-  bool write_part = true;
   if (nch) {
     // one chunk of a long row on the whole workgroup: wavefront `sub` sums
     // its share, the shares are added in wavefront order through LDS
     __shared__ double wsum[2][kRowWaves];
-    const int q = it->first;
     const int c = chunk & 0xfff, sub = chunk >> 24;
     row = lrow;
     b = lb;
     e = le;
     RowIn in{};
-    if (sub == 0) in = row_inputs(a, I, row);
+    if (sub == 0 && nch == 1) in = row_inputs(a, I, row);
     const int cb = b + c * kRowChunk + sub * (kRowChunk / kRowWaves);
     double sr = 0.0, si = 0.0;
     strided_sum<64, kRowChunk / kRowWaves / 64>(col, tm, cb,
@@ -229,52 +226,17 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
       if (nch == 1) {
         if (lane == 0) row_epilogue(a, I, row, in, sr, si, &pn, &pe);
       } else {
-        // publish this chunk's sum, then count arrivals; the last chunk adds
-        // the chunk sums in chunk order (device-scope atomics: chunks run on
-        // different compute units)
-        const int first_slot = it->local - kRowWaves * c;
-        int last = 0;
+        // a row of several chunks: leave this chunk's sum in its slot; the
+        // finish kernel, launched after this one on the same stream, adds
+        // the chunk sums in chunk order (the kernel boundary orders the
+        // stores before its loads) and runs the row's epilogue.  This
+        // chunk's norm / energy slot is cleared here; the finish kernel
+        // fills chunk 0's.
         if (lane == 0) {
-          __hip_atomic_store(I->rpart + 2 * it->local, sr, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(I->rpart + 2 * it->local + 1, si, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-          __builtin_amdgcn_s_waitcnt(0);
-          const int old = __hip_atomic_fetch_add(I->rcnt + q, 1, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-          last = old == nch - 1;
+          I->rpart[2 * it->local] = sr;
+          I->rpart[2 * it->local + 1] = si;
         }
-        last = __builtin_amdgcn_readfirstlane(last);
-        if (last) {
-          if (lane == 0) {
-            double tr = 0.0, ti = 0.0;
-            for (int cc = 0; cc < nch; ++cc) {
-              if (cc == c) {
-                tr += sr;
-                ti += si;
-              } else {
-                const int sl = first_slot + kRowWaves * cc;
-                tr += __hip_atomic_load(I->rpart + 2 * sl, __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-                ti += __hip_atomic_load(I->rpart + 2 * sl + 1, __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-              }
-            }
-            row_epilogue(a, I, row, in, tr, ti, &pn, &pe);
-            __hip_atomic_store(I->rcnt + q, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
-          // the row's partials go to its first chunk's slot; a later chunk
-          // also clears its own slot
-          slot = first_slot;
-          if (c != 0 && a.mode == 1 && a.k == 1 && a.want_partials && lane == 0) {
-            I->partials[2 * it->local] = 0.0;
-            I->partials[2 * it->local + 1] = 0.0;
-          }
-        } else {
-          // chunk 0's slot belongs to the row; other chunks clear their own
-          write_part = c != 0;
-          pn = pe = 0.0;
-        }
+        pn = pe = 0.0;
       }
     }
   } else {
@@ -289,13 +251,37 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
     si = group_sum<kShortLanes>(si);
     if (valid && sub == 0) row_epilogue(a, I, row, in, sr, si, &pn, &pe);
   }
-  if (a.mode == 1 && a.k == 1 && a.want_partials && write_part) {
+  if (a.mode == 1 && a.k == 1 && a.want_partials) {
     pn = group_sum<64>(pn);
     pe = group_sum<64>(pe);
     if (lane == 0) {
-      I->partials[2 * slot] = pn;
-      I->partials[2 * slot + 1] = pe;
+      I->partials[2 * it->local] = pn;
+      I->partials[2 * it->local + 1] = pe;
     }
+  }
+}
+
+// Long rows of several chunks: one lane per row adds its chunk sums in chunk
+// order, then runs the row's epilogue; the row's norm / energy partials go
+// to its chunk-0 slot.
+__global__ __launch_bounds__(64) void finish_kernel(ReduceArgs a, const FinItem *fin, int nfin) {
+  const int f = blockIdx.x * 64 + threadIdx.x;
+  if (f >= nfin) return;
+  const FinItem it = fin[f];
+  const cptr<InstDev> I = a.inst + it.inst;
+  if (I->active == 0 || (a.mode == 1 && a.k > I->K - 1)) return;
+  const RowIn in = row_inputs(a, I, it.row);
+  double sr = 0.0, si = 0.0;
+  for (int c = 0; c < it.nch; ++c) {
+    const int sl = it.first_slot + kRowWaves * c;
+    sr += I->rpart[2 * sl];
+    si += I->rpart[2 * sl + 1];
+  }
+  double pn = 0.0, pe = 0.0;
+  row_epilogue(a, I, it.row, in, sr, si, &pn, &pe);
+  if (a.mode == 1 && a.k == 1 && a.want_partials) {
+    I->partials[2 * it.first_slot] = pn;
+    I->partials[2 * it.first_slot + 1] = pe;
   }
 }
 
@@ -414,11 +400,22 @@ hipError_t launch_reduce(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   a.split = split_form(pl, c.prec) ? 1 : 0;
   const int64_t blocks = (a.nitems + (kRedThreads / 64) - 1) / (kRedThreads / 64);
   if (blocks == 0) return hipSuccess;
-  if (c.ev0 || c.ev1)
+  const int nfin = (int)pl->fin.size();
+  hipEvent_t end_reduce = nfin > 0 ? nullptr : c.ev1;
+  if (c.ev0 || end_reduce)
     hipExtLaunchKernelGGL(reduce_kernel, dim3((unsigned)blocks), dim3(kRedThreads), 0, s, c.ev0,
-                          c.ev1, 0, a);
+                          end_reduce, 0, a);
   else
     hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)blocks), dim3(kRedThreads), 0, s, a);
+  if (nfin > 0) {
+    const unsigned fb = (unsigned)((nfin + 63) / 64);
+    if (c.ev1)
+      hipExtLaunchKernelGGL(finish_kernel, dim3(fb), dim3(64), 0, s, nullptr, c.ev1, 0, a,
+                            (const FinItem *)pl->d_fin, nfin);
+    else
+      hipLaunchKernelGGL(finish_kernel, dim3(fb), dim3(64), 0, s, a, (const FinItem *)pl->d_fin,
+                         nfin);
+  }
   return hipGetLastError();
 }
 

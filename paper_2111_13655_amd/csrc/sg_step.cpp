@@ -42,20 +42,7 @@ constexpr int kMaxTaylorOrder = 40;
 constexpr int kMaxKrylov = 64;
 constexpr int kMaxColumns = 8;
 
-struct Buffers {
-  double2 *v = nullptr;        // vectors, n each
-  double *partials = nullptr;  // multi-dot partial sums
-  double *coef = nullptr;      // multi-axpy coefficients (re, im)
-  double *lz = nullptr;        // Lanczos scalars on the device
-  double *npart = nullptr;     // block sums of |w|^2
-  ~Buffers() {
-    hipFree(v);
-    hipFree(npart);
-    hipFree(lz);
-    hipFree(partials);
-    hipFree(coef);
-  }
-};
+using Buffers = PropBuffers;
 
 // explicit tableaux: strictly lower A (row-major, 4 x 4) and weights b
 struct Tableau {
@@ -256,12 +243,22 @@ sg_status sil_step(sg_problem *p, double2 *psi, double dt, int m, sg_precision p
 
 }  // namespace
 
-extern "C" {
+namespace sg {
 
-sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, int32_t method,
-                       int32_t order, double tol, sg_precision prec, int32_t check_every,
-                       sg_prop_stats *stats, double *norm_trace, double *energy_trace,
-                       void *stream) {
+PropBuffers::~PropBuffers() {
+  if (!owned) return;
+  hipFree(v);
+  hipFree(npart);
+  hipFree(lz);
+  hipFree(partials);
+  hipFree(coef);
+}
+
+// Checks the arguments of a propagation and sizes its work buffers: m (the
+// Krylov dimension used) and nvec (work vectors besides the check vector).
+sg_status propagate_check(sg_problem *p, void *psi_v, double dt, int32_t nsteps, int32_t method,
+                          int32_t order, sg_precision prec, int32_t check_every, int *m_out,
+                          int *nvec_out) {
   if (!p || !psi_v) return fail(SG_EINVAL, "NULL argument");
   if (!(dt > 0.0) || !std::isfinite(dt) || nsteps < 0 || check_every < 0)
     return fail(SG_EINVAL, "dt must be > 0, nsteps and check_every >= 0");
@@ -278,29 +275,52 @@ sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, in
     return fail(SG_EINVAL, "unknown propagator");
   }
   if (p->host_only) return fail(SG_EINVAL, "handle was built without device tables");
-  hipStream_t s = (hipStream_t)stream;
-  double2 *psi = (double2 *)psi_v;
   const int64_t n = p->h.ncs;
   const int m = method == SG_PROP_SIL ? (int)std::min<int64_t>(order, n) : 0;
   // work vectors: Taylor 2, Runge-Kutta 1 + stages, Lanczos m + 1,
   // Bulirsch-Stoer 4 + columns; one more for the checks
-  const int nvec = method == SG_PROP_TAYLOR ? 2
-                   : method == SG_PROP_RK   ? 1 + order
-                   : method == SG_PROP_BS   ? 4 + order
-                                            : m + 1;
-  Buffers B;
-  hipError_t e = hipMalloc((void **)&B.v, (size_t)(nvec + 1) * n * sizeof(double2));
-  if (e == hipSuccess && method == SG_PROP_SIL) {
-    const size_t mm = (size_t)m + 1;
-    e = hipMalloc((void **)&B.partials, 2 * mm * dot_partials_per_vector() * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void **)&B.coef, 2 * mm * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void **)&B.lz, (2 * mm + 1) * sizeof(double));
-    if (e == hipSuccess)
-      e = hipMalloc((void **)&B.npart, (size_t)lanczos_norm_partials() * sizeof(double));
+  *m_out = m;
+  *nvec_out = method == SG_PROP_TAYLOR ? 2
+              : method == SG_PROP_RK   ? 1 + order
+              : method == SG_PROP_BS   ? 4 + order
+                                       : m + 1;
+  return SG_OK;
+}
+
+// Byte offsets of the work buffers inside one region (each 256-byte
+// aligned): v, partials, coef, lz, npart; returns the region's size.
+int64_t propagate_layout(int64_t n, int32_t method, int32_t order, int m, int nvec,
+                         int64_t off[5]) {
+  auto up = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+  int64_t sz[5] = {(int64_t)(nvec + 1) * n * (int64_t)sizeof(double2), 0, 0, 0, 0};
+  if (method == SG_PROP_SIL) {
+    const int64_t mm = (int64_t)m + 1;
+    sz[1] = 2 * mm * dot_partials_per_vector() * (int64_t)sizeof(double);
+    sz[2] = 2 * mm * (int64_t)sizeof(double);
+    sz[3] = (2 * mm + 1) * (int64_t)sizeof(double);
+    sz[4] = (int64_t)lanczos_norm_partials() * (int64_t)sizeof(double);
+  } else if (method == SG_PROP_BS || method == SG_PROP_RK) {
+    sz[2] = 2 * (int64_t)order * (int64_t)sizeof(double);
   }
-  if (e == hipSuccess && (method == SG_PROP_BS || method == SG_PROP_RK))
-    e = hipMalloc((void **)&B.coef, 2 * (size_t)order * sizeof(double));
-  if (e != hipSuccess) return fail(SG_ENOMEM, "propagator work vectors");
+  int64_t at = 0;
+  for (int i = 0; i < 5; ++i) {
+    off[i] = at;
+    at += up(sz[i]);
+  }
+  return at;
+}
+
+// The propagation itself, on work buffers B (sized by propagate_layout).
+// zero_kernel: clear the work vectors with a fill kernel instead of
+// hipMemsetAsync.
+sg_status propagate_run(sg_problem *p, void *psi_v, double dt, int32_t nsteps, int32_t method,
+                        int32_t order, int m, int nvec, double tol, sg_precision prec,
+                        int32_t check_every, sg_prop_stats *stats, double *norm_trace,
+                        double *energy_trace, void *stream, PropBuffers &B, bool zero_kernel) {
+  hipStream_t s = (hipStream_t)stream;
+  double2 *psi = (double2 *)psi_v;
+  const int64_t n = p->h.ncs;
+  hipError_t e = hipSuccess;
   std::vector<double> wts(2 * (size_t)std::max(order, 1), 0.0);
   if (method == SG_PROP_BS) {
     // extrapolation to h = 0 of the midpoint results at h_i = dt / (2i):
@@ -325,8 +345,9 @@ sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, in
       return hip_fail(e, "upload Runge-Kutta weights");
   }
   // zero-filled: vector updates read their destination
-  if ((e = hipMemsetAsync(B.v, 0, (size_t)(nvec + 1) * n * sizeof(double2), s)) != hipSuccess)
-    return hip_fail(e, "clear work vectors");
+  e = zero_kernel ? launch_zero(B.v, (int64_t)(nvec + 1) * n, s)
+                  : hipMemsetAsync(B.v, 0, (size_t)(nvec + 1) * n * sizeof(double2), s);
+  if (e != hipSuccess) return hip_fail(e, "clear work vectors");
   double2 *check_buf = B.v + (size_t)nvec * n;
 
   sg_prop_stats st{};
@@ -389,6 +410,38 @@ sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, in
   if (stats) *stats = st;
   if (ret == SG_ETOL) return fail(SG_ETOL, "norm drift beyond tolerance");
   return SG_OK;
+}
+
+
+}  // namespace sg
+
+extern "C" {
+
+sg_status sg_propagate(sg_problem *p, void *psi_v, double dt, int32_t nsteps, int32_t method,
+                       int32_t order, double tol, sg_precision prec, int32_t check_every,
+                       sg_prop_stats *stats, double *norm_trace, double *energy_trace,
+                       void *stream) {
+  int m = 0, nvec = 0;
+  sg_status cs = propagate_check(p, psi_v, dt, nsteps, method, order, prec, check_every, &m, &nvec);
+  if (cs != SG_OK) return cs;
+  const int64_t n = p->h.ncs;
+  int64_t off[5];
+  propagate_layout(n, method, order, m, nvec, off);
+  PropBuffers B;
+  hipError_t e = hipMalloc((void **)&B.v, (size_t)(nvec + 1) * n * sizeof(double2));
+  if (e == hipSuccess && method == SG_PROP_SIL) {
+    const size_t mm = (size_t)m + 1;
+    e = hipMalloc((void **)&B.partials, 2 * mm * dot_partials_per_vector() * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&B.coef, 2 * mm * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&B.lz, (2 * mm + 1) * sizeof(double));
+    if (e == hipSuccess)
+      e = hipMalloc((void **)&B.npart, (size_t)lanczos_norm_partials() * sizeof(double));
+  }
+  if (e == hipSuccess && (method == SG_PROP_BS || method == SG_PROP_RK))
+    e = hipMalloc((void **)&B.coef, 2 * (size_t)order * sizeof(double));
+  if (e != hipSuccess) return fail(SG_ENOMEM, "propagator work vectors");
+  return propagate_run(p, psi_v, dt, nsteps, method, order, m, nvec, tol, prec, check_every,
+                       stats, norm_trace, energy_trace, stream, B, false);
 }
 
 }  // extern "C"

@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 import sg_inputs
-from oracle.action import Oracle, galerkin_masked_matrix, galerkin_rows
+from oracle.action import Oracle, galerkin_masked_apply, galerkin_masked_matrix, galerkin_rows
 from oracle.smolyak import CompactRanker
 from tests.gpu_util import empty, max_rel, rand_state, say, to_dev, to_host
 
@@ -110,6 +110,31 @@ def test_apply_config2_sampled_rows_and_hermiticity():
     lhs = np.vdot(phi, Hpsi)
     rhs = np.conj(np.vdot(psi, Hphi))
     assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_apply_config2_full_vector_vs_route2():
+    """(D, L) = (12, 6), full size, whole output vector: the GPU FP64 apply
+    against the oracle's matrix-free masked-Galerkin route (Route 2), element
+    by element and in the 2-norm, on a random state and on the displaced
+    Gaussian."""
+    sg = _sg()
+    inst = sg_inputs.config2()
+    say("apply config2 full vector vs route 2")
+    with sg.Problem.from_instance(inst) as P:
+        n = P.n_cs
+        comp = sg.sg_basis_indices(P.handle)
+        g = empty(n)
+        sg.sg_init_gaussian(P.handle, inst.shift, g)
+        states = [rand_state(n, 11), to_host(g)]
+        outs = []
+        for psi in states:
+            x, y = to_dev(psi), empty(n)
+            P.apply(x, y, sg.SG_FP64)
+            outs.append(to_host(y))
+    for psi, out in zip(states, outs):
+        ref = galerkin_masked_apply(inst, psi, comp)
+        assert max_rel(out, ref) < TOL_FP64
+        assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < TOL_FP64
 
 
 @pytest.mark.parametrize("D,L", [(2, 4), (4, 4), (3, 5), (1, 7)])

@@ -129,6 +129,20 @@ def test_batch_rejects_bad_arguments():
             with pytest.raises(sg.SgError) as e:
                 sg.sg_batch_propagate(b, [x], [-1.0], 1)
             assert e.value.status == sg.SG_EINVAL
+            # a state list of the wrong length, or a state of the wrong size,
+            # is refused before anything is launched
+            with pytest.raises(ValueError):
+                sg.sg_batch_propagate(b, [x, x], [0.1, 0.1], 1)
+            with pytest.raises(ValueError):
+                sg.sg_batch_propagate(b, [empty(P.n_cs - 1)], [0.1], 1)
+            assert sg.sg_batch_size(b) == (1, [P.n_cs])
+            # the C ABI itself refuses a count that differs from the batch's
+            import ctypes
+            ptrs = (ctypes.c_void_p * 2)(x.data_ptr(), x.data_ptr())
+            dts = (ctypes.c_double * 2)(0.1, 0.1)
+            st = sg.lib().sg_batch_propagate(b, ptrs, 2, dts, 1, None, None, 0.0, sg.SG_FP64,
+                                             0, 0, None, None)
+            assert st == sg.SG_EINVAL
         finally:
             sg.sg_batch_free(b)
 

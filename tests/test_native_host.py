@@ -167,3 +167,25 @@ def test_propagate_rejects_bad_arguments_host_only():
             assert st == sg.SG_EINVAL   # no device tables
     finally:
         P.close()
+
+
+def test_batch_binding_rejects_bad_state_lists_before_any_launch(monkeypatch):
+    """The binding checks the number of states against the batch's size (read
+    from the library) before it marshals anything: a short or long list never
+    reaches the kernels.  The batch itself needs a device, so its size query
+    is replaced here."""
+    sg = _sg()
+    monkeypatch.setattr(sg, "sg_batch_size", lambda b: (2, [41, 41]))
+    called = []
+    monkeypatch.setattr(sg, "lib", lambda: called.append(1))
+    with pytest.raises(ValueError):
+        sg.sg_batch_propagate(None, [], [], 1)
+    with pytest.raises(ValueError):
+        sg.sg_batch_propagate(None, [object()] * 3, [0.1] * 3, 1)
+    assert called == []
+
+
+def test_batch_abi_refuses_null_batch():
+    sg = _sg()
+    assert sg.lib().sg_batch_propagate(None, None, 0, None, 1, None, None, 0.0, 0, 0, 0,
+                                       None, None) == sg.SG_EINVAL
