@@ -1,15 +1,23 @@
 """Benchmark of the Smolyak H|psi> hot path on one MI355X.
 
-Default workload: the (D, L) = (6, 6) coupled-anharmonic Hamiltonian
-(omega ~ U(0.5, 2), c ~ U(-0.05, 0.05), k ~ U(-0.02, 0.02), seeded), a
-displaced-Gaussian wave packet propagated by Chebyshev steps of dt = 0.05 in
-FP64, with norm and energy checked every 100 steps.  One benchmark "step" is
-one Chebyshev time step: K-1 applications of H_S (term sweep + fixed-order
-reduce with the recurrence fused into it) over the whole term set.
+Default workload: the (D, L) = (12, 6) coupled-anharmonic Hamiltonian
+(omega ~ U(0.5, 2), c ~ U(-0.05, 0.05), k ~ U(-0.02, 0.02), seeded; 18 564
+terms, N_cs = 369 305), a displaced-Gaussian wave packet propagated by 500
+Chebyshev steps of dt = 0.05 in the precision the mixed-precision autotuner
+picks at the 1e-6 bar, with its error against the plain FP64 propagation
+after every step.  One benchmark "step" is one Chebyshev time step: K-1
+applications of H_S (term sweep + fixed-order reduce with the recurrence
+fused into it) over the whole term set.
 
-Prints ONE JSON line: applies/s (value), grid-points/s (literal and active
-counts), p50/p99 latency of a single apply, the dominant kernel's roofline
-(term sweep, FP64 VALU), and the CPU oracle's rate on a bounded sample.
+Prints ONE JSON line: applies/s (value) with the FP64 rate beside it,
+grid-points/s (literal and active counts), p50/p99 latency of a single
+apply, the dominant kernel's roofline (term sweep: FLOP and HBM fractions),
+and the CPU oracle's rate on a bounded sample of the same operator.  The
+extra sections cover the (6, 6) FP64 trajectory, the other propagators, 64
+batched instances and the serving stream, each mixed against FP64.
+
+`--apply-only N` runs N applies of the workload and exits (the command the
+rocprofv3 summaries under profiles/ are taken from).
 """
 from __future__ import annotations
 
@@ -26,19 +34,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+FP64_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2 x 2.4 GHz (vector = matrix)
 HBM_PEAK_GBS = 8000.0
+TOL_MIXED = 1e-6
 # Sources whose change invalidates recorded HBM counters of the sweep kernel.
 KERNEL_SOURCES = ["paper_2111_13655_amd/csrc/sg_sweep.hip", "paper_2111_13655_amd/csrc/sg_internal.h",
                   "paper_2111_13655_amd/csrc/sg_plan.cpp", "paper_2111_13655_amd/csrc/sg_terms.cpp"]
 
 WORKLOADS = {
-    "d6_l6_fp64": dict(D=6, L=6, dt=0.05, check_every=100, precision="fp64",
-                       desc="smolyak H|psi> D=6 L=6 coupled anharmonic, Chebyshev dt=0.05, FP64"),
-    "d2_l4_fp64": dict(D=2, L=4, dt=0.1, check_every=10, precision="fp64",
-                       desc="smolyak H|psi> D=2 L=4 coupled anharmonic, Chebyshev dt=0.1, FP64"),
-    "d12_l6_mixed": dict(D=12, L=6, dt=0.05, check_every=1, precision="mixed",
-                         desc="smolyak H|psi> D=12 L=6 coupled anharmonic, Chebyshev dt=0.05, mixed"),
+    "d12_l6": dict(D=12, L=6, dt=0.05, steps=500, check_every=100, cfg="config2",
+                   desc="smolyak H|psi> D=12 L=6 coupled anharmonic (18564 terms, N_cs=369305), "
+                        "Chebyshev dt=0.05, mixed precision tuned at 1e-6 vs FP64"),
+    "d6_l6": dict(D=6, L=6, dt=0.05, steps=1000, check_every=100, cfg="config1",
+                  desc="smolyak H|psi> D=6 L=6 coupled anharmonic, Chebyshev dt=0.05, FP64"),
+    "d2_l4": dict(D=2, L=4, dt=0.1, steps=100, check_every=10, cfg="config0",
+                  desc="smolyak H|psi> D=2 L=4 coupled anharmonic, Chebyshev dt=0.1, FP64"),
 }
 
 
@@ -48,8 +58,7 @@ def log(msg):
 
 def instance_for(name):
     import sg_inputs
-    return {"d6_l6_fp64": sg_inputs.config1, "d2_l4_fp64": sg_inputs.config0,
-            "d12_l6_mixed": sg_inputs.config2}[name]()
+    return getattr(sg_inputs, WORKLOADS[name]["cfg"])()
 
 
 def kernel_sources_sha256():
@@ -80,105 +89,269 @@ def recorded_traffic(workload: str, kernel: str):
     return None
 
 
-def cpu_baseline(inst, info, budget_s: float):
+def literal_grid_points(levels, nq_a=2, nq_b=2):
+    return int(np.prod([nq_a + nq_b * int(l) for l in levels]))
+
+
+def cpu_baseline(inst, budget_s: float):
     """The FP64 oracle's literal Alg. 1 (test infrastructure) on a bounded
-    sample: as many whole applies as fit in about budget_s seconds."""
+    sample: whole applies when they fit the budget, else a seeded random sample
+    of terms, extrapolated to the whole apply by the literal grid-point share
+    of the sampled terms."""
     from oracle.action import Oracle
     try:
         from threadpoolctl import threadpool_info
         blas_threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
         blas_threads = 1
+    cores = len(os.sched_getaffinity(0))
     O = Oracle(inst)
+    S = O.S
     rng = np.random.default_rng(0)
-    psi = rng.standard_normal(O.S.n_cs) + 1j * rng.standard_normal(O.S.n_cs)
-    n = 0
+    psi = rng.standard_normal(S.n_cs) + 1j * rng.standard_normal(S.n_cs)
+    pts = np.array([literal_grid_points(l, inst.nq_A, inst.nq_B) for l in S.terms], dtype=np.float64)
+    total_pts = float(pts.sum())
+    order = rng.permutation(S.n_terms)
+    done_pts, n_terms_done = 0.0, 0
     t0 = time.perf_counter()
-    while True:
-        psi = O.apply_literal(psi)
-        psi /= np.linalg.norm(psi)
-        n += 1
+    for t in order:
+        O.apply_literal(psi, terms=[int(t)])
+        done_pts += pts[t]
+        n_terms_done += 1
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    rate = n / dt
-    return {"value": rate, "unit": "applies/s", "cores": int(blas_threads),
-            "kind": "oracle",
-            "sample": f"{n} whole FP64 applies of the literal per-term oracle (Alg. 1) on the "
-                      f"same operator, {dt:.1f} s; host affinity {len(os.sched_getaffinity(0))} cpus",
-            "grid_pts_per_s_literal": rate * info["grid_literal"]}
+    apply_s = dt * total_pts / done_pts
+    if n_terms_done == S.n_terms:
+        sample = f"one whole FP64 apply of the literal per-term oracle (Alg. 1), {dt:.1f} s"
+    else:
+        sample = (f"{n_terms_done} of {S.n_terms} terms (seeded random order) of one FP64 apply of "
+                  f"the literal per-term oracle (Alg. 1) in {dt:.1f} s, "
+                  f"{100 * done_pts / total_pts:.2f}% of its literal grid points; "
+                  f"extrapolated to {apply_s:.0f} s per apply by that share")
+    return {"value": 1.0 / apply_s, "unit": "applies/s", "cores": cores, "kind": "oracle",
+            "sample": sample, "blas_threads": int(blas_threads),
+            "grid_pts_per_s_literal": total_pts / apply_s,
+            "note": "single-threaded NumPy per term; host affinity as 'cores'"}
 
 
-def _throughput(sg, P, prec, reps):
-    """Back-to-back applies between two events on the current stream: applies/s."""
+def _rel(a, b):
     import torch
-    n = P.n_cs
-    x = torch.zeros(n, dtype=torch.complex128, device="cuda")
-    x[0] = 1.0
+    return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+
+def tuned_threshold(sg, P, psi):
+    """The mixed-precision autotuner at the 1e-6 bar on the workload's own
+    initial state: the fastest FP32 share whose error against the FP64 apply
+    stays below half the bar."""
+    thr, err = sg.sg_tune_mixed(P.handle, psi, TOL_MIXED, 3)
+    return int(thr), float(err)
+
+
+def step_errors(sg, P, psi0, dt, steps, lo, hi, threshold):
+    """Mixed (at `threshold`) and FP64 propagations side by side from psi0:
+    relative distance of the mixed state from the FP64 one after every step."""
+    import torch
+    sg.sg_set_mixed_threshold(P.handle, threshold)
+    a64, a32 = psi0.clone(), psi0.clone()
+    errs = []
+    for _ in range(steps):
+        sg.sg_propagate_chebyshev(P.handle, a64, dt, 1, lo, hi, tol=0.0)
+        sg.sg_propagate_chebyshev(P.handle, a32, dt, 1, lo, hi, tol=0.0, precision=sg.SG_MIXED)
+        errs.append(_rel(a32, a64))
+    return errs
+
+
+def timed_propagation(sg, P, psi0, dt, steps, warmup, lo, hi, prec, check_every):
+    import torch
+    psi = psi0.clone()
+    if warmup > 0:
+        sg.sg_propagate_chebyshev(P.handle, psi, dt, warmup, lo, hi, tol=1e-6, precision=prec,
+                                  check_every=check_every)
+    psi = psi0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, stats, _, _ = sg.sg_propagate_chebyshev(P.handle, psi, dt, steps, lo, hi, tol=1e-6,
+                                                    precision=prec, check_every=check_every)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, status, stats, psi
+
+
+def kernel_times(sg, P, psi0, dt, steps, lo, hi, prec, check_every):
+    """Average sweep and reduce durations from HIP events attached to every
+    dispatch of `steps` Chebyshev steps, on the stream they are launched on."""
+    psi = psi0.clone()
+    sg.sg_set_timing(P.handle, True)
+    sg.sg_propagate_chebyshev(P.handle, psi, dt, steps, lo, hi, tol=1e-6, precision=prec,
+                              check_every=check_every)
+    tim = sg.sg_get_timing(P.handle)
+    sg.sg_set_timing(P.handle, False)
+    return (tim["sweep_ms"] / max(tim["sweep_launches"], 1) * 1e-3,
+            tim["reduce_ms"] / max(tim["reduce_launches"], 1) * 1e-3, tim)
+
+
+def apply_latency(sg, P, x, prec, samples):
+    import torch
     y = torch.empty_like(x)
-    for _ in range(3):
+    for _ in range(min(50, samples)):
         P.apply(x, y, prec)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(samples):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
         P.apply(x, y, prec)
-    e1.record()
-    e1.synchronize()
-    return reps / (e0.elapsed_time(e1) * 1e-3)
+        e1.record()
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1) * 1e3)
+    lat = np.array(lat)
+    return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
 
 
-def mixed_vs_fp64(sg, reps=20, prop_steps=20):
-    """(D, L) = (12, 6): the precision autotuner's choice at the 1e-6 bar, its
-    measured error against the FP64 apply, both throughputs, and the error of
-    a mixed-precision propagation against the FP64 one after every step."""
+def roofline(info, sweep_s, prec_name, workload):
+    flops = info["sweep_flops_fp64"]
+    nbytes = info["sweep_bytes"]
+    tflops = flops / sweep_s / 1e12
+    gbs = nbytes / sweep_s / 1e9
+    intensity = flops / nbytes
+    ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    # the FP64 contractions run on the vector ALUs (FP64 vector and matrix
+    # peaks are equal on this part)
+    bound = "alu" if intensity >= ridge else "hbm"
+    if bound == "hbm":
+        achieved, peak, unit = gbs, HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved, peak, unit = tflops, FP64_PEAK_TFLOPS, "TFLOP/s"
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak,
+            "traffic": recorded_traffic(f"{workload}/{prec_name}", "sweep_kernel<double>"),
+            "kernel": "sweep_kernel<double>",
+            "flops_per_launch": flops, "bytes_per_launch": nbytes,
+            "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
+            "flop_frac": tflops / FP64_PEAK_TFLOPS, "hbm_frac": gbs / HBM_PEAK_GBS,
+            "achieved_tflops": tflops, "achieved_gbs": gbs}
+
+
+def headline(sg, args, wl, inst):
+    import torch
+    log(f"[bench] build {args.workload} D={inst.D} L={inst.L}")
+    P = sg.Problem.from_instance(inst)
+    info = sg.sg_problem_info(P.handle)
+    n = P.n_cs
+    psi0 = torch.empty(n, dtype=torch.complex128, device="cuda")
+    sg.sg_init_gaussian(P.handle, inst.shift, psi0)
+    lo, hi = sg.sg_spectral_bounds(P.handle, 40)
+    log(f"[bench] N_cs={n} N_st={info['n_terms']} N_s={info['n_s']} bounds=({lo:.3f},{hi:.3f})")
+    dt, steps, ce = wl["dt"], args.steps, wl["check_every"]
+
+    if args.precision == "fp64":
+        prec, thr, thr_err = sg.SG_FP64, 0, 0.0
+    else:
+        thr, thr_err = tuned_threshold(sg, P, psi0)
+        prec = sg.SG_MIXED
+        log(f"[bench] mixed threshold {thr} (error {thr_err:.2e} on the initial state)")
+    prec_name = "fp64" if prec == sg.SG_FP64 else "mixed"
+
+    el, status, stats, _ = timed_propagation(sg, P, psi0, dt, steps, args.warmup, lo, hi, prec, ce)
+    applies = stats["applies"]
+    log(f"[bench] timed {steps} steps ({prec_name}): {el:.3f} s, {applies} applies, status {status}")
+    out_fp64 = None
+    if prec != sg.SG_FP64:
+        el64, st64, stats64, _ = timed_propagation(sg, P, psi0, dt, steps, 0, lo, hi,
+                                                   sg.SG_FP64, ce)
+        out_fp64 = {"applies_per_s": stats64["applies"] / el64, "seconds": el64,
+                    "status": int(st64)}
+        log(f"[bench] fp64 leg: {el64:.3f} s")
+    sweep_s, reduce_s, tim = kernel_times(sg, P, psi0, dt, steps, lo, hi, prec, ce)
+    log(f"[bench] sweep avg {sweep_s * 1e6:.2f} us, reduce avg {reduce_s * 1e6:.2f} us")
+    p50, p99 = apply_latency(sg, P, psi0, prec, args.latency_samples)
+    # sweep durations of the FP64 kernel for the roofline (the tuned path may
+    # mix FP32 launches in)
+    if prec != sg.SG_FP64:
+        sweep64_s, reduce64_s, _ = kernel_times(sg, P, psi0, dt, min(steps, 100), lo, hi,
+                                                sg.SG_FP64, ce)
+    else:
+        sweep64_s, reduce64_s = sweep_s, reduce_s
+    value = applies / el
+    res = {
+        "metric": "H|psi> applies/s and grid-pts/s vs plain FP64 at 1e-6 rel err; p50/p99 latency",
+        "value": value,
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / max(steps, 1) * 1e3,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64" if (prec == sg.SG_FP64 or thr == 0) else "f32+f64",
+        "data": "synthetic (seeded coupled-anharmonic Hamiltonian, displaced Gaussian)",
+        "config": {"workload": wl["desc"], "D": inst.D, "L": inst.L, "dt": dt,
+                   "precision": prec_name, "mixed_threshold": thr, "n_terms": info["n_terms"],
+                   "n_cs": n, "n_s": info["n_s"], "chebyshev_terms": stats["cheb_terms"],
+                   "check_every": ce, "parallelism": "single GPU",
+                   "operator_form": ("split" if (prec == sg.SG_MIXED or info["fp64_split"])
+                                     else "grid_kinetic")},
+        "grid_pts_per_s_literal": value * info["grid_literal"],
+        "grid_pts_per_s_active": value * info["grid_active"],
+        "latency_us_p50": p50,
+        "latency_us_p99": p99,
+        "norm_drift": stats["max_norm_drift"],
+        "energy_drift": stats["max_energy_drift"],
+        "status": int(status),
+        "kernel_avg_us": {"term_sweep": sweep_s * 1e6, "reduce": reduce_s * 1e6,
+                          "term_sweep_fp64": sweep64_s * 1e6, "reduce_fp64": reduce64_s * 1e6},
+        "roofline": roofline(info, sweep64_s, "fp64", args.workload),
+    }
+    if prec != sg.SG_FP64:
+        res["mixed_vs_fp64"] = {
+            "threshold": thr, "apply_rel_err_initial_state": thr_err, "tol": TOL_MIXED,
+            "fp64": out_fp64, "mixed_applies_per_s": value,
+            "speedup": value / out_fp64["applies_per_s"]}
+        if not args.no_error_curve:
+            log("[bench] per-step error vs FP64 (tuned threshold)")
+            errs = step_errors(sg, P, psi0, dt, steps, lo, hi, thr)
+            res["mixed_vs_fp64"]["propagation_rel_err_per_step"] = errs
+            res["mixed_vs_fp64"]["propagation_max_rel_err"] = max(errs) if errs else 0.0
+            if thr < 1 and args.forced_curve_steps > 0:
+                # what FP32 terms would cost: every |D_l| = 1 term in FP32
+                log("[bench] per-step error vs FP64 with every |D_l| = 1 term in FP32")
+                e1 = step_errors(sg, P, psi0, dt, args.forced_curve_steps, lo, hi, 1)
+                x1 = psi0.clone()
+                y1 = torch.empty_like(x1)
+                y64 = torch.empty_like(x1)
+                P.apply(x1, y1, sg.SG_MIXED)
+                P.apply(x1, y64, sg.SG_FP64)
+                sg.sg_set_mixed_threshold(P.handle, thr)
+                res["mixed_vs_fp64"]["threshold_1"] = {
+                    "apply_rel_err_initial_state": _rel(y1, y64),
+                    "propagation_rel_err_per_step": e1}
+    P.close()
+    return res
+
+
+def d6l6_leg(sg, steps=1000):
+    """(D, L) = (6, 6), FP64, 1000 Chebyshev steps of dt = 0.05 with norm and
+    energy checked every 100 steps."""
     import torch
     import sg_inputs
-    inst = sg_inputs.config2()
-    P = sg.Problem.from_instance(inst)
-    n = P.n_cs
-    psi = torch.empty(n, dtype=torch.complex128, device="cuda")
-    sg.sg_init_gaussian(P.handle, inst.shift, psi)
-    thr, err_tuned = sg.sg_tune_mixed(P.handle, psi, 1e-6, 3)
-    # error on an independent random state
-    rng = np.random.default_rng(7)
-    v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
-    x = torch.from_numpy(v / np.linalg.norm(v)).to("cuda")
-    y64, y32 = torch.empty_like(x), torch.empty_like(x)
-    P.apply(x, y64, sg.SG_FP64)
-    P.apply(x, y32, sg.SG_MIXED)
-    torch.cuda.synchronize()
-    err = float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64))
-    t64 = _throughput(sg, P, sg.SG_FP64, reps)
-    t32 = _throughput(sg, P, sg.SG_MIXED, reps)
-    # propagation from the displaced Gaussian in both precisions, step by
-    # step: relative distance of the mixed state from the FP64 one
-    lo, hi = sg.sg_spectral_bounds(P.handle, 40)
-
-    def prop_errors():
-        a64, a32 = psi.clone(), psi.clone()
-        errs = []
-        for _ in range(prop_steps):
-            sg.sg_propagate_chebyshev(P.handle, a64, 0.05, 1, lo, hi, tol=0.0)
-            sg.sg_propagate_chebyshev(P.handle, a32, 0.05, 1, lo, hi, tol=0.0,
-                                      precision=sg.SG_MIXED)
-            errs.append(float(torch.linalg.norm(a32 - a64) / torch.linalg.norm(a64)))
-        return errs
-
-    step_err = prop_errors()
-    # the same with every |D_l| = 1 term in FP32 (the tuner's bar aside)
-    sg.sg_set_mixed_threshold(P.handle, 1)
-    step_err_1 = prop_errors()
-    sg.sg_set_mixed_threshold(P.handle, thr)
-    info = sg.sg_problem_info(P.handle)
-    P.close()
-    return {"workload": "D=12 L=6 coupled anharmonic (same family), one apply",
-            "fp64_applies_per_s": t64, "mixed_applies_per_s": t32, "speedup": t32 / t64,
-            "mixed_threshold": thr, "rel_err_vs_fp64_tuning_state": err_tuned,
-            "rel_err_vs_fp64_random_state": err, "tol": 1e-6,
-            "propagation_dt": 0.05, "propagation_rel_err_per_step": step_err,
-            "propagation_max_rel_err": max(step_err) if step_err else 0.0,
-            "propagation_rel_err_per_step_threshold_1": step_err_1,
-            "grid_pts_per_s_active_mixed": t32 * info["grid_active"]}
+    inst = sg_inputs.config1()
+    with sg.Problem.from_instance(inst) as P:
+        psi0 = torch.empty(P.n_cs, dtype=torch.complex128, device="cuda")
+        sg.sg_init_gaussian(P.handle, inst.shift, psi0)
+        lo, hi = sg.sg_spectral_bounds(P.handle, 40)
+        el, status, stats, _ = timed_propagation(sg, P, psi0, 0.05, steps, 20, lo, hi,
+                                                 sg.SG_FP64, 100)
+        sweep_s, reduce_s, _ = kernel_times(sg, P, psi0, 0.05, 100, lo, hi, sg.SG_FP64, 100)
+        p50, p99 = apply_latency(sg, P, psi0, sg.SG_FP64, 1000)
+        info = sg.sg_problem_info(P.handle)
+    return {"workload": "D=6 L=6, FP64, 1000 steps of dt=0.05, checks every 100",
+            "applies_per_s": stats["applies"] / el, "status": int(status),
+            "norm_drift": stats["max_norm_drift"], "energy_drift": stats["max_energy_drift"],
+            "kernel_avg_us": {"term_sweep": sweep_s * 1e6, "reduce": reduce_s * 1e6},
+            "latency_us_p50": p50, "latency_us_p99": p99,
+            "sweep_flop_frac": info["sweep_flops_fp64"] / sweep_s / 1e12 / FP64_PEAK_TFLOPS}
 
 
 def propagators(sg, steps=40, dt=0.05):
@@ -186,7 +359,6 @@ def propagators(sg, steps=40, dt=0.05):
     and Bulirsch-Stoer propagators against Chebyshev over the same span, from the
     displaced Gaussian: wall time, applies, and the distance of each final
     state from the Chebyshev one (converged to 1e-16 per step)."""
-    import time
     import torch
     import sg_inputs
     inst = sg_inputs.config1()
@@ -215,78 +387,98 @@ def propagators(sg, steps=40, dt=0.05):
                                 ("sil_12", sg.SG_PROP_SIL, 12), ("bs_4", sg.SG_PROP_BS, 4)]:
         x, t, st = run(lambda x: sg.sg_propagate(P.handle, x, dt, steps, method, order)[1])
         out[name] = {"seconds": t, "applies": st["applies"], "applies_per_s": st["applies"] / t,
-                     "rel_diff_vs_chebyshev": float(torch.linalg.norm(x - ref) /
-                                                    torch.linalg.norm(ref))}
+                     "rel_diff_vs_chebyshev": _rel(x, ref)}
     P.close()
     return out
 
 
-def batched(sg, steps):
-    """64 independent instances (D ~ U{4..10}, L ~ U{4..7}) advanced together
-    in mixed precision: instance-applies/s over a bounded number of steps."""
+def batched(sg, steps, latency_steps):
+    """64 independent instances (D ~ U{4..10}, L ~ U{4..7}), all advanced in
+    one launch sequence, mixed (the precision policy below) and FP64 legs over
+    the same `steps` steps: instance-applies/s, p50/p99 of one batched step,
+    and each instance's distance from its FP64 result."""
     import torch
     import sg_inputs
     insts = sg_inputs.config3()
     probs = [sg.Problem.from_instance(i) for i in insts]
-    psis, lo, hi = [], [], []
+    psi0, lo, hi = [], [], []
+    thr = []
     for P, inst in zip(probs, insts):
         x = torch.empty(P.n_cs, dtype=torch.complex128, device="cuda")
         sg.sg_init_gaussian(P.handle, inst.shift, x)
-        psis.append(x)
+        psi0.append(x)
         a, b = sg.sg_spectral_bounds(P.handle, 40)
         lo.append(a)
         hi.append(b)
+        # per instance: the fastest FP32 share within half the bar on its
+        # own initial state
+        t, _ = sg.sg_tune_mixed(P.handle, x, TOL_MIXED, 2)
+        thr.append(int(t))
     b = sg.sg_batch_create([P.handle for P in probs])
     dts = [i.meta["dt"] for i in insts]
-    sg.sg_batch_propagate(b, psis, dts, 1, lo, hi, tol=1e-6, precision=sg.SG_MIXED)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    status, st = sg.sg_batch_propagate(b, psis, dts, steps, lo, hi, tol=1e-6,
-                                       precision=sg.SG_MIXED, check_every=steps,
-                                       use_graph=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    applies = sum(s["applies"] for s in st)
-    grid = sum(P.info["grid_active"] * s["applies"] for P, s in zip(probs, st))
+    legs = {}
+    finals = {}
+    for name, prec in (("mixed", sg.SG_MIXED), ("fp64", sg.SG_FP64)):
+        psis = [x.clone() for x in psi0]
+        sg.sg_batch_propagate(b, [x.clone() for x in psi0], dts, 1, lo, hi, tol=1e-6,
+                              precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status, st = sg.sg_batch_propagate(b, psis, dts, steps, lo, hi, tol=1e-6,
+                                           precision=prec, check_every=steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        applies = sum(s["applies"] for s in st)
+        grid = sum(P.info["grid_active"] * s["applies"] for P, s in zip(probs, st))
+        # per-step latency: single-step calls
+        work = [x.clone() for x in psi0]
+        lat = []
+        for _ in range(latency_steps):
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            sg.sg_batch_propagate(b, work, dts, 1, lo, hi, tol=1e-6, precision=prec)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - s0)
+        legs[name] = {"status": int(status), "seconds": el,
+                      "instance_applies_per_s": applies / el,
+                      "grid_pts_per_s_active": grid / el,
+                      "ms_per_batched_step": el / steps * 1e3,
+                      "step_latency_ms_p50": float(np.percentile(lat, 50)) * 1e3,
+                      "step_latency_ms_p99": float(np.percentile(lat, 99)) * 1e3}
+        finals[name] = psis
+    errs = [_rel(a, b_) for a, b_ in zip(finals["mixed"], finals["fp64"])]
     sg.sg_batch_free(b)
     for P in probs:
         P.close()
-    return {"workload": "64 instances, D ~ U{4..10}, L ~ U{4..7}, mixed, dt = 0.05",
-            "steps": steps, "status": int(status), "seconds": dt,
-            "instance_applies_per_s": applies / dt, "grid_pts_per_s_active": grid / dt,
-            "ms_per_batched_step": dt / steps * 1e3}
+    return {"workload": "64 instances, D ~ U{4..10}, L ~ U{4..7}, dt = 0.05",
+            "steps": steps, "mixed": legs["mixed"], "fp64": legs["fp64"],
+            "speedup_mixed_vs_fp64": legs["fp64"]["seconds"] / legs["mixed"]["seconds"],
+            "mixed_thresholds": thr,
+            "instances_with_fp32_terms": int(sum(t > 0 for t in thr)),
+            "final_state_rel_err_vs_fp64_max": max(errs),
+            "final_state_rel_err_vs_fp64_p50": float(np.percentile(errs, 50)),
+            "final_state_rel_err_vs_fp64": errs}
 
 
-def serve(sg, window_s, steps_scale):
-    """The Poisson request stream (20 req/s; D ~ U{3..20}, L ~ U{3..6} capped
-    so that N_s <= 5e7; steps ~ U{50..2000}) over its first window_s seconds,
-    every request's step count multiplied by steps_scale so that the sample
-    drains in bounded time.  Requests are submitted at their arrival times
-    and stay resident until done; latency is submit -> result."""
-    import sg_inputs
-    reqs = [r for r in sg_inputs.config4() if r.arrival_s < window_s]
-    # FP32 only for the |D_l| = 1 terms: the server applies one precision
-    # policy to every request, and larger thresholds exceed the 1e-6 drift
-    # gate at the largest D of the stream
-    srv = sg.sg_serve_create(max_slots=64, precision=sg.SG_MIXED, check_every=100, tol=1e-6,
-                             mixed_threshold=1, compile_threads=8)
+def serve_leg(sg, reqs, precision, mixed_threshold):
+    """Submits the requests at their arrival times (relative to the start of
+    the leg) and waits for all of them; returns latencies, final states and
+    throughput."""
+    srv = sg.sg_serve_create(max_slots=64, precision=precision, check_every=100, tol=1e-6,
+                             mixed_threshold=mixed_threshold, compile_threads=8)
     tickets = []
     t0 = time.perf_counter()
     for r in reqs:
-        inst = r.inst
-        L = inst.L
-        while L > 0 and sg.sg_count_sizes(inst.D, L)[1] > 5e7:
-            L -= 1
         now = time.perf_counter() - t0
-        if r.arrival_s > now:
-            time.sleep(r.arrival_s - now)
-        nsteps = max(1, int(round(r.steps * steps_scale)))
-        tickets.append((sg.sg_serve_submit(srv, inst.D, L, inst.omega, inst.c, inst.k,
-                                           inst.shift, 0.05, nsteps), nsteps))
-    lat, applies, ok, statuses = [], 0, 0, {}
-    for t, _ in tickets:
+        if r["arrival_s"] > now:
+            time.sleep(r["arrival_s"] - now)
+        inst = r["inst"]
+        tickets.append((sg.sg_serve_submit(srv, inst.D, r["L"], inst.omega, inst.c, inst.k,
+                                           inst.shift, 0.05, r["steps"]), r["n_cs"]))
+    lat, applies, ok, statuses, states = [], 0, 0, {}, []
+    for t, ncs in tickets:
         while True:
-            res = sg.sg_serve_poll(srv, t)
+            res = sg.sg_serve_poll(srv, t, ncs)
             if res is not None:
                 break
             time.sleep(0.001)
@@ -294,35 +486,86 @@ def serve(sg, window_s, steps_scale):
         applies += res["stats"]["applies"]
         ok += res["status"] == sg.SG_OK
         statuses[str(res["status"])] = statuses.get(str(res["status"]), 0) + 1
+        states.append(res["psi"])
     wall = time.perf_counter() - t0
     sg.sg_serve_destroy(srv)
     lat = np.array(lat)
-    return {"workload": "Poisson 20 req/s, D ~ U{3..20}, L ~ U{3..6} (N_s <= 5e7), mixed",
-            "window_s": window_s, "steps_scale": steps_scale, "requests": len(reqs),
-            "completed_ok": int(ok), "statuses": statuses, "wall_s": wall, "requests_per_s": len(reqs) / wall,
+    return {"requests": len(reqs), "completed_ok": int(ok), "statuses": statuses,
+            "wall_s": wall, "requests_per_s": len(reqs) / wall,
             "instance_applies_per_s": applies / wall,
             "latency_s_p50": float(np.percentile(lat, 50)),
-            "latency_s_p99": float(np.percentile(lat, 99))}
+            "latency_s_p99": float(np.percentile(lat, 99))}, states
+
+
+def serve(sg, window_s, steps_scale, mixed_threshold):
+    """The Poisson request stream (20 req/s; D ~ U{3..20}, L ~ U{3..6} capped
+    so that N_s <= 5e7; steps ~ U{50..2000}) over its first window_s seconds,
+    every request's step count multiplied by steps_scale, in a mixed leg and
+    an FP64 leg; each request's mixed result against its FP64 one."""
+    import sg_inputs
+    reqs = []
+    for r in sg_inputs.config4():
+        if r.arrival_s >= window_s:
+            break
+        L = r.inst.L
+        while L > 0 and sg.sg_count_sizes(r.inst.D, L)[1] > 5e7:
+            L -= 1
+        reqs.append({"arrival_s": r.arrival_s, "inst": r.inst, "L": L,
+                     "n_cs": sg.sg_count_sizes(r.inst.D, L)[2],
+                     "steps": max(1, int(round(r.steps * steps_scale)))})
+    mixed, s_mixed = serve_leg(sg, reqs, sg.SG_MIXED, mixed_threshold)
+    fp64, s_fp64 = serve_leg(sg, reqs, sg.SG_FP64, -1)
+    errs = [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(s_mixed, s_fp64)]
+    return {"workload": "Poisson 20 req/s, D ~ U{3..20}, L ~ U{3..6} (N_s <= 5e7)",
+            "window_s": window_s, "steps_scale": steps_scale,
+            "mixed_threshold": mixed_threshold,
+            "mixed": mixed, "fp64": fp64,
+            "request_rel_err_vs_fp64_max": max(errs) if errs else 0.0,
+            "request_rel_err_vs_fp64_p50": float(np.percentile(errs, 50)) if errs else 0.0}
+
+
+def apply_only(sg, args, inst):
+    """N applies of the workload's operator (for the profiler), then exit."""
+    import torch
+    P = sg.Problem.from_instance(inst)
+    psi = torch.empty(P.n_cs, dtype=torch.complex128, device="cuda")
+    sg.sg_init_gaussian(P.handle, inst.shift, psi)
+    y = torch.empty_like(psi)
+    prec = sg.SG_FP64 if (args.precision or "fp64") == "fp64" else sg.SG_MIXED
+    for _ in range(args.apply_only):
+        P.apply(psi, y, prec)
+    torch.cuda.synchronize()
+    P.close()
+    print(json.dumps({"apply_only": args.apply_only, "workload": args.workload,
+                      "precision": "fp64" if prec == sg.SG_FP64 else "mixed"}), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="Chebyshev steps timed (default: the workload's, 500 at D=12 L=6)")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="d6_l6_fp64", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
+    ap.add_argument("--workload", default="d12_l6", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="default: mixed (tuned) for d12_l6, fp64 otherwise")
     ap.add_argument("--latency-samples", type=int, default=1000)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the mixed-vs-FP64, batched and serving sections")
-    ap.add_argument("--batch-steps", type=int, default=10)
-    ap.add_argument("--serve-window", type=float, default=3.0)
-    ap.add_argument("--serve-steps-scale", type=float, default=0.05)
+                    help="skip the (6,6), propagator, batched and serving sections")
+    ap.add_argument("--no-error-curve", action="store_true")
+    ap.add_argument("--forced-curve-steps", type=int, default=100)
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--batch-latency-steps", type=int, default=20)
+    ap.add_argument("--serve-window", type=float, default=2.0)
+    ap.add_argument("--serve-steps-scale", type=float, default=0.1)
+    ap.add_argument("--serve-mixed-threshold", type=int, default=0)
     ap.add_argument("--grid-kinetic", action="store_true",
                     help="SG_FP64 in the literal form (kinetic matrices on every term grid) "
                          "instead of the default exact diagonal split")
+    ap.add_argument("--apply-only", type=int, default=0, metavar="N",
+                    help="only build the workload and run N applies (for the profiler)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the "
                          "reference kernel for scaling HBM byte counters) and exit")
@@ -348,126 +591,35 @@ def main():
     import paper_2111_13655_amd as sg
 
     wl = WORKLOADS[args.workload]
-    prec_name = args.precision or wl["precision"]
-    prec = sg.SG_FP64 if prec_name == "fp64" else sg.SG_MIXED
+    if args.steps is None:
+        args.steps = wl["steps"]
+    if args.precision is None:
+        args.precision = "mixed" if args.workload == "d12_l6" else "fp64"
     inst = instance_for(args.workload)
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    log(f"[bench] build {args.workload} D={inst.D} L={inst.L}")
-    P = sg.Problem.from_instance(inst)
-    if args.grid_kinetic:
-        sg.sg_set_operator_form(P.handle, True)
-    info = sg.sg_problem_info(P.handle)
-    n = P.n_cs
-    psi0 = torch.empty(n, dtype=torch.complex128, device=dev)
-    sg.sg_init_gaussian(P.handle, inst.shift, psi0)
-    emin, emax = sg.sg_spectral_bounds(P.handle, 40)
-    log(f"[bench] N_cs={n} N_st={info['n_terms']} N_s={info['n_s']} bounds=({emin:.3f},{emax:.3f})")
-
-    # warmup
-    psi = psi0.clone()
-    if args.warmup > 0:
-        sg.sg_propagate_chebyshev(P.handle, psi, wl["dt"], args.warmup, emin, emax, tol=1e-6,
-                                  precision=prec, check_every=wl["check_every"])
-    torch.cuda.synchronize()
-
-    # timed region: K Chebyshev steps
-    psi = psi0.clone()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    status, stats, ntr, etr = sg.sg_propagate_chebyshev(
-        P.handle, psi, wl["dt"], args.steps, emin, emax, tol=1e-6, precision=prec,
-        check_every=wl["check_every"])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    applies = stats["applies"]
-    log(f"[bench] timed {args.steps} steps: {elapsed:.3f} s, {applies} applies, status {status}")
-
-    # kernel durations over the same K steps (events around every launch)
-    psi_t = psi0.clone()
-    sg.sg_set_timing(P.handle, True)
-    sg.sg_propagate_chebyshev(P.handle, psi_t, wl["dt"], args.steps, emin, emax, tol=1e-6,
-                              precision=prec, check_every=wl["check_every"])
-    tim = sg.sg_get_timing(P.handle)
-    sg.sg_set_timing(P.handle, False)
-    sweep_avg_s = tim["sweep_ms"] / max(tim["sweep_launches"], 1) * 1e-3
-    reduce_avg_s = tim["reduce_ms"] / max(tim["reduce_launches"], 1) * 1e-3
-    info = sg.sg_problem_info(P.handle)
-    sweep_flops = info["sweep_flops_fp64"] if prec == sg.SG_FP64 else info["sweep_flops_mixed"]
-    achieved_tflops = sweep_flops / sweep_avg_s / 1e12
-    peak = FP64_VALU_PEAK_TFLOPS
-    log(f"[bench] sweep avg {sweep_avg_s * 1e6:.2f} us, reduce avg {reduce_avg_s * 1e6:.2f} us")
-
-    # per-apply latency
-    x = psi0.clone()
-    y = torch.empty_like(x)
-    lat = []
-    for _ in range(min(50, args.latency_samples)):
-        P.apply(x, y, prec)
-    torch.cuda.synchronize()
-    for _ in range(args.latency_samples):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        P.apply(x, y, prec)
-        e1.record()
-        e1.synchronize()
-        lat.append(e0.elapsed_time(e1) * 1e3)
-    lat = np.array(lat)
-
-    value = applies / elapsed
-    out = {
-        "metric": "H|psi> applies/s and grid-pts/s vs plain FP64 at 1e-6 rel err; p50/p99 latency",
-        "value": value,
-        "unit": "applies/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / max(args.steps, 1) * 1e3,
-        "higher_is_better": True,
-        "scaling": "strong",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == sg.SG_FP64 else "f32+f64",
-        "data": "synthetic (seeded coupled-anharmonic Hamiltonian, displaced Gaussian)",
-        "config": {"workload": wl["desc"], "D": inst.D, "L": inst.L, "dt": wl["dt"],
-                   "precision": prec_name, "n_terms": info["n_terms"], "n_cs": n,
-                   "n_s": info["n_s"], "chebyshev_terms": stats["cheb_terms"],
-                   "check_every": wl["check_every"], "parallelism": "single GPU",
-                   "operator_form": ("split" if (prec == sg.SG_MIXED or info["fp64_split"])
-                                     else "grid_kinetic")},
-        "grid_pts_per_s_literal": value * info["grid_literal"],
-        "grid_pts_per_s_active": value * info["grid_active"],
-        "latency_us_p50": float(np.percentile(lat, 50)),
-        "latency_us_p99": float(np.percentile(lat, 99)),
-        "norm_drift": stats["max_norm_drift"],
-        "energy_drift": stats["max_energy_drift"],
-        "status": int(status),
-        "kernel_avg_us": {"term_sweep": sweep_avg_s * 1e6, "reduce": reduce_avg_s * 1e6},
-        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / peak,
-                     "traffic": recorded_traffic(f"{args.workload}/{prec_name}",
-                                                 "sweep_kernel<double>"),
-                     "kernel": "sweep_kernel",
-                     "flops_per_launch": sweep_flops},
-    }
-    P.close()
+    torch.cuda.set_device(torch.device("cuda", 0))
+    if args.apply_only > 0:
+        apply_only(sg, args, inst)
+        return
+    out = headline(sg, args, wl, inst)
     if not args.no_extras:
-        log("[bench] mixed vs fp64 (D=12, L=6)")
-        out["mixed_vs_fp64"] = mixed_vs_fp64(sg)
-        log(f"[bench] {out['mixed_vs_fp64']}")
+        if args.workload != "d6_l6":
+            log("[bench] D=6 L=6 FP64 trajectory")
+            out["d6_l6_fp64"] = d6l6_leg(sg)
+            log(f"[bench] {out['d6_l6_fp64']}")
         log("[bench] propagators (D=6, L=6)")
         out["propagators"] = propagators(sg)
         log(f"[bench] {out['propagators']}")
-        log("[bench] batched (64 instances)")
-        out["batched"] = batched(sg, args.batch_steps)
-        log(f"[bench] {out['batched']}")
-        log("[bench] serving")
-        out["serve"] = serve(sg, args.serve_window, args.serve_steps_scale)
+        log(f"[bench] batched (64 instances, {args.batch_steps} steps, mixed and fp64)")
+        out["batched"] = batched(sg, args.batch_steps, args.batch_latency_steps)
+        log(f"[bench] { {k: v for k, v in out['batched'].items() if k != 'final_state_rel_err_vs_fp64'} }")
+        log("[bench] serving (mixed and fp64 legs)")
+        out["serve"] = serve(sg, args.serve_window, args.serve_steps_scale,
+                             args.serve_mixed_threshold)
         log(f"[bench] {out['serve']}")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(inst, info, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_budget)
+        log(f"[bench] {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 
 
