@@ -151,3 +151,69 @@ def small_instance(D: int, L: int, seed: int = 123, with_k: bool = True,
     inst.nq_A, inst.nq_B = nq
     inst.meta = dict(name=f"small_d{D}_l{L}_s{seed}")
     return inst
+
+
+# ---------------------------------------------------------------------------
+# Two-state (vibronic) instances: the form of the paper's Sec. 5 pyrazine
+# model (gap 2 Delta, linear interstate coupling lambda Q_1, state-dependent
+# linear terms on the other modes), whose parameters the paper does not give,
+# plus optional state-dependent quartic couplings of the family above.
+#   H = sum_i 1/2 omega_i (-d^2/dQ_i^2 + Q_i^2) (x) 1
+#       + [[V_00, V_01], [V_01, V_11]],
+#   V_ss = E_s + sum_i kappa[s, i] Q_i + sum_{i<j} c2[s, i, j] Q_i^2 Q_j^2,
+#   V_01 = sum_i lam[i] Q_i.
+# Draw order per instance: omega[D], Delta, kappa[0, 1:], kappa[1, 1:],
+# lam[0], then (quartic) c2[0] (i<j, row-major), c2[1], then shift[D].
+# ---------------------------------------------------------------------------
+
+@dataclass
+class VibronicInstance:
+    D: int
+    L: int
+    omega: np.ndarray            # [D]
+    E: np.ndarray                # [2] state energies (-Delta, Delta)
+    kappa: np.ndarray            # [2, D] state-dependent linear terms
+    lam: np.ndarray              # [D] interstate linear coupling
+    c2: np.ndarray               # [2, D, D] quartic couplings, i<j entries
+    shift: np.ndarray            # [D] displacement of the initial Gaussian
+    state0: int = 1              # electronic state the initial packet is on
+    nb_A: int = NB_A
+    nb_B: int = NB_B
+    nq_A: int = NQ_A
+    nq_B: int = NQ_B
+    meta: dict = field(default_factory=dict)
+
+
+def draw_vibronic(rng: np.random.Generator, D: int, L: int,
+                  quartic: bool = True) -> VibronicInstance:
+    omega = rng.uniform(0.5, 2.0, size=D)
+    delta = rng.uniform(0.1, 0.5)
+    kappa = np.zeros((2, D))
+    kappa[0, 1:] = rng.uniform(-0.2, 0.2, size=D - 1)
+    kappa[1, 1:] = rng.uniform(-0.2, 0.2, size=D - 1)
+    lam = np.zeros(D)
+    lam[0] = rng.uniform(0.1, 0.4)
+    c2 = np.zeros((2, D, D))
+    if quartic:
+        iu = np.triu_indices(D, 1)
+        for s in range(2):
+            c2[s][iu] = rng.uniform(-0.05, 0.05, size=len(iu[0]))
+    shift = rng.uniform(-1.0, 1.0, size=D)
+    return VibronicInstance(D=D, L=L, omega=omega, E=np.array([-delta, delta]),
+                            kappa=kappa, lam=lam, c2=c2, shift=shift)
+
+
+def vibronic_small(D: int, L: int, seed: int = 321, quartic: bool = True) -> VibronicInstance:
+    """A small seeded two-state instance for parity tests."""
+    inst = draw_vibronic(np.random.default_rng(seed), D, L, quartic=quartic)
+    inst.meta = dict(name=f"vib_d{D}_l{L}_s{seed}")
+    return inst
+
+
+def vibronic_pyrazine(L: int = 5, seed: int | None = None) -> VibronicInstance:
+    """12 modes, the size of the paper's pyrazine propagation, with the
+    pyrazine form (no quartic terms); Chebyshev steps of dt = 0.05."""
+    rng = np.random.default_rng(DEFAULT_SEED + 5 if seed is None else seed)
+    inst = draw_vibronic(rng, 12, L, quartic=False)
+    inst.meta = dict(name=f"vib_pyrazine_d12_l{L}", dt=0.05)
+    return inst
