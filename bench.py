@@ -394,9 +394,12 @@ def propagators(sg, steps=40, dt=0.05):
 
 def batched(sg, steps, latency_steps):
     """64 independent instances (D ~ U{4..10}, L ~ U{4..7}), all advanced in
-    one launch sequence, mixed (the precision policy below) and FP64 legs over
-    the same `steps` steps: instance-applies/s, p50/p99 of one batched step,
-    and each instance's distance from its FP64 result."""
+    one launch sequence, mixed and FP64 legs over the same `steps` steps:
+    instance-applies/s, p50/p99 of one batched step, and each instance's
+    distance from its FP64 result.  The term schedule comes from the batch
+    autotuner; each instance's FP32 share from the precision autotuner, asked
+    for the 1e-6 bar at the end of the whole propagation (the per-apply error
+    budget is the bar divided by the number of applies)."""
     import torch
     import sg_inputs
     insts = sg_inputs.config3()
@@ -410,11 +413,13 @@ def batched(sg, steps, latency_steps):
         a, b = sg.sg_spectral_bounds(P.handle, 40)
         lo.append(a)
         hi.append(b)
-        # per instance: the fastest FP32 share within half the bar on its
-        # own initial state
-        t, _ = sg.sg_tune_mixed(P.handle, x, TOL_MIXED, 2)
+        # per instance: the fastest FP32 share whose error on its own initial
+        # state stays within the bar spread over the propagation's applies
+        K = 14
+        t, _ = sg.sg_tune_mixed(P.handle, x, TOL_MIXED / (steps * (K - 1)), 2)
         thr.append(int(t))
     b = sg.sg_batch_create([P.handle for P in probs])
+    tuned_g, tuned_ms = sg.sg_batch_tune_schedule(b, psi0, sg.SG_FP64, reps=3)
     dts = [i.meta["dt"] for i in insts]
     legs = {}
     finals = {}
@@ -452,6 +457,7 @@ def batched(sg, steps, latency_steps):
         P.close()
     return {"workload": "64 instances, D ~ U{4..10}, L ~ U{4..7}, dt = 0.05",
             "steps": steps, "mixed": legs["mixed"], "fp64": legs["fp64"],
+            "schedule_block_min_grid": tuned_g, "schedule_tuned_apply_ms": tuned_ms,
             "speedup_mixed_vs_fp64": legs["fp64"]["seconds"] / legs["mixed"]["seconds"],
             "mixed_thresholds": thr,
             "instances_with_fp32_terms": int(sum(t > 0 for t in thr)),
@@ -513,8 +519,11 @@ def serve(sg, window_s, steps_scale, mixed_threshold):
         reqs.append({"arrival_s": r.arrival_s, "inst": r.inst, "L": L,
                      "n_cs": sg.sg_count_sizes(r.inst.D, L)[2],
                      "steps": max(1, int(round(r.steps * steps_scale)))})
-    mixed, s_mixed = serve_leg(sg, reqs, sg.SG_MIXED, mixed_threshold)
+    # untimed warm-up (first launches of every kernel variant, compile threads)
+    serve_leg(sg, [dict(r, steps=1) for r in reqs[:8]], sg.SG_MIXED, mixed_threshold)
+    serve_leg(sg, [dict(r, steps=1) for r in reqs[:8]], sg.SG_FP64, -1)
     fp64, s_fp64 = serve_leg(sg, reqs, sg.SG_FP64, -1)
+    mixed, s_mixed = serve_leg(sg, reqs, sg.SG_MIXED, mixed_threshold)
     errs = [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(s_mixed, s_fp64)]
     return {"workload": "Poisson 20 req/s, D ~ U{3..20}, L ~ U{3..6} (N_s <= 5e7)",
             "window_s": window_s, "steps_scale": steps_scale,
@@ -558,8 +567,8 @@ def main():
     ap.add_argument("--forced-curve-steps", type=int, default=100)
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--batch-latency-steps", type=int, default=20)
-    ap.add_argument("--serve-window", type=float, default=2.0)
-    ap.add_argument("--serve-steps-scale", type=float, default=0.1)
+    ap.add_argument("--serve-window", type=float, default=3.0)
+    ap.add_argument("--serve-steps-scale", type=float, default=0.2)
     ap.add_argument("--serve-mixed-threshold", type=int, default=0)
     ap.add_argument("--grid-kinetic", action="store_true",
                     help="SG_FP64 in the literal form (kinetic matrices on every term grid) "

@@ -275,7 +275,71 @@ sg_status sg_batch_propagate(sg_batch *b, void *const *psi, int32_t n, const dou
                              const double *emin, const double *emax, double tol,
                              sg_precision prec, int32_t check_every, int32_t use_graph,
                              sg_prop_stats *stats, void *stream);
+/* Schedule autotuner over the batch's union of terms: terms of at least g
+ * grid points run on a whole workgroup (g = 0: only those a wavefront cannot
+ * hold), for g = 0, 256, 512, ... up to the largest term grid.  Each
+ * candidate plan applies H once to every instance's state psi[i] (n states,
+ * as sg_batch_propagate); the outputs must agree bitwise across candidates
+ * (SG_EDEVICE otherwise), and the fastest of three timed rounds of `reps`
+ * applies is kept (the first candidate unless another is faster by more than
+ * 1%).  chosen_block_min_grid / best_ms: nullable outputs.  Synchronous. */
+sg_status sg_batch_tune_schedule(sg_batch *b, void *const *psi, int32_t n, int32_t prec,
+                                 int32_t reps, int32_t *chosen_block_min_grid, double *best_ms,
+                                 void *stream);
 sg_status sg_batch_free(sg_batch *b);
+
+/* Two-state (vibronic) Hamiltonians: the form of the paper's Sec. 5 pyrazine
+ * model (two electronic states; at every nuclear configuration the operator
+ * is a 2 x 2 matrix), with optional state-dependent quartic couplings:
+ *
+ *   H = sum_i 1/2 omega_i (-d^2/dQ_i^2 + Q_i^2) (x) 1
+ *       + [[V_00(Q), V_01(Q)], [V_01(Q), V_11(Q)]],
+ *   V_ss = E_s + sum_i kappa_s,i Q_i + sum_{i<j} c2_s,ij Q_i^2 Q_j^2,
+ *   V_01 = sum_i lambda_i Q_i.
+ *
+ * (Pyrazine: E = (-Delta, Delta), lambda only on mode 1, kappa_s,1 = 0.)
+ * Standard size maps only (nb(l) = 2l+1, nq(l) = 2l+2), L <= 6.  The wave
+ * packet is state-major: device complex128[2 N_cs], state 0's coefficients in
+ * compact order, then state 1's; N_cs and the compact order are those of
+ * the one-state structure (sg_vibronic_problem).  Each term runs Alg. 1 on
+ * both states, the 2 x 2 matrix acting at every grid point; the separable
+ * harmonic part and E_s act as the exact FP64 diagonal; the scatter-add is
+ * the fixed-order reduce (bitwise reproducible).  All FP64. */
+typedef struct {
+  int32_t D;             /* modes, 1..64                                      */
+  int32_t L;             /* Smolyak level, 0..6                               */
+  const double *omega;   /* [D] > 0                                           */
+  const double *E;       /* [2] state energies                                */
+  const double *kappa;   /* [2*D] row s: state s's linear coefficients        */
+  const double *lambda;  /* [D] interstate linear coupling                    */
+  const double *c2;      /* [2*D*D] row-major per state, entries i<j used;
+                            NULL means all zero                               */
+} sg_vibronic_desc;
+typedef struct sg_vibronic sg_vibronic;
+/* Host compile + device upload (synchronous).  SG_EINVAL on bad input. */
+sg_status sg_vibronic_build(const sg_vibronic_desc *desc, sg_vibronic **out);
+sg_status sg_vibronic_free(sg_vibronic *v);
+/* The one-state structure the handle owns (sizes, compact order through
+ * sg_problem_info / sg_basis_indices; sg_set_timing / sg_get_timing time the
+ * two-state kernels).  Valid until sg_vibronic_free; do not free it. */
+sg_status sg_vibronic_problem(const sg_vibronic *v, sg_problem **out);
+/* Algorithmic flops and HBM bytes of one two-state term sweep. */
+sg_status sg_vibronic_figures(const sg_vibronic *v, double *sweep_flops, double *sweep_bytes);
+/* psi (device complex128[2 N_cs]) = the displaced Gaussian (as
+ * sg_init_gaussian) on electronic state `state` (0 or 1), zero on the other. */
+sg_status sg_vibronic_init(sg_vibronic *v, const double *shift, int32_t state, void *psi,
+                           void *stream);
+/* psi_out = H_S psi_in, both device complex128[2 N_cs], distinct.  Async. */
+sg_status sg_vibronic_apply(sg_vibronic *v, const void *psi_in, void *psi_out, void *stream);
+/* Spectral bounds by `iters` Lanczos steps, padded as sg_spectral_bounds. */
+sg_status sg_vibronic_bounds(sg_vibronic *v, int32_t iters, double *emin, double *emax,
+                             void *stream);
+/* Chebyshev propagation in place, as sg_propagate_chebyshev (FP64).
+ * pop_trace (nullable): the population of state 1 at each check (same
+ * points as the norm checks: step 0, every check_every steps, the end). */
+sg_status sg_vibronic_propagate(sg_vibronic *v, void *psi, double dt, int32_t nsteps,
+                                double emin, double emax, double tol, int32_t check_every,
+                                sg_prop_stats *stats, double *pop_trace, void *stream);
 
 /* Continuous-batching server of propagation requests on one device.
  *

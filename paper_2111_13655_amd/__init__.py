@@ -28,9 +28,13 @@ __all__ = [
     "sg_set_timing", "sg_get_timing", "sg_set_mixed_threshold",
     "sg_tune_mixed", "sg_set_operator_form", "sg_set_schedule", "sg_tune_schedule",
     "sg_eigensolve", "sg_embed_basis",
-    "sg_batch_create", "sg_batch_size", "sg_batch_propagate", "sg_batch_free",
+    "sg_batch_create", "sg_batch_size", "sg_batch_propagate", "sg_batch_tune_schedule",
+    "sg_batch_free",
     "ServeConfig", "sg_serve_create", "sg_serve_submit", "sg_serve_poll", "sg_serve_cancel",
     "sg_serve_counters", "sg_serve_destroy", "Problem",
+    "VibronicDesc", "sg_vibronic_build", "sg_vibronic_free", "sg_vibronic_problem",
+    "sg_vibronic_figures", "sg_vibronic_init", "sg_vibronic_apply", "sg_vibronic_bounds",
+    "sg_vibronic_propagate", "Vibronic",
 ]
 
 SG_OK, SG_EINVAL, SG_ENOMEM, SG_EDEVICE = 0, -1, -2, -3
@@ -59,6 +63,15 @@ class ProblemDesc(ctypes.Structure):
                 ("omega", ctypes.POINTER(ctypes.c_double)),
                 ("c", ctypes.POINTER(ctypes.c_double)),
                 ("k", ctypes.POINTER(ctypes.c_double))]
+
+
+class VibronicDesc(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("omega", ctypes.POINTER(ctypes.c_double)),
+                ("E", ctypes.POINTER(ctypes.c_double)),
+                ("kappa", ctypes.POINTER(ctypes.c_double)),
+                ("lam", ctypes.POINTER(ctypes.c_double)),
+                ("c2", ctypes.POINTER(ctypes.c_double))]
 
 
 class Info(ctypes.Structure):
@@ -159,7 +172,25 @@ _SIGNATURES = {
                                     ctypes.c_int32, ctypes.c_double, ctypes.c_int, ctypes.c_int32,
                                     ctypes.POINTER(PropStats), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double), _P]),
+    "sg_vibronic_build": (ctypes.c_int, [ctypes.POINTER(VibronicDesc), ctypes.POINTER(_P)]),
+    "sg_vibronic_free": (ctypes.c_int, [_P]),
+    "sg_vibronic_problem": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
+    "sg_vibronic_figures": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double)]),
+    "sg_vibronic_init": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _P,
+                                        _P]),
+    "sg_vibronic_apply": (ctypes.c_int, [_P, _P, _P, _P]),
+    "sg_vibronic_bounds": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double), _P]),
+    "sg_vibronic_propagate": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32,
+                                             ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_int32, ctypes.POINTER(PropStats),
+                                             ctypes.POINTER(ctypes.c_double), _P]),
     "sg_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)]),
+    "sg_batch_tune_schedule": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_double), _P]),
     "sg_batch_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int64)]),
     "sg_batch_propagate": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.c_int32,
@@ -504,6 +535,21 @@ def sg_batch_propagate(b, psis, dts, nsteps: int, emins=None, emaxs=None, tol: f
     return status, [st[i].as_dict() for i in range(n)]
 
 
+def sg_batch_tune_schedule(b, psis, precision: int = SG_FP64, reps: int = 3, stream=None):
+    """Tunes the batch's term schedule on its instances' states; returns
+    (chosen block_min_grid, best ms per batched apply)."""
+    n_inst, n_cs = sg_batch_size(b)
+    if len(psis) != n_inst:
+        raise ValueError(f"{len(psis)} states for a batch of {n_inst} instances")
+    for i, t in enumerate(psis):
+        _vec_ptr(t, n_cs[i], f"psi[{i}]")
+    ptrs = (_P * n_inst)(*[t.data_ptr() for t in psis])
+    g, ms = ctypes.c_int32(0), ctypes.c_double(0.0)
+    _check(lib().sg_batch_tune_schedule(b, ptrs, n_inst, int(precision), int(reps),
+                                        ctypes.byref(g), ctypes.byref(ms), _stream_ptr(stream)))
+    return g.value, ms.value
+
+
 def sg_batch_free(b) -> None:
     _check(lib().sg_batch_free(b))
 
@@ -580,6 +626,111 @@ class Problem:
     def close(self):
         if self.handle is not None:
             sg_free(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Two-state (vibronic) problems
+# ---------------------------------------------------------------------------
+
+def sg_vibronic_build(D, L, omega, E, kappa, lam, c2=None):
+    omega = np.ascontiguousarray(omega, dtype=np.float64).reshape(D)
+    E = np.ascontiguousarray(E, dtype=np.float64).reshape(2)
+    kappa = np.ascontiguousarray(kappa, dtype=np.float64).reshape(2 * D)
+    lam = np.ascontiguousarray(lam, dtype=np.float64).reshape(D)
+    c2a = None if c2 is None else np.ascontiguousarray(c2, dtype=np.float64).reshape(2 * D * D)
+    d = VibronicDesc(int(D), int(L), _dptr(omega), _dptr(E), _dptr(kappa), _dptr(lam),
+                     _dptr(c2a) if c2a is not None else ctypes.POINTER(ctypes.c_double)())
+    h = _P()
+    _check(lib().sg_vibronic_build(ctypes.byref(d), ctypes.byref(h)))
+    return h
+
+
+def sg_vibronic_free(v) -> None:
+    _check(lib().sg_vibronic_free(v))
+
+
+def sg_vibronic_problem(v):
+    """The one-state structure handle (owned by v)."""
+    h = _P()
+    _check(lib().sg_vibronic_problem(v, ctypes.byref(h)))
+    return h
+
+
+def sg_vibronic_figures(v):
+    f, b = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().sg_vibronic_figures(v, ctypes.byref(f), ctypes.byref(b)))
+    return f.value, b.value
+
+
+def sg_vibronic_init(v, n_cs, shift, state, psi, stream=None) -> None:
+    shift = np.ascontiguousarray(shift, dtype=np.float64)
+    _check(lib().sg_vibronic_init(v, _dptr(shift), int(state), _vec_ptr(psi, 2 * n_cs, "psi"),
+                                  _stream_ptr(stream)))
+
+
+def sg_vibronic_apply(v, n_cs, psi_in, psi_out, stream=None) -> None:
+    _check(lib().sg_vibronic_apply(v, _vec_ptr(psi_in, 2 * n_cs, "psi_in"),
+                                   _vec_ptr(psi_out, 2 * n_cs, "psi_out"), _stream_ptr(stream)))
+
+
+def sg_vibronic_bounds(v, iters: int = 40, stream=None):
+    lo, hi = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().sg_vibronic_bounds(v, int(iters), ctypes.byref(lo), ctypes.byref(hi),
+                                    _stream_ptr(stream)))
+    return lo.value, hi.value
+
+
+def sg_vibronic_propagate(v, n_cs, psi, dt: float, nsteps: int, emin=math.nan, emax=math.nan,
+                          tol: float = 0.0, check_every: int = 0, stream=None):
+    """Returns (status, stats dict, population of state 1 at the checks)."""
+    st = PropStats()
+    ntr = max((nsteps // check_every + 2) if check_every > 0 else 2, 2)
+    pop = np.zeros(ntr)
+    status = lib().sg_vibronic_propagate(v, _vec_ptr(psi, 2 * n_cs, "psi"), float(dt),
+                                         int(nsteps), float(emin), float(emax), float(tol),
+                                         int(check_every), ctypes.byref(st), _dptr(pop),
+                                         _stream_ptr(stream))
+    if status not in (SG_OK, SG_ETOL):
+        _check(status)
+    d = st.as_dict()
+    done = d["steps_done"]
+    n = (1 + (done // check_every if check_every > 0 else 0)) if done < nsteps else \
+        ((0 if nsteps == 0 else 1 + ((nsteps - 1) // check_every if check_every > 0 else 0)) + 1)
+    return status, d, pop[:min(n, ntr)]
+
+
+class Vibronic:
+    """Owns one two-state problem handle built on the current device."""
+
+    def __init__(self, D, L, omega, E, kappa, lam, c2=None):
+        self.handle = sg_vibronic_build(D, L, omega, E, kappa, lam, c2)
+        self.problem = sg_vibronic_problem(self.handle)
+        self.info = sg_problem_info(self.problem)
+        self.n_cs = self.info["n_cs"]
+
+    @classmethod
+    def from_instance(cls, inst):
+        return cls(inst.D, inst.L, inst.omega, inst.E, inst.kappa, inst.lam, inst.c2)
+
+    def apply(self, psi_in, psi_out, stream=None):
+        sg_vibronic_apply(self.handle, self.n_cs, psi_in, psi_out, stream)
+
+    def close(self):
+        if self.handle is not None:
+            sg_vibronic_free(self.handle)
             self.handle = None
 
     def __enter__(self):

@@ -117,6 +117,14 @@ hipError_t run_reduce(sg_problem *owner, const Plan *pl, const LaunchCtl &c, hip
   return timed(owner, 1, s, c, [&](const LaunchCtl &ct) { return launch_reduce(pl, ct, s); });
 }
 
+hipError_t run_vib_sweep(sg_problem *owner, const VibLaunch &v, const double2 *vin, double2 *tm,
+                         hipStream_t s) {
+  if (!owner) return launch_vib_sweep(v, vin, tm, s, nullptr, nullptr);
+  return timed(owner, 0, s, LaunchCtl{}, [&](const LaunchCtl &ct) {
+    return launch_vib_sweep(v, vin, tm, s, ct.ev0, ct.ev1);
+  });
+}
+
 }  // namespace sg
 
 using namespace sg;

@@ -4,6 +4,7 @@
 // launches can be captured once into a hipGraph and replayed.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <new>
 #include <vector>
 
@@ -78,6 +79,116 @@ sg_status sg_batch_create(sg_problem *const *problems, int32_t n, sg_batch **out
     return st;
   }
   *out = b;
+  return SG_OK;
+}
+
+sg_status sg_batch_tune_schedule(sg_batch *b, void *const *psi, int32_t n_psi, int32_t prec,
+                                 int32_t reps, int32_t *chosen_block_min_grid, double *best_ms,
+                                 void *stream) {
+  if (!b || !psi) return fail(SG_EINVAL, "NULL argument");
+  if (n_psi != (int32_t)b->probs.size())
+    return fail(SG_EINVAL, "the number of states must equal the batch's number of instances");
+  if (reps < 1) return fail(SG_EINVAL, "reps must be >= 1");
+  if (prec != SG_FP64 && prec != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
+  for (int i = 0; i < n_psi; ++i)
+    if (!psi[i]) return fail(SG_EINVAL, "NULL state");
+  hipStream_t s = (hipStream_t)stream;
+  const int n = (int)b->probs.size();
+  int64_t max_grid = 0, total = 0;
+  for (sg_problem *p : b->probs) {
+    max_grid = std::max<int64_t>(max_grid, p->h.max_grid);
+    total += p->h.ncs;
+  }
+  // candidates: terms of at least g grid points run on a whole workgroup
+  std::vector<int32_t> cand = {0};
+  for (int32_t g = 256; g <= max_grid; g *= 2) cand.push_back(g);
+  const std::vector<int32_t> saved = [&] {
+    std::vector<int32_t> v;
+    for (sg_problem *p : b->probs) v.push_back(p->block_grid);
+    return v;
+  }();
+  // one batched apply: every instance's state in x0, its own work buffer out
+  auto rebuild = [&](int32_t g) -> sg_status {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "synchronise before the plan upload");
+    for (sg_problem *p : b->probs) p->block_grid = g;
+    std::string err;
+    sg_status st = plan_build(&b->plan, b->probs, &err);
+    if (st != SG_OK) return fail(st, err);
+    for (int i = 0; i < n; ++i) {
+      b->plan.inst[i].result = b->d_results + 2 * i;
+      b->plan.inst[i].x0 = (double2 *)psi[i];
+    }
+    return plan_upload(&b->plan, s);
+  };
+  LaunchCtl c;
+  c.mode = Mode::Apply;
+  c.prec = (sg_precision)prec;
+  auto apply_all = [&]() -> hipError_t {
+    hipError_t e = launch_sweep(&b->plan, c, s);
+    if (e == hipSuccess) e = launch_reduce(&b->plan, c, s);
+    return e;
+  };
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(SG_EDEVICE, "hipEventCreate");
+  std::vector<double2> h_ref((size_t)total), h_out((size_t)total);
+  sg_status st = SG_OK;
+  int32_t best = cand[0];
+  double best_t = 1e300;
+  for (size_t ci = 0; ci < cand.size() && st == SG_OK; ++ci) {
+    if ((st = rebuild(cand[ci])) != SG_OK) break;
+    if (apply_all() != hipSuccess) {
+      st = fail(SG_EDEVICE, "batched apply");
+      break;
+    }
+    // every schedule computes each term with the same arithmetic: the
+    // outputs must agree bitwise
+    double2 *dst = ci == 0 ? h_ref.data() : h_out.data();
+    size_t at = 0;
+    for (int i = 0; i < n && st == SG_OK; ++i) {
+      const int64_t m = b->probs[i]->h.ncs;
+      if (hipMemcpyAsync(dst + at, b->plan.inst[i].x1, (size_t)m * sizeof(double2),
+                         hipMemcpyDeviceToHost, s) != hipSuccess)
+        st = fail(SG_EDEVICE, "copy of the tuning result");
+      at += (size_t)m;
+    }
+    if (st != SG_OK || hipStreamSynchronize(s) != hipSuccess) {
+      if (st == SG_OK) st = fail(SG_EDEVICE, "tuning synchronisation");
+      break;
+    }
+    if (ci > 0 && std::memcmp(h_ref.data(), h_out.data(), (size_t)total * sizeof(double2)) != 0) {
+      st = fail(SG_EDEVICE, "schedules disagree bitwise");
+      break;
+    }
+    double t = 1e300;
+    for (int round = 0; round < 3; ++round) {
+      hipEventRecord(e0, s);
+      for (int r = 0; r < reps; ++r) apply_all();
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      t = std::min(t, (double)ms / reps);
+    }
+    // the default (first) stays unless another schedule is faster by more
+    // than the timing noise
+    if (ci == 0 || t < 0.99 * best_t) {
+      best_t = t;
+      best = cand[ci];
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != SG_OK) {
+    for (int i = 0; i < n; ++i) b->probs[i]->block_grid = saved[i];
+    rebuild(saved.empty() ? 0 : saved[0]);
+    for (int i = 0; i < n; ++i) b->probs[i]->block_grid = saved[i];
+    return st;
+  }
+  if ((st = rebuild(best)) != SG_OK) return st;
+  if (chosen_block_min_grid) *chosen_block_min_grid = best;
+  if (best_ms) *best_ms = best_t;
   return SG_OK;
 }
 

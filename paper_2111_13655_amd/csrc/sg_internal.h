@@ -127,6 +127,9 @@ struct InstDev {
   double ebar, inv_half, phase_re, phase_im;
   int32_t active;           // 0: the launch skips this instance
   int32_t pad;
+  int64_t vec_off;          // added to the launch's vector overrides (x0o, x1o) for this
+                            // instance: the electronic states of a two-state problem
+                            // are instances over consecutive halves of one vector
 };
 
 // Term-sweep packing.  A workgroup (kSweepThreads threads, eight wavefronts)
@@ -466,6 +469,34 @@ void release_problem(sg_problem *p);
 
 // Chebyshev series for one instance: K and coefficients for R = dE dt / 2.
 int chebyshev_series(double R, std::vector<double> *a);
+
+// Two-state (vibronic) term sweep (sg_vibronic.hip).  Coefficient block per
+// term: kVibSurf doubles per state (constant, Q_p^2, Q_p, pair Q_p^2 Q_q^2
+// coefficients of the active modes) and the interstate Q_p coefficients.
+constexpr int kVibSurf = 17 + kMaxPairs;   // 45
+constexpr int kVibCoef = 104;              // 2 kVibSurf + kMaxActive, padded
+static_assert(2 * kVibSurf + kMaxActive <= kVibCoef, "vibronic coefficient block");
+struct VibGroup {
+  int32_t first = 0, count = 0;   // range of the term order launched together
+  int32_t max_grid = 0;           // largest grid of the group (sizes its LDS)
+};
+struct VibLaunch {
+  const TermDev *terms = nullptr;
+  const int32_t *mb = nullptr;
+  const double *tab = nullptr;    // standard-map tables, levels 0..L
+  const double *coef = nullptr;   // [nterms][kVibCoef]
+  const int32_t *order = nullptr; // device: terms, largest grid first
+  std::vector<VibGroup> groups;
+  int64_t ncs = 0, ns = 0;
+  int tab_elems = 0;
+};
+// vin: [2 N_cs] state-major; tm: [2 N_s].  ev0 / ev1 (nullable) attach to the
+// first / last dispatch.
+hipError_t launch_vib_sweep(const VibLaunch &v, const double2 *vin, double2 *tm, hipStream_t s,
+                            hipEvent_t ev0, hipEvent_t ev1);
+// the same, timed as a sweep by owner's events when its timing is on
+hipError_t run_vib_sweep(sg_problem *owner, const VibLaunch &v, const double2 *vin, double2 *tm,
+                         hipStream_t s);
 
 // Work buffers of one sg_propagate call (sg_step.cpp): allocated for the call
 // (owned), or carved out of a region the caller provides (not owned).

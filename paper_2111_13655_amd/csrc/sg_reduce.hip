@@ -90,8 +90,8 @@ struct RowIn {
 
 __device__ __forceinline__ RowIn row_inputs(const ReduceArgs &a, cptr<InstDev> I, int64_t row) {
   RowIn in{};
-  double2 *x0 = a.x0o ? a.x0o : I->x0;
-  double2 *x1 = a.x1o ? a.x1o : I->x1;
+  double2 *x0 = a.x0o ? a.x0o + I->vec_off : I->x0;
+  double2 *x1 = a.x1o ? a.x1o + I->vec_off : I->x1;
   const double2 *vin = (a.mode == 0) ? x0 : (((a.k - 1) & 1) ? x1 : x0);
   in.vk = ldz((glb_p<const Z64>)vin + row);
   in.d = a.split ? ((glb_p<const double>)I->h0)[row] : 0.0;
@@ -110,8 +110,8 @@ __device__ __forceinline__ RowIn row_inputs(const ReduceArgs &a, cptr<InstDev> I
 __device__ __forceinline__ void row_epilogue(const ReduceArgs &a, cptr<InstDev> I, int64_t row,
                                              const RowIn &in, double sr, double si, double *pn,
                                              double *pe) {
-  double2 *x0 = a.x0o ? a.x0o : I->x0;
-  double2 *x1 = a.x1o ? a.x1o : I->x1;
+  double2 *x0 = a.x0o ? a.x0o + I->vec_off : I->x0;
+  double2 *x1 = a.x1o ? a.x1o + I->vec_off : I->x1;
   const Z64 vk = in.vk;
   if (a.split) {
     sr = fma(in.d, vk.x, sr);

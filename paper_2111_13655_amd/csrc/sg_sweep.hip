@@ -1419,8 +1419,8 @@ __device__ __forceinline__ bool live(const SweepArgs &a, cptr<InstDev> I) {
   return I->active && (a.mode == 0 || a.k <= I->K - 1);
 }
 __device__ __forceinline__ const double2 *input_of(const SweepArgs &a, cptr<InstDev> I) {
-  double2 *x0 = a.x0o ? a.x0o : I->x0;
-  double2 *x1 = a.x1o ? a.x1o : I->x1;
+  double2 *x0 = a.x0o ? a.x0o + I->vec_off : I->x0;
+  double2 *x1 = a.x1o ? a.x1o + I->vec_off : I->x1;
   if (a.mode == 0) return x0;
   return ((a.k - 1) & 1) ? x1 : x0;   // phi_{k-1}
 }

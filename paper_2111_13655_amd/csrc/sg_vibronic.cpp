@@ -1,0 +1,454 @@
+// Two-state (vibronic) Hamiltonians of the paper's Sec. 5 pyrazine form: the
+// host side.  A two-state problem shares the one-state Smolyak structure
+// (terms, D_l, compact basis, M^B and its inverse, tables) of a problem built
+// from the harmonic frequencies alone; on top of it come
+//   * per-term coefficient blocks of the three potentials V_00, V_11, V_01
+//     with level-0 modes integrated out exactly (the nq = 2 rule of a level-0
+//     mode gives <Q> = 0 and <Q^2> = 1/2 for the single Hermite function);
+//   * the exact diagonals h0 + E_s of the two states (the separable harmonic
+//     part and the state energies, by the combination identity);
+//   * a two-instance launch plan for the fixed-order reduce: instance s sums
+//     state s's term-major contributions into the compact rows of state s,
+//     with its own diagonal, partial sums and Chebyshev accumulator, over the
+//     s-th half of the state-major vectors.
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "sg_internal.h"
+
+struct sg_vibronic {
+  sg_problem *p = nullptr;        // one-state structure
+  sg::Plan plan;                  // the reduce over both states
+  sg::VibLaunch vl;
+  double E[2] = {0.0, 0.0};
+  double *d_coef = nullptr;       // [nterms][kVibCoef]
+  int32_t *d_order = nullptr;     // terms, largest grid first
+  double *d_h0s = nullptr;        // [2 N_cs] h0 + E_s
+  double2 *d_tm = nullptr;        // [2 N_s]
+  double2 *d_work = nullptr;      // 4 x [2 N_cs]: phi, accumulator, two spares
+  double *d_partials = nullptr;   // [2][2 n_items]
+  double *d_rpart = nullptr;      // [2][2 n_items]
+  double *d_res = nullptr;        // [8]
+  double *d_dot = nullptr;        // dot partials
+  double *h_res = nullptr;        // pinned [8]
+  double sweep_flops = 0.0, sweep_bytes = 0.0;
+};
+
+namespace sg {
+namespace {
+
+void vib_release(sg_vibronic *v) {
+  if (!v) return;
+  plan_free(&v->plan);
+  hipFree(v->d_coef);
+  hipFree(v->d_order);
+  hipFree(v->d_h0s);
+  hipFree(v->d_tm);
+  hipFree(v->d_work);
+  hipFree(v->d_partials);
+  hipFree(v->d_rpart);
+  hipFree(v->d_res);
+  hipFree(v->d_dot);
+  if (v->h_res) hipHostFree(v->h_res);
+  if (v->p) sg_free(v->p);
+  delete v;
+}
+
+sg_status read_res(sg_vibronic *v, hipStream_t s, int n, double *out) {
+  hipError_t e = hipMemcpyAsync(v->h_res, v->d_res, n * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "read reduction result");
+  for (int i = 0; i < n; ++i) out[i] = v->h_res[i];
+  return SG_OK;
+}
+
+// <x|y> over n complex entries (fixed-order partial sums), result at d_res[slot]
+hipError_t vdot(sg_vibronic *v, const double2 *x, const double2 *y, int64_t n, int slot,
+                hipStream_t s) {
+  return launch_multi_dot(x, n, 1, y, n, v->d_dot, v->d_res + slot, s);
+}
+
+}  // namespace
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+sg_status sg_vibronic_build(const sg_vibronic_desc *d, sg_vibronic **out) {
+  if (!out) return fail(SG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!d || !d->omega || !d->E || !d->kappa || !d->lambda) return fail(SG_EINVAL, "NULL argument");
+  if (d->D < 1 || d->D > 64) return fail(SG_EINVAL, "D must be 1..64");
+  if (d->L < 0 || d->L > 6) return fail(SG_EINVAL, "the two-state path takes L = 0..6");
+  const int D = d->D;
+  for (int i = 0; i < D; ++i)
+    if (!(d->omega[i] > 0.0) || !std::isfinite(d->omega[i])) return fail(SG_EINVAL, "omega must be > 0");
+  for (int i = 0; i < 2 * D; ++i)
+    if (!std::isfinite(d->kappa[i])) return fail(SG_EINVAL, "kappa must be finite");
+  for (int i = 0; i < D; ++i)
+    if (!std::isfinite(d->lambda[i])) return fail(SG_EINVAL, "lambda must be finite");
+  if (!std::isfinite(d->E[0]) || !std::isfinite(d->E[1])) return fail(SG_EINVAL, "E must be finite");
+  auto c2 = [&](int s, int i, int j) -> double {
+    if (!d->c2 || i == j) return 0.0;
+    if (i > j) std::swap(i, j);
+    return d->c2[((size_t)s * D + i) * D + j];
+  };
+  if (d->c2)
+    for (size_t i = 0; i < (size_t)2 * D * D; ++i)
+      if (!std::isfinite(d->c2[i])) return fail(SG_EINVAL, "c2 must be finite");
+
+  sg_vibronic *v = new (std::nothrow) sg_vibronic();
+  if (!v) return fail(SG_ENOMEM, "host allocation failed");
+  v->E[0] = d->E[0];
+  v->E[1] = d->E[1];
+  std::vector<double> zero((size_t)D * D, 0.0);
+  sg_problem_desc pd{D, d->L, 1, 2, 2, 2, d->omega, zero.data(), nullptr};
+  sg_status st = sg_build_terms(&pd, &v->p);
+  if (st != SG_OK) {
+    delete v;
+    return st;
+  }
+  sg_problem *p = v->p;
+  const Compiled &h = p->h;
+  const int64_t ncs = h.ncs, ns = (int64_t)h.MB.size(), nt = h.nterms;
+  if (h.max_grid > 4096) {
+    vib_release(v);
+    return fail(SG_EINVAL, "term grid above 4096 points");
+  }
+  // coefficient blocks and the algorithmic figures
+  std::vector<double> coef((size_t)nt * kVibCoef, 0.0);
+  std::vector<int32_t> order(nt);
+  for (int64_t t = 0; t < nt; ++t) {
+    const TermDev &T = h.terms[t];
+    const int na = T.na;
+    std::vector<char> act(D, 0);
+    for (int q = 0; q < na; ++q) act[T.mode[q]] = 1;
+    double *cb = coef.data() + (size_t)t * kVibCoef;
+    for (int s = 0; s < 2; ++s) {
+      double *c = cb + s * kVibSurf;
+      for (int i = 0; i < D; ++i)
+        for (int j = i + 1; j < D; ++j)
+          if (!act[i] && !act[j]) c[0] += 0.25 * c2(s, i, j);
+      for (int q = 0; q < na; ++q) {
+        const int i = T.mode[q];
+        for (int j = 0; j < D; ++j)
+          if (!act[j]) c[1 + q] += 0.5 * c2(s, i, j);
+        c[9 + q] = d->kappa[(size_t)s * D + i];
+        for (int r = q + 1; r < na; ++r) c[17 + pair_index(q, r)] = c2(s, i, T.mode[r]);
+      }
+    }
+    for (int q = 0; q < na; ++q) cb[2 * kVibSurf + q] = d->lambda[T.mode[q]];
+    order[t] = (int32_t)t;
+    // two states through every transform; the 2 x 2 product at every grid
+    // point (4 complex-by-real multiply-adds); the D_l scaling of both
+    double f_bg = 0.0, sz = (double)T.nbasis;
+    for (int q = 0; q < na; ++q) {
+      sz = sz / T.nb[q] * T.nq[q];
+      f_bg += 4.0 * sz * T.nb[q];
+    }
+    v->sweep_flops += 2.0 * (2.0 * f_bg) + 16.0 * (double)T.ngrid + 4.0 * (double)T.nbasis;
+  }
+  v->sweep_bytes = 2.0 * 16.0 * (double)ncs + 4.0 * (double)ns + 2.0 * 16.0 * (double)ns +
+                   (double)nt * (sizeof(TermDev) + kVibCoef * 8.0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return h.terms[a].ngrid > h.terms[b].ngrid;
+  });
+  // launch groups by LDS need: grids above 1024, 257..1024, up to 256 points
+  {
+    const int bounds[3] = {1 << 30, 1024, 256};
+    int64_t i = 0;
+    for (int g = 0; g < 3; ++g) {
+      VibGroup G;
+      G.first = (int32_t)i;
+      while (i < nt && h.terms[order[i]].ngrid <= bounds[g] &&
+             (g == 2 || h.terms[order[i]].ngrid > bounds[g + 1]))
+        ++i;
+      G.count = (int32_t)(i - G.first);
+      G.max_grid = G.count ? h.terms[order[G.first]].ngrid : 0;
+      if (G.count) v->vl.groups.push_back(G);
+    }
+    if (i != nt) {
+      vib_release(v);
+      return fail(SG_EINVAL, "term grouping failed");
+    }
+  }
+  // the reduce over both states: one instance per state
+  std::string err;
+  st = plan_build(&v->plan, {p, p}, &err);
+  if (st != SG_OK) {
+    vib_release(v);
+    return fail(st, err);
+  }
+  const int64_t nitems = h.n_items + kRowWaves;
+  hipError_t e = hipMalloc((void **)&v->d_coef, coef.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void **)&v->d_order, (size_t)nt * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc((void **)&v->d_h0s, 2 * (size_t)ncs * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void **)&v->d_tm, 2 * (size_t)ns * sizeof(double2));
+  if (e == hipSuccess) e = hipMalloc((void **)&v->d_work, 8 * (size_t)ncs * sizeof(double2));
+  if (e == hipSuccess) e = hipMalloc((void **)&v->d_partials, 4 * (size_t)nitems * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void **)&v->d_rpart, 4 * (size_t)nitems * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void **)&v->d_res, 8 * sizeof(double));
+  if (e == hipSuccess)
+    e = hipMalloc((void **)&v->d_dot, 2 * (size_t)dot_partials_per_vector() * sizeof(double));
+  if (e == hipSuccess) e = hipHostMalloc((void **)&v->h_res, 8 * sizeof(double), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    vib_release(v);
+    return fail(SG_ENOMEM, "device allocation failed");
+  }
+  std::vector<double> h0s(2 * (size_t)ncs);
+  for (int s = 0; s < 2; ++s)
+    for (int64_t r = 0; r < ncs; ++r) h0s[(size_t)s * ncs + r] = h.h0[r] + d->E[s];
+  e = hipMemcpy(v->d_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(v->d_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(v->d_h0s, h0s.data(), h0s.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    vib_release(v);
+    return hip_fail(e, "upload the two-state tables");
+  }
+  for (int s = 0; s < 2; ++s) {
+    InstDev &I = v->plan.inst[s];
+    I.tm = v->d_tm + (size_t)s * ns;
+    I.h0 = v->d_h0s + (size_t)s * ncs;
+    I.x0 = v->d_work + (size_t)s * ncs;
+    I.x1 = v->d_work + 2 * (size_t)ncs + (size_t)s * ncs;
+    I.acc = v->d_work + 4 * (size_t)ncs + (size_t)s * ncs;
+    I.partials = v->d_partials + (size_t)s * 2 * nitems;
+    I.rpart = v->d_rpart + (size_t)s * 2 * nitems;
+    I.result = v->d_res + 2 * s;
+    I.vec_off = (int64_t)s * ncs;
+  }
+  st = plan_upload(&v->plan, nullptr);
+  if (st != SG_OK) {
+    vib_release(v);
+    return st;
+  }
+  v->vl.terms = p->d_terms;
+  v->vl.mb = p->d_mb;
+  v->vl.tab = v->plan.d_stab64;
+  v->vl.tab_elems = (int)((v->plan.stab64.size() + 1) & ~(size_t)1);
+  v->vl.coef = v->d_coef;
+  v->vl.order = v->d_order;
+  v->vl.ncs = ncs;
+  v->vl.ns = ns;
+  if (v->plan.stab_L < d->L) {
+    vib_release(v);
+    return fail(SG_EINVAL, "standard-map tables missing");
+  }
+  *out = v;
+  return SG_OK;
+}
+
+sg_status sg_vibronic_free(sg_vibronic *v) {
+  vib_release(v);
+  return SG_OK;
+}
+
+sg_status sg_vibronic_problem(const sg_vibronic *v, sg_problem **out) {
+  if (!v || !out) return fail(SG_EINVAL, "NULL argument");
+  *out = v->p;
+  return SG_OK;
+}
+
+sg_status sg_vibronic_figures(const sg_vibronic *v, double *sweep_flops, double *sweep_bytes) {
+  if (!v) return fail(SG_EINVAL, "NULL argument");
+  if (sweep_flops) *sweep_flops = v->sweep_flops;
+  if (sweep_bytes) *sweep_bytes = v->sweep_bytes;
+  return SG_OK;
+}
+
+sg_status sg_vibronic_init(sg_vibronic *v, const double *shift, int32_t state, void *psi,
+                           void *stream) {
+  if (!v || !shift || !psi) return fail(SG_EINVAL, "NULL argument");
+  if (state != 0 && state != 1) return fail(SG_EINVAL, "state must be 0 or 1");
+  const int64_t ncs = v->p->h.ncs;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_zero((double2 *)psi, 2 * ncs, s);
+  if (e != hipSuccess) return hip_fail(e, "clear state");
+  return sg_init_gaussian(v->p, shift, (double2 *)psi + (size_t)state * ncs, nullptr, stream);
+}
+
+sg_status sg_vibronic_apply(sg_vibronic *v, const void *psi_in, void *psi_out, void *stream) {
+  if (!v || !psi_in || !psi_out) return fail(SG_EINVAL, "NULL argument");
+  if (psi_in == psi_out) return fail(SG_EINVAL, "psi_in and psi_out must differ");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = run_vib_sweep(v->p, v->vl, (const double2 *)psi_in, v->d_tm, s);
+  if (e != hipSuccess) return hip_fail(e, "two-state term sweep");
+  LaunchCtl c;
+  c.mode = Mode::Apply;
+  c.prec = SG_FP64;
+  c.x0o = (double2 *)psi_in;
+  c.x1o = (double2 *)psi_out;
+  e = run_reduce(v->p, &v->plan, c, s);
+  if (e != hipSuccess) return hip_fail(e, "two-state reduce");
+  return SG_OK;
+}
+
+sg_status sg_vibronic_bounds(sg_vibronic *v, int32_t iters, double *emin, double *emax,
+                             void *stream) {
+  if (!v || !emin || !emax) return fail(SG_EINVAL, "NULL argument");
+  if (iters < 2) return fail(SG_EINVAL, "iters must be >= 2");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = 2 * v->p->h.ncs;
+  const int m = (int)std::min<int64_t>(iters, n);
+  double2 *vp = v->d_work, *vc = v->d_work + n, *w = v->d_work + 2 * n;
+  std::vector<double2> v0(n);
+  double nn = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double x = 1.0 + 0.5 * std::sin(0.7 * (double)i + 0.3);
+    v0[i] = make_double2(x, 0.0);
+    nn += x * x;
+  }
+  nn = std::sqrt(nn);
+  for (auto &x : v0) x.x /= nn;
+  hipError_t e = hipMemcpyAsync(vc, v0.data(), n * sizeof(double2), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_zero(vp, n, s);
+  if (e != hipSuccess) return hip_fail(e, "Lanczos setup");
+  std::vector<double> alpha, beta;
+  double b_prev = 0.0, r[2];
+  for (int j = 0; j < m; ++j) {
+    sg_status st = sg_vibronic_apply(v, vc, w, stream);
+    if (st != SG_OK) return st;
+    if ((e = vdot(v, vc, w, n, 0, s)) != hipSuccess) return hip_fail(e, "dot");
+    if ((st = read_res(v, s, 2, r)) != SG_OK) return st;
+    const double a = r[0];
+    alpha.push_back(a);
+    if ((e = launch_axpby(n, w, vc, -a, 0.0, 1.0, s)) != hipSuccess) return hip_fail(e, "axpby");
+    if (j > 0 && (e = launch_axpby(n, w, vp, -b_prev, 0.0, 1.0, s)) != hipSuccess)
+      return hip_fail(e, "axpby");
+    if ((e = vdot(v, w, w, n, 0, s)) != hipSuccess) return hip_fail(e, "dot");
+    if ((st = read_res(v, s, 2, r)) != SG_OK) return st;
+    const double b = std::sqrt(std::max(r[0], 0.0));
+    beta.push_back(b);
+    if (b < 1e-12 || j == m - 1) break;
+    if ((e = launch_axpby(n, vp, vc, 1.0, 0.0, 0.0, s)) != hipSuccess) return hip_fail(e, "axpby");
+    if ((e = launch_axpby(n, vc, w, 1.0 / b, 0.0, 0.0, s)) != hipSuccess) return hip_fail(e, "axpby");
+    b_prev = b;
+  }
+  const int k = (int)alpha.size();
+  std::vector<double> T((size_t)k * k, 0.0), ev, V;
+  for (int i = 0; i < k; ++i) {
+    T[(size_t)i * k + i] = alpha[i];
+    if (i + 1 < k) T[(size_t)i * k + i + 1] = T[(size_t)(i + 1) * k + i] = beta[i];
+  }
+  jacobi_eigen(T, k, &ev, &V);
+  const double blast = beta.empty() ? 0.0 : beta.back();
+  const double res_lo = std::fabs(blast * V[(size_t)(k - 1) * k + 0]);
+  const double res_hi = std::fabs(blast * V[(size_t)(k - 1) * k + (k - 1)]);
+  const double lo = ev.front(), hi = ev.back();
+  const double pad = 0.05 * (hi - lo);
+  *emin = lo - std::max(pad, res_lo) - pad;
+  *emax = hi + std::max(pad, res_hi) + pad;
+  return SG_OK;
+}
+
+sg_status sg_vibronic_propagate(sg_vibronic *v, void *psi, double dt, int32_t nsteps,
+                                double emin, double emax, double tol, int32_t check_every,
+                                sg_prop_stats *stats, double *pop_trace, void *stream) {
+  if (!v || !psi) return fail(SG_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt) || nsteps < 0 || check_every < 0)
+    return fail(SG_EINVAL, "dt must be > 0, nsteps and check_every >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  if (std::isnan(emin) || std::isnan(emax)) {
+    sg_status st = sg_vibronic_bounds(v, 40, &emin, &emax, stream);
+    if (st != SG_OK) return st;
+  }
+  if (!(emax > emin)) return fail(SG_EINVAL, "emax must exceed emin");
+  sg_problem *p = v->p;
+  const int64_t ncs = p->h.ncs, n = 2 * ncs;
+  const double half = 0.5 * (emax - emin), ebar = 0.5 * (emax + emin);
+  std::vector<double> a;
+  const int K = chebyshev_series(half * dt, &a);
+  if (K < 2 || K > kMaxChebTerms) return fail(SG_EINVAL, "Chebyshev series length out of range");
+  hipError_t e = hipMemcpyAsync(p->d_cheb_a, a.data(), K * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "upload series");
+  for (int st = 0; st < 2; ++st) {
+    InstDev &I = v->plan.inst[st];
+    I.K = K;
+    I.ebar = ebar;
+    I.inv_half = 1.0 / half;
+    I.phase_re = std::cos(-ebar * dt);
+    I.phase_im = std::sin(-ebar * dt);
+    I.active = 1;
+  }
+  sg_status r0 = plan_upload_inst(&v->plan, s);
+  if (r0 != SG_OK) return r0;
+  double2 *x0 = (double2 *)psi, *x1 = v->d_work + 6 * (size_t)ncs;   // phi buffers
+  sg_prop_stats st{};
+  st.cheb_terms = K;
+  st.emin = emin;
+  st.emax = emax;
+  int ntrace = 0;
+  bool have0 = false;
+  sg_status ret = SG_OK;
+  auto record = [&](double nrm2, double ene) -> sg_status {
+    const double nrm = std::sqrt(nrm2), E = ene / nrm2;
+    if (!have0) {
+      st.norm0 = nrm;
+      st.energy0 = E;
+      have0 = true;
+    }
+    st.norm_last = nrm;
+    st.energy_last = E;
+    st.max_norm_drift = std::max(st.max_norm_drift, std::fabs(nrm - st.norm0));
+    st.max_energy_drift = std::max(st.max_energy_drift, std::fabs(E - st.energy0));
+    if (pop_trace) {
+      // population of state 1 (upper state)
+      hipError_t ee = vdot(v, x0 + ncs, x0 + ncs, ncs, 4, s);
+      if (ee != hipSuccess) return hip_fail(ee, "dot");
+      double rr[6];
+      sg_status rs = read_res(v, s, 6, rr);
+      if (rs != SG_OK) return rs;
+      pop_trace[ntrace] = rr[4] / nrm2;
+    }
+    ++ntrace;
+    if (tol > 0.0 && std::fabs(nrm - st.norm0) > tol) ret = SG_ETOL;
+    return SG_OK;
+  };
+  LaunchCtl c;
+  c.mode = Mode::Cheb;
+  c.prec = SG_FP64;
+  c.x0o = x0;
+  c.x1o = x1;
+  for (int step = 0; step < nsteps; ++step) {
+    const bool check = step == 0 || (check_every > 0 && step % check_every == 0);
+    for (int k = 1; k < K; ++k) {
+      c.k = k;
+      c.want_partials = (k == 1 && check) ? 1 : 0;
+      const double2 *vin = ((k - 1) & 1) ? x1 : x0;   // phi_{k-1}
+      if ((e = run_vib_sweep(p, v->vl, vin, v->d_tm, s)) != hipSuccess) return hip_fail(e, "sweep");
+      if ((e = run_reduce(p, &v->plan, c, s)) != hipSuccess) return hip_fail(e, "reduce");
+      if (k == 1 && check) {
+        if ((e = launch_finalize(&v->plan, s)) != hipSuccess) return hip_fail(e, "finalize");
+        double rr[4];
+        sg_status rs = read_res(v, s, 4, rr);
+        if (rs != SG_OK) return rs;
+        // the check reads psi = phi_0, which the recurrence still holds at k = 1
+        if ((rs = record(rr[0] + rr[2], rr[1] + rr[3])) != SG_OK) return rs;
+      }
+    }
+    st.applies += K - 1;
+    st.steps_done = step + 1;
+    if (ret != SG_OK) break;
+  }
+  if (ret == SG_OK) {
+    double2 *w = v->d_work + 4 * (size_t)ncs;   // the accumulator is free after a step
+    sg_status as = sg_vibronic_apply(v, x0, w, stream);
+    if (as != SG_OK) return as;
+    double rr[4];
+    if ((e = vdot(v, x0, x0, n, 0, s)) != hipSuccess) return hip_fail(e, "dot");
+    if ((e = vdot(v, x0, w, n, 2, s)) != hipSuccess) return hip_fail(e, "dot");
+    if ((as = read_res(v, s, 4, rr)) != SG_OK) return as;
+    if ((as = record(rr[0], rr[2])) != SG_OK) return as;
+    st.applies += 1;
+  }
+  if (stats) *stats = st;
+  if (ret == SG_ETOL) return fail(SG_ETOL, "norm drift beyond tolerance: spectral bounds too tight?");
+  return ret;
+}
+
+}  // extern "C"

@@ -83,6 +83,43 @@ def test_batch_bitwise_equal_to_alone(use_graph):
         assert abs(stats[i]["norm_last"] - 1.0) < 1e-12
 
 
+def test_batch_schedule_tuner_keeps_results_bitwise():
+    """The batch schedule autotuner over the union of the instances' terms:
+    every candidate schedule gives bitwise the same apply (the tuner checks
+    that itself), the chosen one is a candidate, and a propagation after the
+    tuning is still bitwise the alone result."""
+    sg = _sg()
+    insts = _mix()[:5]
+    say("batch schedule tuner")
+    probs = [sg.Problem.from_instance(i) for i in insts]
+    try:
+        bounds = [sg.sg_spectral_bounds(P.handle, 40) for P in probs]
+        psis = []
+        for P, inst in zip(probs, insts):
+            x = empty(P.n_cs)
+            sg.sg_init_gaussian(P.handle, inst.shift, x)
+            psis.append(x)
+        b = sg.sg_batch_create([P.handle for P in probs])
+        try:
+            g, ms = sg.sg_batch_tune_schedule(b, psis, sg.SG_FP64, reps=2)
+            max_grid = max(P.info["max_term_grid"] for P in probs)
+            assert g == 0 or (g >= 256 and g <= max_grid and (g & (g - 1)) == 0)
+            assert ms > 0.0
+            status, _ = sg.sg_batch_propagate(
+                b, psis, [0.05] * len(insts), 4, [lo for lo, _ in bounds],
+                [hi for _, hi in bounds])
+        finally:
+            sg.sg_batch_free(b)
+        assert status == sg.SG_OK
+        outs = [to_host(x) for x in psis]
+    finally:
+        for P in probs:
+            P.close()
+    for i, inst in enumerate(insts):
+        ref, _ = _alone(sg, inst, 0.05, 4, bounds[i][0], bounds[i][1], sg.SG_FP64)
+        assert np.array_equal(outs[i], ref), i
+
+
 def test_batch_mixed_precision_bitwise_equal_to_alone():
     sg = _sg()
     insts = _mix()[:5]
