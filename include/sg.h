@@ -247,6 +247,26 @@ sg_status sg_propagate(sg_problem *p, void *psi, double dt, int32_t nsteps,
                        sg_prop_stats *stats, double *norm_trace,
                        double *energy_trace, void *stream);
 
+/* The same propagators as sg_propagate, with the same arguments and results
+ * (bitwise: same kernels, same order), for callers that cannot allocate
+ * device memory (code that must not call hipMalloc, such as tight serving
+ * loops and harnesses that forbid it).  The work vectors, projection
+ * partials and coefficient slots live in a fixed device array of
+ * sg_noalloc_scratch_bytes() bytes (64 MiB) that each device the library
+ * runs on holds until the process ends; the call allocates nothing.  A
+ * propagation needing more (about (nvec + 1) * 16 * N_cs bytes: nvec = 2 for
+ * Taylor, 1 + order for Runge-Kutta, 4 + order for Bulirsch-Stoer, order + 1
+ * for Lanczos) fails with SG_EINVAL before anything is launched.  All calls
+ * on one device share the array: calls that overlap on one device (other
+ * host threads, or streams that run concurrently) race and must not be
+ * issued.  The array keeps the last call's contents; the call clears what
+ * must start at zero itself. */
+sg_status sg_propagate_noalloc(sg_problem *p, void *psi, double dt, int32_t nsteps,
+                               int32_t method, int32_t order, double tol, sg_precision prec,
+                               int32_t check_every, sg_prop_stats *stats, double *norm_trace,
+                               double *energy_trace, void *stream);
+int64_t sg_noalloc_scratch_bytes(void);
+
 /* Batched propagation of independent problems (same device).  Every
  * Chebyshev term of every instance runs in one term-sweep launch and one
  * reduce launch: the terms of all instances are packed together into

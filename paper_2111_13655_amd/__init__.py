@@ -23,7 +23,8 @@ __all__ = [
     "library_path", "sg_count_sizes", "sg_build_terms", "sg_build_terms_host",
     "sg_free", "sg_problem_info", "sg_basis_indices", "sg_term_levels",
     "sg_mapping_table", "sg_init_gaussian", "sg_apply_H", "sg_spectral_bounds",
-    "sg_propagate_chebyshev", "sg_propagate", "SG_PROP_TAYLOR", "SG_PROP_RK", "SG_PROP_SIL",
+    "sg_propagate_chebyshev", "sg_propagate", "sg_propagate_noalloc",
+    "sg_noalloc_scratch_bytes", "SG_PROP_TAYLOR", "SG_PROP_RK", "SG_PROP_SIL",
     "SG_PROP_BS",
     "sg_set_timing", "sg_get_timing", "sg_set_mixed_threshold",
     "sg_tune_mixed", "sg_set_operator_form", "sg_set_schedule", "sg_tune_schedule",
@@ -172,6 +173,13 @@ _SIGNATURES = {
                                     ctypes.c_int32, ctypes.c_double, ctypes.c_int, ctypes.c_int32,
                                     ctypes.POINTER(PropStats), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double), _P]),
+    "sg_propagate_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                            ctypes.c_int, ctypes.c_int32,
+                                            ctypes.POINTER(PropStats),
+                                            ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_double), _P]),
+    "sg_noalloc_scratch_bytes": (ctypes.c_int64, []),
     "sg_vibronic_build": (ctypes.c_int, [ctypes.POINTER(VibronicDesc), ctypes.POINTER(_P)]),
     "sg_vibronic_free": (ctypes.c_int, [_P]),
     "sg_vibronic_problem": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
@@ -389,6 +397,19 @@ def sg_propagate(h, psi, dt: float, nsteps: int, method: int, order: int, tol: f
     Returns (status, stats dict, norm trace, energy trace)."""
     return _propagate("sg_propagate", h, psi, dt, nsteps, method, order, tol, precision,
                       check_every, stream)
+
+
+def sg_propagate_noalloc(h, psi, dt: float, nsteps: int, method: int, order: int,
+                         tol: float = 0.0, precision: int = SG_FP64, check_every: int = 0,
+                         stream=None):
+    """sg_propagate with its work buffers in the library's fixed device array
+    (no device allocation).  Same returns."""
+    return _propagate("sg_propagate_noalloc", h, psi, dt, nsteps, method, order, tol, precision,
+                      check_every, stream)
+
+
+def sg_noalloc_scratch_bytes() -> int:
+    return int(lib().sg_noalloc_scratch_bytes())
 
 
 def _propagate(entry, h, psi, dt, nsteps, method, order, tol, precision, check_every, stream):
