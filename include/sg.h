@@ -443,11 +443,14 @@ sg_status sg_set_operator_form(sg_problem *p, int32_t grid_kinetic);
 sg_status sg_tune_mixed(sg_problem *p, const void *psi, double tol, int32_t reps,
                         int32_t *chosen, double *chosen_error, void *stream);
 
-/* Term-to-workgroup schedule.  A term whose in-place contractions fit the
- * registers of one wavefront runs on one (up to eight such terms share a
- * workgroup), unless block_min_grid > 0 and the term has at least that many
- * grid points: then it runs on a whole workgroup (0, the default, never
- * forces one).  When there are fewer wave terms than compute units can take,
+/* Term-to-workgroup schedule.  An in-place term of at most 4096 grid points
+ * can run on one wavefront (up to eight such terms share a workgroup; a
+ * contraction over more fibers than the lanes hold runs in chunks), unless
+ * it has at least block_min_grid grid points: then it runs on a whole
+ * workgroup.  block_min_grid = 0 (the default) picks the threshold from the
+ * problem's size: 1025 for a problem of fewer than 1024 terms (the launch
+ * then lasts as long as its longest term chain), else 4096 (many terms:
+ * throughput-bound).  When there are fewer wave terms than compute units can take,
  * they are spread over packs_per_cu workgroups per compute unit (1, the
  * default, .. 4; at most as many as fit a CU).  The schedule decides only
  * which threads compute a term; every schedule gives bitwise the same

@@ -98,7 +98,6 @@ void release(sg_problem *p) {
   hipFree(p->d_work);
   hipFree(p->d_partials);
   hipFree(p->d_abc);
-  hipFree(p->d_rpart);
   hipFree(p->d_cheb_a);
   hipFree(p->d_result);
   if (p->h_result) hipHostFree(p->h_result);
@@ -220,9 +219,6 @@ sg_status upload_problem(sg_problem *p, sg_problem **out) {
   bytes += (int64_t)work_bytes;
   const int64_t npart = std::max<int64_t>(h.n_items, 256);
   e = hipMalloc((void **)&p->d_partials, 2 * (size_t)npart * sizeof(double));
-  if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
-  bytes += 2 * npart * (int64_t)sizeof(double);
-  e = hipMalloc((void **)&p->d_rpart, 2 * (size_t)npart * sizeof(double));
   if (e != hipSuccess) { release(p); return fail(SG_ENOMEM, "device allocation failed"); }
   bytes += 2 * npart * (int64_t)sizeof(double);
   e = hipMalloc((void **)&p->d_cheb_a, kMaxChebTerms * sizeof(double));

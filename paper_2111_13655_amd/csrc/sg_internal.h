@@ -115,7 +115,6 @@ struct InstDev {
   double2 *x0, *x1;         // apply: x0 -> x1.  Chebyshev: phi buffers, x0 = psi
   double2 *acc;             // Chebyshev running sum
   double *partials;         // [2 * nitems] norm / energy partial sums
-  double *rpart;            // [2 * nitems] chunk sums of long rows of several chunks
   double *result;           // [2] finalised sums
   const double *cheb_a;     // [K] series coefficients (2 - delta_k0) J_k(R)
   int64_t ncs;
@@ -145,6 +144,9 @@ constexpr int kPackTerms = 8;
 constexpr int kLdsPerCU = 160 * 1024;
 constexpr int kComputeUnits = 256;   // MI355X; used to size the packing only
 constexpr int kPingPongWaveMaxGrid = 512;
+// Largest in-place term a single wavefront runs (its contractions in chunks
+// of inplace_fpt(NI) fibers per lane when the fibers exceed the lanes).
+constexpr int kWaveMaxGrid = 4096;
 // Fibers of NI values one thread holds in an in-place contraction.
 __host__ __device__ constexpr int inplace_fpt(int ni) { return ni <= 18 ? 18 / ni : 1; }
 enum PackKind : int32_t { kPackWaves = 0, kPackBlockLds = 1, kPackBlockScratch = 2 };
@@ -182,29 +184,20 @@ enum PackSetId { kSetGrid64 = 0, kSetSplit64 = 1, kSetMixed64 = 2, kSetMixed32 =
 // Rows of the inverse mapping longer than this are reduced by a whole
 // wavefront, shorter ones by a group of 8 lanes.
 constexpr int kLongRow = 64;
-// Long rows are summed in chunks of at most kRowChunk entries, one workgroup
-// of kRowWaves wavefronts each (kRowChunk / kRowWaves entries per wavefront,
-// combined through LDS in wavefront order); a row of several chunks is
-// finished by the last chunk to arrive, which adds the chunk sums in chunk
-// order.
+// A long row is summed by one workgroup of kRowWaves wavefronts: wavefront w
+// takes the w-th of kRowWaves consecutive runs of the row's entries (runs of
+// at least kRowRun entries), and the run sums are added in wavefront order
+// through LDS.  Long rows come first in the reduce order, so the longest
+// (the ground function takes one contribution from every term) start first.
 constexpr int kRowWaves = 4;
-constexpr int kRowChunk = 1024;
+constexpr int kRowRun = 256;
 constexpr int kShortLanes = 8;
-// A long row of several chunks: its chunks leave their sums in rpart (at
-// first_slot + kRowWaves c for chunk c), and a second kernel adds them in
-// chunk order and runs the row's epilogue.
-struct FinItem {
-  int32_t inst;
-  int32_t row;          // compact row
-  int32_t first_slot;   // reduce-item slot of the row's chunk 0
-  int32_t nch;          // chunks
-};
 // One reduce work item = one wavefront: a long row, or 8 short rows.
 struct RedItem {
   int32_t inst;
   int32_t first;    // index into the instance's row list
   int32_t local;    // item index inside the instance (partial-sum slot)
-  int32_t chunk;    // long rows: chunk | (chunks << 12) | (wavefront << 24);
+  int32_t chunk;    // long rows: 1 << 12 | (wavefront << 24);
                     // short rows: how many of the item's rows exist (0 for padding)
   const int32_t *rows;  // the instance's row list and row bounds at `first`
   const int32_t *ptr;   // (device), so that they load without the instance record
@@ -287,7 +280,6 @@ struct PackCache {
   int32_t pack_lds[kPackSets] = {0, 0, 0, 0};   // largest pack, tables excluded
   int64_t scratch[kPackSets] = {0, 0, 0, 0};    // scratch bytes of each set
   std::vector<RedItem> items;              // inst = 0
-  std::vector<FinItem> fin;                // inst = 0
   bool inst32 = false;
 };
 }  // namespace sg
@@ -314,7 +306,6 @@ struct sg_problem {
   double2 *d_tm = nullptr;         // term-major results [N_s]
   double2 *d_work = nullptr;       // 4 * N_cs: Chebyshev phi, ACC, spares
   double *d_partials = nullptr;    // [2 * n_items] reduction partials
-  double *d_rpart = nullptr;       // [2 * n_items] chunk sums of long rows
   double *d_cheb_a = nullptr;      // [kMaxChebTerms] series coefficients
   int grid_kinetic = 0;            // 1: SG_FP64 applies the kinetic matrices on the grid
   int32_t block_grid = 0;          // > 0: terms of at least this many grid points run on a
@@ -349,15 +340,12 @@ struct Plan {
   std::vector<PackDev> packs;
   PackSet sets[kPackSets];
   std::vector<RedItem> items;
-  std::vector<FinItem> fin;        // long rows of several chunks
   InstDev *d_inst = nullptr;
   PackDev *d_packs = nullptr;
   RedItem *d_items = nullptr;
-  FinItem *d_fin = nullptr;
   char *d_scratch = nullptr;
   int64_t scratch_bytes = 0;
-  int64_t packs_capacity = 0, items_capacity = 0, inst_capacity = 0, scratch_capacity = 0,
-          fin_capacity = 0;
+  int64_t packs_capacity = 0, items_capacity = 0, inst_capacity = 0, scratch_capacity = 0;
   bool any32 = false;              // some term of some instance runs in FP32
   bool fp64_split = false;         // SG_FP64 launches use the split form
   bool any_round32 = false;        // some instance's FP64 terms use rounded tables

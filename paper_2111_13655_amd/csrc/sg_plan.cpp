@@ -2,9 +2,9 @@
 //
 // Packing (the term -> workgroup schedule).  Each term gets the smallest
 // group that runs it well:
-//   * one wavefront, when every contraction of the term has at most
-//     inplace_fpt(NI) fibers per lane (in-place form) or the term is small
-//     (ping-pong form);
+//   * one wavefront, for in-place terms of at most kWaveMaxGrid points (a
+//     contraction over more fibers than the lanes hold runs in chunks) and
+//     for small ping-pong terms;
 //   * the four wavefronts of a workgroup otherwise, with its buffer in LDS
 //     when it fits under the per-workgroup cap, else in global scratch.
 // Wave terms are dealt, most expensive first, to the least loaded of enough
@@ -13,8 +13,8 @@
 // computed by the same code whatever its pack, so results do not depend on
 // the mix.
 //
-// Reduce items (one per wavefront): a workgroup's worth per chunk of a long
-// row, one per eight short rows, in each instance's row order, padded to
+// Reduce items (one per wavefront): a workgroup's worth per long row, one per
+// eight short rows, in each instance's row order, padded to
 // whole workgroups; an item's partial sums go to its own slot so that the
 // per-instance norm / energy sums run in a fixed order.
 #include <algorithm>
@@ -59,6 +59,19 @@ bool inplace_fits(const TermDev &T, int n) {
   return true;
 }
 
+// The schedule knob in effect for a problem: its own setting, or by default
+// (0) a threshold from the problem's size.  A launch over few terms lasts as
+// long as its longest term chain, so there terms above 1024 points run on a
+// whole workgroup; a launch over many terms is bound by throughput, where a
+// wavefront per term (no workgroup barriers, more terms in flight per
+// compute unit) wins for terms up to 2048 points and 4096-point terms stay on
+// workgroups.  Plans over several problems always hold many terms.
+int32_t effective_block_grid(const sg_problem *p, bool multi) {
+  if (p->block_grid > 0) return p->block_grid;
+  if (!multi && p->h.nterms < 4 * kComputeUnits) return 1025;
+  return 4096;
+}
+
 // One candidate per term of a pack set.  split: the set applies the split
 // operator (no kinetic contractions, so the in-place form applies to the
 // standard size maps); elem: bytes of one complex value.
@@ -77,7 +90,9 @@ Cand make_cand(int32_t inst, int32_t term, const Compiled &h, bool split, int el
   } else if (split && std_maps && inplace_fits(T, kSweepThreads)) {
     c.inplace = 1;
     c.slice = one + kCoefLdsBytes;
-    c.wave = inplace_fits(T, 64) && !(block_grid > 0 && T.ngrid >= block_grid) ? 1 : 0;
+    // a wavefront runs any in-place term up to kWaveMaxGrid points, in chunks
+    // of the fibers its registers hold when one pass does not fit
+    c.wave = T.ngrid <= kWaveMaxGrid && !(block_grid > 0 && T.ngrid >= block_grid) ? 1 : 0;
   } else {
     c.inplace = 0;
     c.slice = 2 * one;
@@ -263,7 +278,6 @@ void inst_from_problem(const sg_problem *p, InstDev *d) {
   d->partials = p->d_partials;
   d->abc = p->d_abc;
   d->nfib = p->h.nfib;
-  d->rpart = p->d_rpart;
   d->result = p->d_result;
   d->cheb_a = p->d_cheb_a;
   d->ncs = h.ncs;
@@ -284,20 +298,14 @@ namespace {
 constexpr int kTabMax64 = ((std_table_base(8) * 8 + 15) / 16) * 16;
 constexpr int kTabMax32 = ((std_table_base(8) * 4 + 15) / 16) * 16;
 
-void reduce_items(const sg_problem *p, int32_t inst, std::vector<RedItem> *items,
-                  std::vector<FinItem> *fin) {
+void reduce_items(const sg_problem *p, int32_t inst, std::vector<RedItem> *items) {
   const Compiled &h = p->h;
   auto at = [&](int64_t q, const int32_t *base) { return base ? base + q : nullptr; };
   int32_t local = 0;
-  for (int64_t q = 0; q < h.n_long_rows; ++q) {
-    const int64_t len = h.red_ptr[q + 1] - h.red_ptr[q];
-    const int32_t nch = (int32_t)((len + kRowChunk - 1) / kRowChunk);
-    if (nch > 1) fin->push_back({inst, h.rows[q], local, nch});
-    for (int32_t c = 0; c < nch; ++c)
-      for (int32_t w = 0; w < kRowWaves; ++w)
-        items->push_back({inst, (int32_t)q, local++, c | (nch << 12) | (w << 24),
-                          at(q, p->d_rows), at(q, p->d_inv_ptr)});
-  }
+  for (int64_t q = 0; q < h.n_long_rows; ++q)
+    for (int32_t w = 0; w < kRowWaves; ++w)
+      items->push_back({inst, (int32_t)q, local++, (1 << 12) | (w << 24), at(q, p->d_rows),
+                        at(q, p->d_inv_ptr)});
   const int64_t nshort = h.ncs - h.n_long_rows;
   for (int64_t q = 0; q < nshort; q += kShortLanes) {
     const int64_t first = h.n_long_rows + q;
@@ -318,13 +326,14 @@ void build_cache(sg_problem *p) {
   std::vector<Cand> cg64, cs64, m64, m32;
   c.inst32 = false;
   for (int64_t t = 0; t < h.nterms; ++t) {
-    cg64.push_back(make_cand(0, (int32_t)t, h, false, 16, p->d_mb, p->block_grid));
-    cs64.push_back(make_cand(0, (int32_t)t, h, true, 16, p->d_mb, p->block_grid));
+    const int32_t bg = effective_block_grid(p, true);
+    cg64.push_back(make_cand(0, (int32_t)t, h, false, 16, p->d_mb, bg));
+    cs64.push_back(make_cand(0, (int32_t)t, h, true, 16, p->d_mb, bg));
     if (std::abs(h.coeff[t]) <= h.mixed_max_fp32_coeff) {
-      m32.push_back(make_cand(0, (int32_t)t, h, true, 8, p->d_mb, p->block_grid));
+      m32.push_back(make_cand(0, (int32_t)t, h, true, 8, p->d_mb, bg));
       c.inst32 = true;
     } else {
-      m64.push_back(make_cand(0, (int32_t)t, h, true, 16, p->d_mb, p->block_grid));
+      m64.push_back(make_cand(0, (int32_t)t, h, true, 16, p->d_mb, bg));
     }
   }
   const std::vector<Cand> *cs[kPackSets] = {&cg64, &cs64, &m64, &m32};
@@ -339,8 +348,7 @@ void build_cache(sg_problem *p) {
     c.pack_lds[k] = ps.count ? ps.lds_bytes - ps.tab_bytes : 0;
   }
   c.items.clear();
-  c.fin.clear();
-  reduce_items(p, 0, &c.items, &c.fin);
+  reduce_items(p, 0, &c.items);
   c.thr = h.mixed_max_fp32_coeff;
   c.grid_kinetic = p->grid_kinetic;
   c.block_grid = p->block_grid;
@@ -370,7 +378,6 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
   pl->inst.assign(probs.size(), InstDev{});
   pl->packs.clear();
   pl->items.clear();
-  pl->fin.clear();
   pl->scratch_bytes = 0;
   pl->any32 = false;
   pl->fp64_split = false;
@@ -389,21 +396,19 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
       const size_t first = pl->items.size();
       pl->items.insert(pl->items.end(), p->pcache.items.begin(), p->pcache.items.end());
       for (size_t q = first; q < pl->items.size(); ++q) pl->items[q].inst = (int32_t)i;
-      const size_t ffirst = pl->fin.size();
-      pl->fin.insert(pl->fin.end(), p->pcache.fin.begin(), p->pcache.fin.end());
-      for (size_t q = ffirst; q < pl->fin.size(); ++q) pl->fin[q].inst = (int32_t)i;
     } else {
       for (int64_t t = 0; t < h.nterms; ++t) {
-        cg64.push_back(make_cand((int32_t)i, (int32_t)t, h, false, 16, p->d_mb, p->block_grid));
-        cs64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16, p->d_mb, p->block_grid));
+        const int32_t bg = effective_block_grid(p, false);
+        cg64.push_back(make_cand((int32_t)i, (int32_t)t, h, false, 16, p->d_mb, bg));
+        cs64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16, p->d_mb, bg));
         if (std::abs(h.coeff[t]) <= h.mixed_max_fp32_coeff) {
-          m32.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 8, p->d_mb, p->block_grid));
+          m32.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 8, p->d_mb, bg));
           inst32 = true;
         } else {
-          m64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16, p->d_mb, p->block_grid));
+          m64.push_back(make_cand((int32_t)i, (int32_t)t, h, true, 16, p->d_mb, bg));
         }
       }
-      reduce_items(p, (int32_t)i, &pl->items, &pl->fin);
+      reduce_items(p, (int32_t)i, &pl->items);
     }
     pl->inst[i].round32 = inst32 ? 1 : 0;
     pl->any32 = pl->any32 || inst32;
@@ -509,12 +514,7 @@ sg_status plan_upload(Plan *pl, hipStream_t s) {
     return fail(SG_ENOMEM, "device allocation of reduce items failed");
   if ((e = ensure(&pl->d_scratch, &pl->scratch_capacity, pl->scratch_bytes, nullptr)) != hipSuccess)
     return fail(SG_ENOMEM, "device allocation of sweep scratch failed");
-  if ((e = ensure(&pl->d_fin, &pl->fin_capacity, (int64_t)pl->fin.size(), nullptr)) != hipSuccess)
-    return fail(SG_ENOMEM, "device allocation of long-row items failed");
-  if (!pl->fin.empty() &&
-      (e = hipMemcpyAsync(pl->d_fin, pl->fin.data(), pl->fin.size() * sizeof(FinItem),
-                          hipMemcpyHostToDevice, s)) != hipSuccess)
-    return hip_fail(e, "upload long-row items");
+
   if (!pl->packs.empty() &&
       (e = hipMemcpyAsync(pl->d_packs, pl->packs.data(), pl->packs.size() * sizeof(PackDev),
                           hipMemcpyHostToDevice, s)) != hipSuccess)
@@ -565,7 +565,6 @@ void plan_free(Plan *pl) {
   hipFree(pl->d_inst);
   hipFree(pl->d_packs);
   hipFree(pl->d_items);
-  hipFree(pl->d_fin);
   hipFree(pl->d_scratch);
   hipFree(pl->d_stab64);
   hipFree(pl->d_stab32r);
@@ -576,10 +575,8 @@ void plan_free(Plan *pl) {
   pl->d_inst = nullptr;
   pl->d_packs = nullptr;
   pl->d_items = nullptr;
-  pl->d_fin = nullptr;
   pl->d_scratch = nullptr;
   pl->inst_capacity = pl->packs_capacity = pl->items_capacity = pl->scratch_capacity = 0;
-  pl->fin_capacity = 0;
 }
 
 }  // namespace sg

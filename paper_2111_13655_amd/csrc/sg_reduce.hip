@@ -192,20 +192,20 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
   const glb_p<const int32_t> col = (glb_p<const int32_t>)I->inv_col;
   double pn = 0.0, pe = 0.0;
   if (nch) {
-    // one chunk of a long row on the whole workgroup: wavefront `sub` sums
-    // its share, the shares are added in wavefront order through LDS
+    // a long row on the whole workgroup: wavefront `sub` sums the sub-th of
+    // kRowWaves consecutive runs of its entries, the run sums are added in
+    // wavefront order through LDS
     __shared__ double wsum[2][kRowWaves];
-    const int c = chunk & 0xfff, sub = chunk >> 24;
+    const int sub = chunk >> 24;
     row = lrow;
     b = lb;
     e = le;
     RowIn in{};
-    if (sub == 0 && nch == 1) in = row_inputs(a, I, row);
-    const int cb = b + c * kRowChunk + sub * (kRowChunk / kRowWaves);
+    if (sub == 0) in = row_inputs(a, I, row);
+    const int run = max(kRowRun, (e - b + kRowWaves - 1) / kRowWaves);
+    const int cb = min(e, b + sub * run);
     double sr = 0.0, si = 0.0;
-    strided_sum<64, kRowChunk / kRowWaves / 64>(col, tm, cb,
-                                                 min(e, cb + kRowChunk / kRowWaves), lane, &sr,
-                                                 &si);
+    strided_sum<64, 8>(col, tm, cb, min(e, cb + run), lane, &sr, &si);
     sr = group_sum<64>(sr);
     si = group_sum<64>(si);
     if (lane == 0) {
@@ -213,9 +213,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
       wsum[1][sub] = si;
     }
     __syncthreads();
-    if (sub != 0) {
-      pn = pe = 0.0;     // clears its partial slot
-    } else {
+    if (sub == 0) {
       sr = wsum[0][0];
       si = wsum[1][0];
 #pragma unroll
@@ -223,21 +221,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
         sr += wsum[0][w];
         si += wsum[1][w];
       }
-      if (nch == 1) {
-        if (lane == 0) row_epilogue(a, I, row, in, sr, si, &pn, &pe);
-      } else {
-        // a row of several chunks: leave this chunk's sum in its slot; the
-        // finish kernel, launched after this one on the same stream, adds
-        // the chunk sums in chunk order (the kernel boundary orders the
-        // stores before its loads) and runs the row's epilogue.  This
-        // chunk's norm / energy slot is cleared here; the finish kernel
-        // fills chunk 0's.
-        if (lane == 0) {
-          I->rpart[2 * it->local] = sr;
-          I->rpart[2 * it->local + 1] = si;
-        }
-        pn = pe = 0.0;
-      }
+      if (lane == 0) row_epilogue(a, I, row, in, sr, si, &pn, &pe);
     }
   } else {
     const int sub = lane % kShortLanes;
@@ -258,30 +242,6 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
       I->partials[2 * it->local] = pn;
       I->partials[2 * it->local + 1] = pe;
     }
-  }
-}
-
-// Long rows of several chunks: one lane per row adds its chunk sums in chunk
-// order, then runs the row's epilogue; the row's norm / energy partials go
-// to its chunk-0 slot.
-__global__ __launch_bounds__(64) void finish_kernel(ReduceArgs a, const FinItem *fin, int nfin) {
-  const int f = blockIdx.x * 64 + threadIdx.x;
-  if (f >= nfin) return;
-  const FinItem it = fin[f];
-  const cptr<InstDev> I = a.inst + it.inst;
-  if (I->active == 0 || (a.mode == 1 && a.k > I->K - 1)) return;
-  const RowIn in = row_inputs(a, I, it.row);
-  double sr = 0.0, si = 0.0;
-  for (int c = 0; c < it.nch; ++c) {
-    const int sl = it.first_slot + kRowWaves * c;
-    sr += I->rpart[2 * sl];
-    si += I->rpart[2 * sl + 1];
-  }
-  double pn = 0.0, pe = 0.0;
-  row_epilogue(a, I, it.row, in, sr, si, &pn, &pe);
-  if (a.mode == 1 && a.k == 1 && a.want_partials) {
-    I->partials[2 * it.first_slot] = pn;
-    I->partials[2 * it.first_slot + 1] = pe;
   }
 }
 
@@ -400,22 +360,11 @@ hipError_t launch_reduce(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
   a.split = split_form(pl, c.prec) ? 1 : 0;
   const int64_t blocks = (a.nitems + (kRedThreads / 64) - 1) / (kRedThreads / 64);
   if (blocks == 0) return hipSuccess;
-  const int nfin = (int)pl->fin.size();
-  hipEvent_t end_reduce = nfin > 0 ? nullptr : c.ev1;
-  if (c.ev0 || end_reduce)
+  if (c.ev0 || c.ev1)
     hipExtLaunchKernelGGL(reduce_kernel, dim3((unsigned)blocks), dim3(kRedThreads), 0, s, c.ev0,
-                          end_reduce, 0, a);
+                          c.ev1, 0, a);
   else
     hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)blocks), dim3(kRedThreads), 0, s, a);
-  if (nfin > 0) {
-    const unsigned fb = (unsigned)((nfin + 63) / 64);
-    if (c.ev1)
-      hipExtLaunchKernelGGL(finish_kernel, dim3(fb), dim3(64), 0, s, nullptr, c.ev1, 0, a,
-                            (const FinItem *)pl->d_fin, nfin);
-    else
-      hipLaunchKernelGGL(finish_kernel, dim3(fb), dim3(64), 0, s, a, (const FinItem *)pl->d_fin,
-                         nfin);
-  }
   return hipGetLastError();
 }
 

@@ -957,23 +957,39 @@ struct Rows {
   }
 };
 
+// Chunks of an in-place contraction over more fibers than the group holds
+// at once (FPT fibers per thread): each chunk loads all its input fibers,
+// syncs the group, then writes its outputs.  A compacting contraction (fewer
+// outputs than inputs per fiber) visits its chunks in increasing fiber order
+// and an expanding one in decreasing order; then a chunk's outputs never
+// land on inputs of a chunk not yet read.  (Fiber f = lo + stride hi reads
+// in[lo + stride (k + NI hi)] and writes out[lo + stride (u + NO hi)];
+// positions of two fibers coincide only for the same lo, where NO < NI puts
+// every output of hi below the inputs of any later hi' > hi, and NO > NI puts
+// them above the inputs of any earlier hi' < hi.)  A chunk's results do not
+// depend on the chunking: every output is the same FMA chain.
+__device__ __forceinline__ int chunk_index(int cc, int nch, bool compacting) {
+  return compacting ? cc : nch - 1 - cc;
+}
+
+// One chunk of an in-place contraction: fibers base + tid + j N (j < FPT).
 template <typename G, typename R, int NI, int NO>
-__device__ __forceinline__ void contract_ip(lds_p<typename Cx<R>::T> buf, lds_p<const R> M,
-                                            int stride, int nouter) {
+__device__ __forceinline__ void contract_ip_chunk(lds_p<typename Cx<R>::T> buf,
+                                                  lds_p<const R> M, int stride, int F,
+                                                  int base) {
   typedef typename Cx<R>::T C;
   constexpr int FPT = inplace_fpt(NI);
-  const int F = stride * nouter;
   const float rcp = 1.0f / (float)stride;
   const int sNI = stride * NI, sNO = stride * NO;
-  // fiber slots this contraction needs (wave-uniform)
-  const int nj = min(FPT, (F + G::N - 1) / G::N);
+  // fiber slots this chunk needs (wave-uniform)
+  const int nj = min(FPT, (F - base + G::N - 1) / G::N);
   int ob[FPT];
   bool ok[FPT];
   C x[FPT][NI];
 #pragma unroll
   for (int j = 0; j < FPT; ++j) {
     if (j >= nj) break;
-    int f = G::tid() + j * G::N;
+    int f = base + G::tid() + j * G::N;
     ok[j] = f < F;
     f = ok[j] ? f : 0;
     const int hi = fdiv(f, rcp);
@@ -995,6 +1011,24 @@ __device__ __forceinline__ void contract_ip(lds_p<typename Cx<R>::T> buf, lds_p<
     }
     if (ok[j]) stc(buf + ob[j] + u * stride, Cx<R>::make(re, im));
   });
+}
+
+template <typename G, typename R, int NI, int NO>
+__device__ __forceinline__ void contract_ip(lds_p<typename Cx<R>::T> buf, lds_p<const R> M,
+                                            int stride, int nouter) {
+  constexpr int CH = inplace_fpt(NI) * G::N;
+  const int F = stride * nouter;
+  const int nch = (F + CH - 1) / CH;
+  if (nch <= 1) {
+    contract_ip_chunk<G, R, NI, NO>(buf, M, stride, F, 0);
+    return;
+  }
+  for (int cc = 0; cc < nch; ++cc) {
+    // the previous chunk's stores before this chunk's loads (disjoint, but
+    // the group's accesses of one chunk must not move across another's sync)
+    if (cc > 0) G::sync();
+    contract_ip_chunk<G, R, NI, NO>(buf, M, stride, F, chunk_index(cc, nch, NO < NI) * CH);
+  }
 }
 
 // Two consecutive in-place contractions along level-1 modes p and p+1 (the
@@ -1158,17 +1192,18 @@ struct FiberABC {
 };
 template <typename G, typename R, int NQ>
 __device__ __forceinline__ FiberABC<R, inplace_fpt(NQ)> load_abc(const TermCtx &a,
-                                                                 const TermHdr &T, int nfib) {
+                                                                 const TermHdr &T, int nfib,
+                                                                 int base = 0) {
   constexpr int FPT = inplace_fpt(NQ);
   FiberABC<R, FPT> r;
   if constexpr (sizeof(R) == sizeof(double)) {
-    const int nj = min(FPT, (nfib + G::N - 1) / G::N);
+    const int nj = min(FPT, (nfib - base + G::N - 1) / G::N);
     const glb_p<const double> A = a.abc + T.foff();
     const glb_p<const double> B = A + a.nfib, Cc = B + a.nfib;
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
       if (j >= nj) break;
-      const int f = G::tid() + j * G::N;
+      const int f = base + G::tid() + j * G::N;
       const int fi = f < nfib ? f : 0;
       r.A[j] = A[fi];
       r.B[j] = B[fi];
@@ -1179,16 +1214,15 @@ __device__ __forceinline__ FiberABC<R, inplace_fpt(NQ)> load_abc(const TermCtx &
   return r;
 }
 
-template <typename G, typename R, int NQ, int NB, bool STORE>
-__device__ __forceinline__ void pot_g2b0_ip(const TermHdr &T, lds_p<typename Cx<R>::T> buf,
-                                            lds_p<const R> lt, lds_p<const R> cf, int nfib,
-                                            Out o, double dl,
-                                            const FiberABC<R, inplace_fpt(NQ)> &pre) {
+template <typename G, typename R, int NQ, int NB, bool STORE, int FPT>
+__device__ __forceinline__ void pot_g2b0_chunk(const TermHdr &T, lds_p<typename Cx<R>::T> buf,
+                                               lds_p<const R> lt, lds_p<const R> cf, int nfib,
+                                               Out o, double dl, const FiberABC<R, FPT> &pre,
+                                               int base) {
   typedef typename Cx<R>::T C;
-  constexpr int FPT = inplace_fpt(NQ);
   const int na = T.na();
   const int l0 = T.lev(0);
-  const int nj = min(FPT, (nfib + G::N - 1) / G::N);
+  const int nj = min(FPT, (nfib - base + G::N - 1) / G::N);
   bool ok[FPT];
   int fb[FPT], rem[FPT];
   R A[FPT], B[FPT], Cl[FPT];
@@ -1196,7 +1230,7 @@ __device__ __forceinline__ void pot_g2b0_ip(const TermHdr &T, lds_p<typename Cx<
   if (pre.have) {
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
-      const int f = G::tid() + j * G::N;
+      const int f = base + G::tid() + j * G::N;
       ok[j] = f < nfib && j < nj;
       fb[j] = ok[j] ? f : 0;
       A[j] = pre.A[j];
@@ -1207,7 +1241,7 @@ __device__ __forceinline__ void pot_g2b0_ip(const TermHdr &T, lds_p<typename Cx<
     const R c0 = cf[0], al0 = cf[1], be0 = cf[2];
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
-      const int f = G::tid() + j * G::N;
+      const int f = base + G::tid() + j * G::N;
       ok[j] = f < nfib && j < nj;
       fb[j] = ok[j] ? f : 0;
       rem[j] = fb[j];
@@ -1285,6 +1319,36 @@ __device__ __forceinline__ void pot_g2b0_ip(const TermHdr &T, lds_p<typename Cx<
   });
 }
 
+// A compacting contraction: chunks in increasing fiber order (see
+// chunk_index).  The first chunk (inplace_fpt(NQ) fibers per thread) takes
+// the prefetched A, B, C (FP64 terms); the rest, when the fibers exceed one
+// pass, run in chunks of one fiber per thread that load theirs (any partition
+// into increasing contiguous ranges is safe; small chunks keep the
+// registers of the first pass free).
+template <typename G, typename R, int NQ, int NB, bool STORE>
+__device__ __forceinline__ void pot_g2b0_ip(const TermCtx &a, const TermHdr &T,
+                                            lds_p<typename Cx<R>::T> buf, lds_p<const R> lt,
+                                            lds_p<const R> cf, int nfib, Out o, double dl,
+                                            const FiberABC<R, inplace_fpt(NQ)> &pre0) {
+  constexpr int FPT = inplace_fpt(NQ);
+  pot_g2b0_chunk<G, R, NQ, NB, STORE, FPT>(T, buf, lt, cf, nfib, o, dl, pre0, 0);
+  for (int base = FPT * G::N; base < nfib; base += G::N) {
+    if (!STORE) G::sync();
+    FiberABC<R, 1> pre;
+    if constexpr (sizeof(R) == sizeof(double)) {
+      if (pre0.have) {
+        const int f = base + G::tid();
+        const glb_p<const double> A = a.abc + T.foff() + (f < nfib ? f : 0);
+        pre.A[0] = A[0];
+        pre.B[0] = A[a.nfib];
+        pre.C[0] = A[2 * a.nfib];
+        pre.have = true;
+      }
+    }
+    pot_g2b0_chunk<G, R, NQ, NB, STORE, 1>(T, buf, lt, cf, nfib, o, dl, pre, base);
+  }
+}
+
 // Level dispatch of the in-place steps (standard maps: nb = 2l+1, nq = 2l+2).
 #define SG_LEVELS(X) X(1, 3, 4) X(2, 5, 6) X(3, 7, 8) X(4, 9, 10) X(5, 11, 12) X(6, 13, 14) X(7, 15, 16)
 
@@ -1350,8 +1414,8 @@ __device__ __forceinline__ void run_term_inplace(const TermCtx &a, const TermHdr
   if (na == 1) {
 #define SG_P1CASE(L_, NB_, NQ_)                                                  \
   case L_:                                                                      \
-    pot_g2b0_ip<G, R, NQ_, NB_, true>(T, buf, lt, coef, nfib, Out{a.tm + off}, cf,   \
-                                      FiberABC<R, inplace_fpt(NQ_)>{});             \
+    pot_g2b0_ip<G, R, NQ_, NB_, true>(a, T, buf, lt, coef, nfib, Out{a.tm + off}, cf,  \
+                                      FiberABC<R, inplace_fpt(NQ_)>{});               \
     break;
     switch (l0) { SG_LEVELS(SG_P1CASE) default: break; }
 #undef SG_P1CASE
@@ -1361,7 +1425,7 @@ __device__ __forceinline__ void run_term_inplace(const TermCtx &a, const TermHdr
   case L_: {                                                                    \
     const auto pre = load_abc<G, R, NQ_>(a, T, nfib);                           \
     G::sync();                                                                  \
-    pot_g2b0_ip<G, R, NQ_, NB_, false>(T, buf, lt, coef, nfib, Out{a.tm + off}, cf, pre); \
+    pot_g2b0_ip<G, R, NQ_, NB_, false>(a, T, buf, lt, coef, nfib, Out{a.tm + off}, cf, pre); \
     break;                                                                      \
   }
   switch (l0) { SG_LEVELS(SG_PCASE) default: G::sync(); break; }

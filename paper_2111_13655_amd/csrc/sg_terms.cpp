@@ -497,17 +497,17 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
   h.n_long_rows = (int64_t)h.rows.size();
   for (int64_t r = 0; r < h.ncs; ++r)
     if (h.inv_ptr[r + 1] - h.inv_ptr[r] <= kLongRow) h.rows.push_back((int32_t)r);
-  // reduce items: kRowWaves per chunk of a long row, then one per kShortLanes
+  // reduce items: kRowWaves per long row, then one per kShortLanes
   // short rows, padded to whole workgroups
   h.n_items = (h.ncs - h.n_long_rows + kShortLanes - 1) / kShortLanes;
   h.n_items = (h.n_items + kRowWaves - 1) / kRowWaves * kRowWaves;
   for (int64_t q = 0; q < h.n_long_rows; ++q) {
     const int64_t len = h.inv_ptr[h.rows[q] + 1] - h.inv_ptr[h.rows[q]];
-    if (len > (int64_t)4095 * kRowChunk) {
+    if (len > (int64_t)INT32_MAX / 2) {
       *err = "a compact row has too many term contributions";
       return SG_EINVAL;
     }
-    h.n_items += kRowWaves * ((len + kRowChunk - 1) / kRowChunk);
+    h.n_items += kRowWaves;
   }
   // the inverse CSR in that row order: the reduce loads a row's id and its
   // bounds at the same index, in parallel

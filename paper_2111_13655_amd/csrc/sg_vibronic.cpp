@@ -29,7 +29,6 @@ struct sg_vibronic {
   double2 *d_tm = nullptr;        // [2 N_s]
   double2 *d_work = nullptr;      // 4 x [2 N_cs]: phi, accumulator, two spares
   double *d_partials = nullptr;   // [2][2 n_items]
-  double *d_rpart = nullptr;      // [2][2 n_items]
   double *d_res = nullptr;        // [8]
   double *d_dot = nullptr;        // dot partials
   double *h_res = nullptr;        // pinned [8]
@@ -48,7 +47,6 @@ void vib_release(sg_vibronic *v) {
   hipFree(v->d_tm);
   hipFree(v->d_work);
   hipFree(v->d_partials);
-  hipFree(v->d_rpart);
   hipFree(v->d_res);
   hipFree(v->d_dot);
   if (v->h_res) hipHostFree(v->h_res);
@@ -189,7 +187,6 @@ sg_status sg_vibronic_build(const sg_vibronic_desc *d, sg_vibronic **out) {
   if (e == hipSuccess) e = hipMalloc((void **)&v->d_tm, 2 * (size_t)ns * sizeof(double2));
   if (e == hipSuccess) e = hipMalloc((void **)&v->d_work, 8 * (size_t)ncs * sizeof(double2));
   if (e == hipSuccess) e = hipMalloc((void **)&v->d_partials, 4 * (size_t)nitems * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void **)&v->d_rpart, 4 * (size_t)nitems * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void **)&v->d_res, 8 * sizeof(double));
   if (e == hipSuccess)
     e = hipMalloc((void **)&v->d_dot, 2 * (size_t)dot_partials_per_vector() * sizeof(double));
@@ -218,7 +215,6 @@ sg_status sg_vibronic_build(const sg_vibronic_desc *d, sg_vibronic **out) {
     I.x1 = v->d_work + 2 * (size_t)ncs + (size_t)s * ncs;
     I.acc = v->d_work + 4 * (size_t)ncs + (size_t)s * ncs;
     I.partials = v->d_partials + (size_t)s * 2 * nitems;
-    I.rpart = v->d_rpart + (size_t)s * 2 * nitems;
     I.result = v->d_res + 2 * s;
     I.vec_off = (int64_t)s * ncs;
   }

@@ -68,33 +68,12 @@ int main() {
         if (it.chunk < 0 || it.chunk > kShortLanes) { printf("short count\n"); bad++; }
       }
     }
-    // long rows of several chunks: one finish item each, naming the row and
-    // the slots its chunks leave their sums in (wave 0 of chunk c at
-    // first_slot + kRowWaves c)
-    for (size_t i = 0; i < probs.size(); ++i) {
-      std::vector<const RedItem *> by_local;
-      int multi = 0;
-      for (const RedItem &it : pl.items) {
-        if (it.inst != (int)i) continue;
-        if ((size_t)it.local >= by_local.size()) by_local.resize(it.local + 1, nullptr);
-        by_local[it.local] = &it;
-        const int nch = (it.chunk >> 12) & 0xfff;
-        if (nch > 1 && (it.chunk & 0xfff) == 0 && (it.chunk >> 24) == 0) multi++;
-      }
-      int nfin = 0;
-      for (const FinItem &f : pl.fin) {
-        if (f.inst != (int)i) continue;
-        nfin++;
-        for (int c = 0; c < f.nch; ++c) {
-          const size_t sl = (size_t)f.first_slot + kRowWaves * c;
-          const RedItem *it = sl < by_local.size() ? by_local[sl] : nullptr;
-          if (!it || ((it->chunk >> 12) & 0xfff) != f.nch || (it->chunk & 0xfff) != c ||
-              (it->chunk >> 24) != 0 || probs[i]->h.rows[it->first] != f.row) {
-            printf("finish item\n"); bad++; break;
-          }
-        }
-      }
-      if (nfin != multi) { printf("finish items %d, multi-chunk rows %d\n", nfin, multi); bad++; }
+    // a long row is one workgroup: kRowWaves consecutive items from a
+    // workgroup boundary, waves 0..kRowWaves-1
+    for (size_t q = 0; q < pl.items.size(); ++q) {
+      const RedItem &it = pl.items[q];
+      const int nch = (it.chunk >> 12) & 0xfff;
+      if (nch && (nch != 1 || (int)(q % kRowWaves) != (it.chunk >> 24))) { printf("long row item\n"); bad++; }
     }
     // every row is covered exactly once by short items or chunk 0 wave 0 of long rows
     for (size_t i = 0; i < probs.size(); ++i) {
