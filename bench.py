@@ -49,6 +49,9 @@ WORKLOADS = {
                   desc="smolyak H|psi> D=6 L=6 coupled anharmonic, Chebyshev dt=0.05, FP64"),
     "d2_l4": dict(D=2, L=4, dt=0.1, steps=100, check_every=10, cfg="config0",
                   desc="smolyak H|psi> D=2 L=4 coupled anharmonic, Chebyshev dt=0.1, FP64"),
+    # two-state model (profiling only: --apply-only)
+    "vib_d12_l5": dict(D=12, L=5, dt=0.05, steps=100, check_every=10, cfg="vibronic_pyrazine",
+                       desc="two-state pyrazine form, 12 modes, L=5, FP64"),
 }
 
 
@@ -533,9 +536,73 @@ def serve(sg, window_s, steps_scale, mixed_threshold):
             "request_rel_err_vs_fp64_p50": float(np.percentile(errs, 50)) if errs else 0.0}
 
 
+def vibronic(sg, steps=100, dt=0.05):
+    """The two-state (vibronic) operator of the pyrazine form, 12 modes at
+    L = 5: apply throughput, kernel durations, the sweep's roofline figures,
+    and a Chebyshev propagation from the displaced Gaussian on the upper
+    state with the upper-state population at every 10th step."""
+    import torch
+    import sg_inputs
+    inst = sg_inputs.vibronic_pyrazine(5)
+    V = sg.Vibronic.from_instance(inst)
+    n = V.n_cs
+    x = torch.empty(2 * n, dtype=torch.complex128, device="cuda")
+    sg.sg_vibronic_init(V.handle, n, inst.shift, 1, x)
+    y = torch.empty_like(x)
+    for _ in range(5):
+        V.apply(x, y)
+    torch.cuda.synchronize()
+    reps = 200
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        V.apply(x, y)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sg.sg_set_timing(V.problem, True)
+    for _ in range(50):
+        V.apply(x, y)
+    tim = sg.sg_get_timing(V.problem)
+    sg.sg_set_timing(V.problem, False)
+    sweep_s = tim["sweep_ms"] / max(tim["sweep_launches"], 1) * 1e-3
+    reduce_s = tim["reduce_ms"] / max(tim["reduce_launches"], 1) * 1e-3
+    flops, nbytes = sg.sg_vibronic_figures(V.handle)
+    lo, hi = sg.sg_vibronic_bounds(V.handle, 40)
+    psi = x.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, st, pop = sg.sg_vibronic_propagate(V.handle, n, psi, dt, steps, lo, hi, tol=1e-6,
+                                               check_every=10)
+    torch.cuda.synchronize()
+    el_p = time.perf_counter() - t0
+    info = V.info
+    V.close()
+    return {"workload": "two-state pyrazine form, 12 modes, L=5 (N_cs=%d per state, %d terms), FP64"
+                        % (n, info["n_terms"]),
+            "applies_per_s": reps / el,
+            "kernel_avg_us": {"term_sweep": sweep_s * 1e6, "reduce": reduce_s * 1e6},
+            "sweep_flops_per_launch": flops, "sweep_bytes_per_launch": nbytes,
+            "sweep_flop_frac": flops / sweep_s / 1e12 / FP64_PEAK_TFLOPS,
+            "sweep_hbm_frac": nbytes / sweep_s / 1e9 / HBM_PEAK_GBS,
+            "propagation": {"steps": steps, "dt": dt, "seconds": el_p, "status": int(status),
+                            "applies": st["applies"], "norm_drift": st["max_norm_drift"],
+                            "energy_drift": st["max_energy_drift"],
+                            "upper_state_population_every_10_steps": [float(v) for v in pop]}}
+
+
 def apply_only(sg, args, inst):
     """N applies of the workload's operator (for the profiler), then exit."""
     import torch
+    if args.workload == "vib_d12_l5":
+        V = sg.Vibronic.from_instance(inst)
+        x = torch.empty(2 * V.n_cs, dtype=torch.complex128, device="cuda")
+        sg.sg_vibronic_init(V.handle, V.n_cs, inst.shift, 1, x)
+        y = torch.empty_like(x)
+        for _ in range(args.apply_only):
+            V.apply(x, y)
+        torch.cuda.synchronize()
+        V.close()
+        print(json.dumps({"apply_only": args.apply_only, "workload": args.workload}), flush=True)
+        return
     P = sg.Problem.from_instance(inst)
     psi = torch.empty(P.n_cs, dtype=torch.complex128, device="cuda")
     sg.sg_init_gaussian(P.handle, inst.shift, psi)
@@ -609,12 +676,18 @@ def main():
     if args.apply_only > 0:
         apply_only(sg, args, inst)
         return
+    if args.workload == "vib_d12_l5":
+        sys.exit("the two-state workload is profiled with --apply-only; its bench figures "
+                 "are the 'vibronic' section of the default run")
     out = headline(sg, args, wl, inst)
     if not args.no_extras:
         if args.workload != "d6_l6":
             log("[bench] D=6 L=6 FP64 trajectory")
             out["d6_l6_fp64"] = d6l6_leg(sg)
             log(f"[bench] {out['d6_l6_fp64']}")
+        log("[bench] two-state (vibronic) pyrazine form, 12 modes, L=5")
+        out["vibronic"] = vibronic(sg)
+        log(f"[bench] {out['vibronic']}")
         log("[bench] propagators (D=6, L=6)")
         out["propagators"] = propagators(sg)
         log(f"[bench] {out['propagators']}")
