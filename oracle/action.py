@@ -28,7 +28,10 @@ largest level's basis and grid, then masks and restricts it: an independent
 check of both routes at tiny D, L.
 
 The Hamiltonian family: H = sum_i 1/2 omega_i (-d^2/dQ_i^2 + Q_i^2)
-+ sum_{i<j} c_ij Q_i^2 Q_j^2 + sum_{i<j} k_ij Q_i^2 Q_j.
++ sum_{i<j} c_ij Q_i^2 Q_j^2 + sum_{i<j} k_ij Q_i^2 Q_j, or, in Route 1, the
+harmonic part plus a general coupling potential V(Q) given as a function.
+For a general V the term rules are no longer exact and Route 2 does not
+apply; Route 1 is then the definition.
 """
 from __future__ import annotations
 
@@ -48,14 +51,19 @@ def mode_product(T: np.ndarray, M: np.ndarray, axis: int) -> np.ndarray:
     return np.moveaxis(out, 0, axis)
 
 
-def potential_on_grid(inst, xs: list[np.ndarray]) -> np.ndarray:
+def potential_on_grid(inst, xs: list[np.ndarray], coupling=None) -> np.ndarray:
     """V(Q) on the direct product of the one-mode grids xs (axis i = mode i):
-    the harmonic part 1/2 omega_i Q_i^2 plus the couplings."""
+    the harmonic part 1/2 omega_i Q_i^2 plus the couplings.  `coupling`, if
+    given, replaces the polynomial couplings: a function of the list of D
+    coordinate arrays (broadcasting against each other) returning the
+    coupling potential at those points."""
     D = inst.D
     Q = np.meshgrid(*xs, indexing="ij", sparse=True)
     V = np.zeros(tuple(len(x) for x in xs))
     for i in range(D):
         V = V + 0.5 * inst.omega[i] * Q[i] ** 2
+    if coupling is not None:
+        return V + np.broadcast_to(coupling(Q), V.shape)
     for i in range(D):
         for j in range(i + 1, D):
             if inst.c[i, j] != 0.0:
@@ -66,10 +74,13 @@ def potential_on_grid(inst, xs: list[np.ndarray]) -> np.ndarray:
 
 
 class Oracle:
-    """Holds the structure and tables for one instance."""
+    """Holds the structure and tables for one instance.  `coupling` (a
+    function of the D coordinate arrays, as in potential_on_grid) replaces the
+    instance's polynomial couplings by a general potential."""
 
-    def __init__(self, inst, structure=None):
+    def __init__(self, inst, structure=None, coupling=None):
         self.inst = inst
+        self.coupling = coupling
         self.S = structure if structure is not None else build_structure(
             inst.D, inst.L, inst.nb_A, inst.nb_B)
         self.tab = tables_for(inst.L, inst.nb_A, inst.nb_B, inst.nq_A, inst.nq_B)
@@ -86,7 +97,7 @@ class Oracle:
         G = X
         for i, li in enumerate(l):                            # step 2 (B -> G)
             G = mode_product(G, tab[li].b, i)
-        V = potential_on_grid(inst, [tab[li].x for li in l])
+        V = potential_on_grid(inst, [tab[li].x for li in l], self.coupling)
         HG = V * G                                            # step 3 (potential)
         for i in range(inst.D):                               # step 3 (kinetic)
             T = X

@@ -217,3 +217,44 @@ def vibronic_pyrazine(L: int = 5, seed: int | None = None) -> VibronicInstance:
     inst = draw_vibronic(rng, 12, L, quartic=False)
     inst.meta = dict(name=f"vib_pyrazine_d12_l{L}", dt=0.05)
     return inst
+
+
+# ---------------------------------------------------------------------------
+# General (non-polynomial) coupling potentials for the tabulated path.  The
+# paper's systems use general potential-energy surfaces; a seeded smooth
+# family of the same kind stands in for them:
+#   V(Q) = sum_i a_i (1 - cos(b_i Q_i)) + sum_{i<j} g_ij exp(-(Q_i - Q_j)^2 / 2)
+# with a ~ U(0.05, 0.2), b ~ U(0.5, 1.5), g ~ U(-0.05, 0.05).  Draw order:
+# a[D], b[D], g (i<j, row-major).
+# ---------------------------------------------------------------------------
+
+@dataclass
+class GeneralPotential:
+    D: int
+    a: np.ndarray
+    b: np.ndarray
+    g: np.ndarray                # [D, D], only i<j entries are non-zero
+
+    def __call__(self, Q):
+        """V at the points given by D coordinate arrays (broadcasting)."""
+        V = 0.0
+        for i in range(self.D):
+            V = V + self.a[i] * (1.0 - np.cos(self.b[i] * Q[i]))
+        for i in range(self.D):
+            for j in range(i + 1, self.D):
+                V = V + self.g[i, j] * np.exp(-0.5 * (Q[i] - Q[j]) ** 2)
+        return V
+
+    def at_points(self, P: np.ndarray) -> np.ndarray:
+        """V at the rows of an (n, D) array of points."""
+        return np.asarray(self([P[:, i] for i in range(self.D)]), dtype=np.float64)
+
+
+def general_potential(D: int, seed: int = 777) -> GeneralPotential:
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.05, 0.2, size=D)
+    b = rng.uniform(0.5, 1.5, size=D)
+    g = np.zeros((D, D))
+    iu = np.triu_indices(D, 1)
+    g[iu] = rng.uniform(-0.05, 0.05, size=len(iu[0]))
+    return GeneralPotential(D=D, a=a, b=b, g=g)
