@@ -15,11 +15,15 @@
  * propagation in Sec. 3 and uses it in Sec. 5), a batched multi-instance
  * propagator and a continuous-batching server.
  *
- * Problem family (the paper's Hamiltonians are general; the library computes
- * this polynomial family, Cartesian normal modes, hbar = 1):
+ * Problem family (Cartesian normal modes, hbar = 1):
  *
  *   H = sum_i 1/2 omega_i (-d^2/dQ_i^2 + Q_i^2)
  *       + sum_{i<j} c_ij Q_i^2 Q_j^2 + sum_{i<j} k_ij Q_i^2 Q_j
+ *
+ * with the couplings evaluated in closed form on every term grid, or, after
+ * sg_set_potential, a general potential V(Q) from a caller's function
+ * tabulated on the term grids.  The two-state calls (sg_vibronic_*) take the
+ * paper's Sec. 5 pyrazine form.
  *
  * Primitive basis per mode: orthonormal Hermite functions ("Hm", Q0 = 0,
  * scaleQ = 1, Example subsection of Sec. 4) with N^b_l = nb_A + nb_B l functions and
@@ -119,7 +123,9 @@ typedef struct {
   double sweep_bytes;      /* HBM bytes the term sweep of one SG_FP64 apply must
                               move as designed: psi read once, M^B, the
                               term-major results written, term records and the
-                              per-fiber potential coefficients it reads        */
+                              per-fiber potential coefficients it reads (with a
+                              tabulated potential: its 8 bytes per active grid
+                              point instead)                                   */
   double reduce_bytes;     /* ... the reduce: term-major results and inverse map
                               read, row lists, psi and the diagonal read, the
                               result written                                   */
@@ -431,6 +437,33 @@ sg_status sg_set_mixed_threshold(sg_problem *p, int32_t max_fp32_coeff);
  * always uses the grid form.  SG_MIXED always uses the split form.
  * Synchronous; also valid on a host-only handle. */
 sg_status sg_set_operator_form(sg_problem *p, int32_t grid_kinetic);
+
+/* General coupling potential (Alg. 1, Sec. 3: the operator applied on each
+ * term's direct-product grid; eq_action_smolyak, Sec. 2).  After
+ * sg_set_potential(p, V, user) the problem's operator is
+ *   H = sum_i 1/2 omega_i (-d^2/dQ_i^2 + Q_i^2) + V(Q),
+ * V replacing the polynomial couplings c and k of its description.  The
+ * library evaluates V once, here, on the host: at every point of every term's
+ * direct-product grid (the paper's grids; their number is
+ * sg_info.grid_literal), in batches of at most 65536 points, calling
+ *   V(n, Q, out, user)   Q: [n][D] row-major, mode 1 first (read only);
+ *                        out: [n], V at those points (written by V).
+ * For every term it sums V over the points of the level-0 modes with their
+ * weights wt_u b_0(Q_u)^2 (those modes carry one basis function, so this is
+ * what their basis -> grid -> basis passes compute) and uploads the result,
+ * one FP64 value per active grid point (sg_info.grid_active values).  Applies
+ * then read those tables; the separable part acts as the exact diagonal, as
+ * in the default operator form.  V must be pure and return finite values; it
+ * is not called after sg_set_potential returns.  V == NULL restores the
+ * polynomial couplings.
+ * Requirements: a device handle with the standard size maps (nb = 1 + 2l,
+ * nq = 2 + 2l), L <= 6, the split operator form, and at most 1e11 grid points.
+ * Such a problem runs in FP64 only (SG_MIXED calls fail with SG_EINVAL) and on
+ * its own (sg_batch_create refuses it).  Errors: SG_EINVAL (requirements, a
+ * non-finite V), SG_ENOMEM, SG_EDEVICE; on error the previous potential stays.
+ * Synchronous: the device is synchronised before the tables are replaced. */
+typedef void (*sg_potential_fn)(int64_t n, const double *Q, double *out, void *user);
+sg_status sg_set_potential(sg_problem *p, sg_potential_fn V, void *user);
 
 /* Precision autotuner.  Tries every threshold from "all terms in FP32" down
  * to 0 (no FP32 term: the exact FP64 split) on the device vector psi

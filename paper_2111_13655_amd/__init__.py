@@ -35,7 +35,7 @@ __all__ = [
     "sg_serve_counters", "sg_serve_destroy", "Problem",
     "VibronicDesc", "sg_vibronic_build", "sg_vibronic_free", "sg_vibronic_problem",
     "sg_vibronic_figures", "sg_vibronic_init", "sg_vibronic_apply", "sg_vibronic_bounds",
-    "sg_vibronic_propagate", "Vibronic",
+    "sg_vibronic_propagate", "Vibronic", "sg_set_potential",
 ]
 
 SG_OK, SG_EINVAL, SG_ENOMEM, SG_EDEVICE = 0, -1, -2, -3
@@ -135,7 +135,12 @@ class Result(ctypes.Structure):
                 ("t_done", ctypes.c_double)]
 
 
+# V(n, Q [n][D], out [n], user)
+POTENTIAL_FN = ctypes.CFUNCTYPE(None, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)
+
 _SIGNATURES = {
+    "sg_set_potential": (ctypes.c_int, [_P, POTENTIAL_FN, ctypes.c_void_p]),
     "sg_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "sg_set_operator_form": (ctypes.c_int, [_P, ctypes.c_int32]),
     "sg_set_schedule": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
@@ -448,6 +453,37 @@ def sg_tune_mixed(h, psi, tol: float = 1e-6, reps: int = 3, stream=None):
     _check(lib().sg_tune_mixed(h, _vec_ptr(psi, n_cs, "psi"), float(tol), int(reps),
                                ctypes.byref(ch), ctypes.byref(er), _stream_ptr(stream)))
     return ch.value, er.value
+
+
+def sg_set_potential(h, V) -> None:
+    """Replaces the problem's polynomial couplings by the potential V: a
+    function taking an (n, D) float64 array of points (mode 1 first) and
+    returning their n values.  The library calls it only during this call;
+    V=None restores the polynomial couplings.  An exception raised by V is
+    re-raised here."""
+    if V is None:
+        _check(lib().sg_set_potential(h, POTENTIAL_FN(), None))
+        return
+    D = sg_problem_info(h)["D"]
+    raised = []
+
+    def thunk(n, Q, out, _user):
+        res = np.ctypeslib.as_array(out, shape=(n,))
+        if raised:
+            res[:] = np.nan
+            return
+        try:
+            pts = np.ctypeslib.as_array(Q, shape=(n, D))
+            res[:] = np.asarray(V(pts), dtype=np.float64).reshape(n)
+        except BaseException as exc:   # reported after the library returns
+            raised.append(exc)
+            res[:] = np.nan
+
+    cb = POTENTIAL_FN(thunk)
+    status = lib().sg_set_potential(h, cb, None)
+    if raised:
+        raise raised[0]
+    _check(status)
 
 
 def sg_set_operator_form(h, grid_kinetic: bool) -> None:

@@ -269,6 +269,7 @@ struct Plan;
 }  // namespace sg
 
 namespace sg {
+struct TabLaunch;
 // A problem's own term packs and reduce items, kept so that plans over many
 // problems (batches, the server) concatenate them instead of packing every
 // term again.  Built for a fixed mixed threshold and operator form.
@@ -316,6 +317,7 @@ struct sg_problem {
   double *h_result = nullptr;      // pinned host mirror of d_result
   int64_t device_bytes = 0;
   sg::Plan *plan = nullptr;        // launch plan of this problem alone
+  sg::TabLaunch *tabpot = nullptr; // tabulated coupling potential (sg_set_potential), or none
   // optional per-kernel timing with HIP events (sg_set_timing)
   struct Timing {
     bool on = false;
@@ -464,17 +466,33 @@ int chebyshev_series(double R, std::vector<double> *a);
 constexpr int kVibSurf = 17 + kMaxPairs;   // 45
 constexpr int kVibCoef = 104;              // 2 kVibSurf + kMaxActive, padded
 static_assert(2 * kVibSurf + kMaxActive <= kVibCoef, "vibronic coefficient block");
-struct VibGroup {
+// Launch shapes of the term sweeps that run one term per workgroup (the
+// two-state operator, tabulated potentials): threads per term, the largest
+// term grid and the highest active level a shape's kernel takes.  With the
+// standard maps and L <= 6 every term fits one of them (grids above 1024
+// points have levels <= 2, above 256 levels <= 3, above 64 levels <= 4).
+struct GroupShape {
+  int vt, max_grid, max_level;
+};
+constexpr int kGroupShapes = 4;
+constexpr GroupShape kGroupShape[kGroupShapes] = {{256, 4096, 2}, {256, 1024, 3}, {64, 256, 4},
+                                                  {64, 64, 6}};
+struct TermGroup {
   int32_t first = 0, count = 0;   // range of the term order launched together
   int32_t max_grid = 0;           // largest grid of the group (sizes its LDS)
+  int32_t shape = 0;              // index into kGroupShape
 };
+// Orders the terms of a compiled problem for such sweeps: each term goes to
+// the smallest shape that takes its grid and highest level, groups in shape
+// order, largest grids first within a group.  False if a term fits no shape.
+bool group_terms(const Compiled &h, std::vector<int32_t> *order, std::vector<TermGroup> *groups);
 struct VibLaunch {
   const TermDev *terms = nullptr;
   const int32_t *mb = nullptr;
   const double *tab = nullptr;    // standard-map tables, levels 0..L
   const double *coef = nullptr;   // [nterms][kVibCoef]
   const int32_t *order = nullptr; // device: terms, largest grid first
-  std::vector<VibGroup> groups;
+  std::vector<TermGroup> groups;
   int64_t ncs = 0, ns = 0;
   int tab_elems = 0;
 };
@@ -485,6 +503,25 @@ hipError_t launch_vib_sweep(const VibLaunch &v, const double2 *vin, double2 *tm,
 // the same, timed as a sweep by owner's events when its timing is on
 hipError_t run_vib_sweep(sg_problem *owner, const VibLaunch &v, const double2 *vin, double2 *tm,
                          hipStream_t s);
+
+// A problem's tabulated coupling potential (sg_tabpot.cpp): V_eff of every
+// term on its active grid (mode 0 fastest), and the sweep's launch groups.
+struct TabLaunch {
+  const TermDev *terms = nullptr;
+  const int32_t *mb = nullptr;
+  const double *tab = nullptr;     // standard-map tables, levels 0..L
+  double *veff = nullptr;          // device, owned: [n_veff]
+  int64_t *voff = nullptr;         // device, owned: [nterms], term t's V_eff from voff[t]
+  int32_t *order = nullptr;        // device, owned: terms in group order
+  std::vector<TermGroup> groups;
+  int tab_elems = 0;
+  int64_t n_veff = 0;
+};
+void tabpot_free(TabLaunch *t);   // the device buffers and the record
+// vin: [N_cs]; tm: [N_s].  ev0 / ev1 (nullable) attach to the first / last
+// dispatch.
+hipError_t launch_tab_sweep(const TabLaunch &v, const double2 *vin, double2 *tm, hipStream_t s,
+                            hipEvent_t ev0, hipEvent_t ev1);
 
 // Work buffers of one sg_propagate call (sg_step.cpp): allocated for the call
 // (owned), or carved out of a region the caller provides (not owned).

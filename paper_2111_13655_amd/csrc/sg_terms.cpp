@@ -523,4 +523,37 @@ sg_status compile_problem(const sg_problem_desc *desc, Compiled *out, std::strin
   return SG_OK;
 }
 
+bool group_terms(const Compiled &h, std::vector<int32_t> *order, std::vector<TermGroup> *groups) {
+  const int64_t nt = h.nterms;
+  std::vector<int32_t> shape_of(nt, -1);
+  for (int64_t t = 0; t < nt; ++t) {
+    const TermDev &T = h.terms[t];
+    int maxlev = 0;
+    for (int q = 0; q < T.na; ++q) maxlev = std::max(maxlev, (int)T.lev[q]);
+    for (int k = kGroupShapes - 1; k >= 0; --k)
+      if (T.ngrid <= kGroupShape[k].max_grid && maxlev <= kGroupShape[k].max_level) {
+        shape_of[t] = k;
+        break;
+      }
+    if (shape_of[t] < 0) return false;
+  }
+  order->resize(nt);
+  std::iota(order->begin(), order->end(), 0);
+  std::stable_sort(order->begin(), order->end(), [&](int32_t a, int32_t b) {
+    if (shape_of[a] != shape_of[b]) return shape_of[a] < shape_of[b];
+    return h.terms[a].ngrid > h.terms[b].ngrid;
+  });
+  groups->clear();
+  for (int64_t i = 0; i < nt;) {
+    TermGroup G;
+    G.first = (int32_t)i;
+    G.shape = shape_of[(*order)[i]];
+    G.max_grid = h.terms[(*order)[i]].ngrid;
+    while (i < nt && shape_of[(*order)[i]] == G.shape) ++i;
+    G.count = (int32_t)(i - G.first);
+    groups->push_back(G);
+  }
+  return true;
+}
+
 }  // namespace sg

@@ -151,27 +151,9 @@ sg_status sg_vibronic_build(const sg_vibronic_desc *d, sg_vibronic **out) {
   }
   v->sweep_bytes = 2.0 * 16.0 * (double)ncs + 4.0 * (double)ns + 2.0 * 16.0 * (double)ns +
                    (double)nt * (sizeof(TermDev) + kVibCoef * 8.0);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    return h.terms[a].ngrid > h.terms[b].ngrid;
-  });
-  // launch groups by LDS need: grids above 1024, 257..1024, up to 256 points
-  {
-    const int bounds[3] = {1 << 30, 1024, 256};
-    int64_t i = 0;
-    for (int g = 0; g < 3; ++g) {
-      VibGroup G;
-      G.first = (int32_t)i;
-      while (i < nt && h.terms[order[i]].ngrid <= bounds[g] &&
-             (g == 2 || h.terms[order[i]].ngrid > bounds[g + 1]))
-        ++i;
-      G.count = (int32_t)(i - G.first);
-      G.max_grid = G.count ? h.terms[order[G.first]].ngrid : 0;
-      if (G.count) v->vl.groups.push_back(G);
-    }
-    if (i != nt) {
-      vib_release(v);
-      return fail(SG_EINVAL, "term grouping failed");
-    }
+  if (!group_terms(h, &order, &v->vl.groups)) {
+    vib_release(v);
+    return fail(SG_EINVAL, "a term of the two-state operator fits no launch shape");
   }
   // the reduce over both states: one instance per state
   std::string err;
