@@ -49,6 +49,9 @@ WORKLOADS = {
                   desc="smolyak H|psi> D=6 L=6 coupled anharmonic, Chebyshev dt=0.05, FP64"),
     "d2_l4": dict(D=2, L=4, dt=0.1, steps=100, check_every=10, cfg="config0",
                   desc="smolyak H|psi> D=2 L=4 coupled anharmonic, Chebyshev dt=0.1, FP64"),
+    # general tabulated potential (profiling only: --apply-only)
+    "tab_d8_l6": dict(D=8, L=6, dt=0.05, steps=100, check_every=10, cfg="tabulated_d8_l6",
+                      desc="general potential tabulated on the term grids, D=8, L=6, FP64"),
     # two-state model (profiling only: --apply-only)
     "vib_d12_l5": dict(D=12, L=5, dt=0.05, steps=100, check_every=10, cfg="vibronic_pyrazine",
                        desc="two-state pyrazine form, 12 modes, L=5, FP64"),
@@ -589,9 +592,67 @@ def vibronic(sg, steps=100, dt=0.05):
                             "upper_state_population_every_10_steps": [float(v) for v in pop]}}
 
 
+def tabulated(sg, steps=100, dt=0.05):
+    """A general (non-polynomial) coupling potential tabulated on the term
+    grids, D = 8, L = 6: host tabulation time, apply throughput, kernel
+    durations, the sweep's roofline figures (its bytes include the V_eff
+    tables) and a Chebyshev propagation from the displaced Gaussian."""
+    import torch
+    import sg_inputs
+    inst, V = sg_inputs.tabulated_d8_l6()
+    P = sg.Problem.from_instance(inst)
+    t0 = time.perf_counter()
+    sg.sg_set_potential(P.handle, V.at_points)
+    t_tab = time.perf_counter() - t0
+    info = sg.sg_problem_info(P.handle)
+    n = P.n_cs
+    x = torch.empty(n, dtype=torch.complex128, device="cuda")
+    sg.sg_init_gaussian(P.handle, inst.shift, x)
+    y = torch.empty_like(x)
+    for _ in range(5):
+        P.apply(x, y)
+    torch.cuda.synchronize()
+    reps = 500
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P.apply(x, y)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    lo, hi = sg.sg_spectral_bounds(P.handle, 40)
+    sweep_s, reduce_s, _ = kernel_times(sg, P, x, dt, 20, lo, hi, sg.SG_FP64, 10)
+    el_p, status, st, _ = timed_propagation(sg, P, x, dt, steps, 5, lo, hi, sg.SG_FP64, 10)
+    flops, nbytes = info["sweep_flops_fp64"], info["sweep_bytes"]
+    P.close()
+    return {"workload": "general potential (cosine and Gaussian pair terms) tabulated on the term "
+                        "grids, D=8, L=6 (N_cs=%d, %d terms, %d V_eff values), FP64"
+                        % (n, info["n_terms"], info["grid_active"]),
+            "tabulate_s": t_tab, "potential_evaluations": info["grid_literal"],
+            "applies_per_s": reps / el,
+            "kernel_avg_us": {"term_sweep": sweep_s * 1e6, "reduce": reduce_s * 1e6},
+            "sweep_flops_per_launch": flops, "sweep_bytes_per_launch": nbytes,
+            "sweep_flop_frac": flops / sweep_s / 1e12 / FP64_PEAK_TFLOPS,
+            "sweep_hbm_frac": nbytes / sweep_s / 1e9 / HBM_PEAK_GBS,
+            "propagation": {"steps": steps, "dt": dt, "seconds": el_p, "status": int(status),
+                            "applies": st["applies"], "norm_drift": st["max_norm_drift"],
+                            "energy_drift": st["max_energy_drift"]}}
+
+
 def apply_only(sg, args, inst):
     """N applies of the workload's operator (for the profiler), then exit."""
     import torch
+    if args.workload == "tab_d8_l6":
+        inst, V = inst
+        P = sg.Problem.from_instance(inst)
+        sg.sg_set_potential(P.handle, V.at_points)
+        x = torch.empty(P.n_cs, dtype=torch.complex128, device="cuda")
+        sg.sg_init_gaussian(P.handle, inst.shift, x)
+        y = torch.empty_like(x)
+        for _ in range(args.apply_only):
+            P.apply(x, y)
+        torch.cuda.synchronize()
+        P.close()
+        print(json.dumps({"apply_only": args.apply_only, "workload": args.workload}), flush=True)
+        return
     if args.workload == "vib_d12_l5":
         V = sg.Vibronic.from_instance(inst)
         x = torch.empty(2 * V.n_cs, dtype=torch.complex128, device="cuda")
@@ -676,9 +737,9 @@ def main():
     if args.apply_only > 0:
         apply_only(sg, args, inst)
         return
-    if args.workload == "vib_d12_l5":
-        sys.exit("the two-state workload is profiled with --apply-only; its bench figures "
-                 "are the 'vibronic' section of the default run")
+    if args.workload in ("vib_d12_l5", "tab_d8_l6"):
+        sys.exit("this workload is profiled with --apply-only; its bench figures are a "
+                 "section of the default run")
     out = headline(sg, args, wl, inst)
     if not args.no_extras:
         if args.workload != "d6_l6":
@@ -688,6 +749,9 @@ def main():
         log("[bench] two-state (vibronic) pyrazine form, 12 modes, L=5")
         out["vibronic"] = vibronic(sg)
         log(f"[bench] {out['vibronic']}")
+        log("[bench] tabulated general potential, D=8 L=6")
+        out["tabulated"] = tabulated(sg)
+        log(f"[bench] {out['tabulated']}")
         log("[bench] propagators (D=6, L=6)")
         out["propagators"] = propagators(sg)
         log(f"[bench] {out['propagators']}")

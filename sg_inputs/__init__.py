@@ -258,3 +258,14 @@ def general_potential(D: int, seed: int = 777) -> GeneralPotential:
     iu = np.triu_indices(D, 1)
     g[iu] = rng.uniform(-0.05, 0.05, size=len(iu[0]))
     return GeneralPotential(D=D, a=a, b=b, g=g)
+
+
+def tabulated_d8_l6(seed: int | None = None):
+    """The tabulated-potential workload: D = 8, L = 6, harmonic frequencies of
+    the family above and a general potential of the family above (seed
+    DEFAULT_SEED + 5 for the instance, + 1005 for the potential)."""
+    s = DEFAULT_SEED + 5 if seed is None else seed
+    inst = draw_instance(np.random.default_rng(s), 8, 6, with_k=False)
+    inst.c[:] = 0.0
+    inst.meta = dict(name="tabulated_d8_l6", dt=0.05)
+    return inst, general_potential(8, seed=s + 1000)

@@ -156,14 +156,14 @@ def test_tabulated_refusals():
             sg.sg_set_potential(P.handle, boom)
 
 
-def test_tabulated_d6_l6_full_vector():
-    """The bench size (D=6, L=6): the whole output against Route 1."""
+def test_tabulated_bench_workload_full_vector():
+    """The bench's workload (D=8, L=6, its potential): the whole output
+    against Route 1."""
     sg = _sg()
-    inst = sg_inputs.config1()
-    V = sg_inputs.general_potential(6, seed=606)
+    inst, V = sg_inputs.tabulated_d8_l6()
     O = Oracle(inst, coupling=V)
     psi = rand_state(O.S.n_cs, 9)
-    say("tabulated D=6 L=6 full vector")
+    say("tabulated D=8 L=6 full vector")
     ref = O.apply_literal(psi)
     with _problem(sg, inst, V) as P:
         assert max_rel(_apply(P, psi), ref) < TOL
