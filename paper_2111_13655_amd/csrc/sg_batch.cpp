@@ -22,10 +22,18 @@ struct sg_batch {
 namespace sg {
 namespace {
 
+// The precision a batch launch runs in: with no FP32 term in the plan, the
+// mixed path is the FP64 split path term by term (same tables, same
+// contractions, same fixed-order reduce), so it launches that pack set, which
+// the cached multi-problem packs lay out for FP64 tables only.
+sg_precision launch_precision(const Plan &pl, sg_precision prec) {
+  return (prec == SG_MIXED && !pl.any32 && pl.fp64_split) ? SG_FP64 : prec;
+}
+
 sg_status batch_step_launches(sg_batch *b, sg_precision prec, int kmax, hipStream_t s) {
   LaunchCtl c;
   c.mode = Mode::Cheb;
-  c.prec = prec;
+  c.prec = launch_precision(b->plan, prec);
   for (int k = 1; k < kmax; ++k) {
     c.k = k;
     c.want_partials = 0;
@@ -124,7 +132,7 @@ sg_status sg_batch_tune_schedule(sg_batch *b, void *const *psi, int32_t n_psi, i
   };
   LaunchCtl c;
   c.mode = Mode::Apply;
-  c.prec = (sg_precision)prec;
+  c.prec = launch_precision(b->plan, (sg_precision)prec);
   auto apply_all = [&]() -> hipError_t {
     hipError_t e = launch_sweep(&b->plan, c, s);
     if (e == hipSuccess) e = launch_reduce(&b->plan, c, s);
@@ -292,7 +300,7 @@ sg_status sg_batch_propagate(sg_batch *b, void *const *psi, int32_t n_psi, const
   sg_status ret = SG_OK;
   LaunchCtl c;
   c.mode = Mode::Cheb;
-  c.prec = prec;
+  c.prec = launch_precision(pl, prec);
   for (int step = 0; step < nsteps && ret == SG_OK; ++step) {
     const bool check = step == 0 || (check_every > 0 && step % check_every == 0);
     if (check || !exec) {

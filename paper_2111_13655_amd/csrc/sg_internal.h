@@ -470,13 +470,14 @@ static_assert(2 * kVibSurf + kMaxActive <= kVibCoef, "vibronic coefficient block
 // two-state operator, tabulated potentials): threads per term, the largest
 // term grid and the highest active level a shape's kernel takes.  With the
 // standard maps and L <= 6 every term fits one of them (grids above 1024
-// points have levels <= 2, above 256 levels <= 3, above 64 levels <= 4).
+// points have levels <= 2, above 256 levels <= 3).  Every shape is one
+// dispatch, and a dispatch of small terms lasts about one term's chain of
+// dependent steps, so the small terms share one shape.
 struct GroupShape {
   int vt, max_grid, max_level;
 };
-constexpr int kGroupShapes = 4;
-constexpr GroupShape kGroupShape[kGroupShapes] = {{256, 4096, 2}, {256, 1024, 3}, {64, 256, 4},
-                                                  {64, 64, 6}};
+constexpr int kGroupShapes = 3;
+constexpr GroupShape kGroupShape[kGroupShapes] = {{512, 4096, 2}, {256, 1024, 3}, {64, 256, 6}};
 struct TermGroup {
   int32_t first = 0, count = 0;   // range of the term order launched together
   int32_t max_grid = 0;           // largest grid of the group (sizes its LDS)

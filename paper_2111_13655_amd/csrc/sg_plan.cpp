@@ -338,7 +338,10 @@ void build_cache(sg_problem *p) {
   }
   const std::vector<Cand> *cs[kPackSets] = {&cg64, &cs64, &m64, &m32};
   const int elem[kPackSets] = {16, 16, 16, 8};
-  const int tab[kPackSets] = {0, kTabMax64, 2 * kTabMax64, kTabMax32};
+  // the mixed path's FP64 terms hold the exact and the FP32-rounded tables
+  // only when the instance has FP32 terms; otherwise they pack like the FP64
+  // split set (no term pushed out of LDS into global scratch)
+  const int tab[kPackSets] = {0, kTabMax64, c.inst32 ? 2 * kTabMax64 : kTabMax64, kTabMax32};
   for (int k = 0; k < kPackSets; ++k) {
     c.packs[k].clear();
     c.cost[k].clear();

@@ -305,7 +305,10 @@ void scheduler_loop(sg_server *s) {
     }
     LaunchCtl c;
     c.mode = Mode::Cheb;
-    c.prec = s->cfg.prec;
+    // with no FP32 term resident, the mixed path is the FP64 split path term
+    // by term: launch that pack set (laid out for FP64 tables only)
+    c.prec = (s->cfg.prec == SG_MIXED && !s->plan.any32 && s->plan.fp64_split) ? SG_FP64
+                                                                                 : s->cfg.prec;
     hipError_t e = hipSuccess;
     for (int k = 1; k < kmax && e == hipSuccess; ++k) {
       c.k = k;

@@ -78,10 +78,9 @@ constexpr auto tab_kernel() {
 
 hipError_t launch_tab_sweep(const TabLaunch &v, const double2 *vin, double2 *tm, hipStream_t s,
                             hipEvent_t ev0, hipEvent_t ev1) {
-  static_assert(kGroupShapes == 4, "one kernel per shape");
+  static_assert(kGroupShapes == 3, "one kernel per shape");
   static const void *const kernels[kGroupShapes] = {
-      (const void *)tab_kernel<0>(), (const void *)tab_kernel<1>(),
-      (const void *)tab_kernel<2>(), (const void *)tab_kernel<3>()};
+      (const void *)tab_kernel<0>(), (const void *)tab_kernel<1>(), (const void *)tab_kernel<2>()};
   static bool attr_set = false;
   if (!attr_set) {
     for (int k = 0; k < kGroupShapes; ++k) {

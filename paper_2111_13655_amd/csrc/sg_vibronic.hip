@@ -134,10 +134,9 @@ constexpr auto vib_kernel() {
 
 hipError_t launch_vib_sweep(const VibLaunch &v, const double2 *vin, double2 *tm, hipStream_t s,
                             hipEvent_t ev0, hipEvent_t ev1) {
-  static_assert(kGroupShapes == 4, "one kernel per shape");
+  static_assert(kGroupShapes == 3, "one kernel per shape");
   static const void *const kernels[kGroupShapes] = {
-      (const void *)vib_kernel<0>(), (const void *)vib_kernel<1>(),
-      (const void *)vib_kernel<2>(), (const void *)vib_kernel<3>()};
+      (const void *)vib_kernel<0>(), (const void *)vib_kernel<1>(), (const void *)vib_kernel<2>()};
   static bool attr_set = false;
   if (!attr_set) {
     for (int k = 0; k < kGroupShapes; ++k) {

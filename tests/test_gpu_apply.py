@@ -300,3 +300,28 @@ def test_apply_mixed_all_fp32_config2_error_is_bounded():
         err = _rel2(to_host(ym), to_host(y64))
     say(f"  all-FP32 rel err {err:.3e}")
     assert err < 1e-5
+
+
+def test_apply_mixed_config2_no_fp32_share_meets_the_bar():
+    """(12, 6) full size, on the displaced Gaussian: even the smallest FP32
+    share (the terms with |D_l| = 1) misses 1e-6 against the FP64 GPU path,
+    so the precision autotuner keeps every term in FP64 there and SG_MIXED is
+    then bitwise the FP64 apply.  This is the measured negative result the
+    configuration's mixed leg rests on."""
+    sg = _sg()
+    inst = sg_inputs.config2()
+    say("apply mixed config2: smallest FP32 share")
+    with sg.Problem.from_instance(inst) as P:
+        g = empty(P.n_cs)
+        sg.sg_init_gaussian(P.handle, inst.shift, g)
+        y64, ym = empty(P.n_cs), empty(P.n_cs)
+        P.apply(g, y64, sg.SG_FP64)
+        sg.sg_set_mixed_threshold(P.handle, 1)
+        P.apply(g, ym, sg.SG_MIXED)
+        err1 = _rel2(to_host(ym), to_host(y64))
+        say(f"  |D_l| = 1 terms in FP32: rel err {err1:.3e}")
+        assert TOL_MIXED < err1 < 1e-5
+        thr, _ = sg.sg_tune_mixed(P.handle, g, TOL_MIXED)
+        assert thr == 0
+        P.apply(g, ym, sg.SG_MIXED)
+        assert np.array_equal(to_host(ym), to_host(y64))
