@@ -16,8 +16,7 @@ BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 SOURCES = ["sg_terms.cpp", "sg_tables.cpp", "sg_api.cpp", "sg_cheb.cpp",
            "sg_tune.cpp", "sg_plan.cpp", "sg_batch.cpp", "sg_serve.cpp",
            "sg_eig.cpp", "sg_step.cpp", "sg_sweep.hip", "sg_reduce.hip", "sg_blas.hip",
-           "sg_noalloc.hip", "sg_vibronic.cpp", "sg_vibronic.hip", "sg_tabpot.cpp",
-           "sg_tabpot.hip"]
+           "sg_noalloc.hip", "sg_vibronic.cpp", "sg_vibronic.hip", "sg_tabpot.cpp"]
 
 ARCH = os.environ.get("SG_OFFLOAD_ARCH", "gfx950")
 

@@ -79,8 +79,8 @@ void release(sg_problem *p) {
     return;
   }
   for (hipEvent_t ev : p->timing.ev) hipEventDestroy(ev);
-  tabpot_free(p->tabpot);
-  p->tabpot = nullptr;
+  hipFree(p->d_veff);
+  hipFree(p->d_voff);
   if (p->plan) {
     plan_free(p->plan);
     delete p->plan;
@@ -109,18 +109,6 @@ void release(sg_problem *p) {
 }  // namespace
 
 hipError_t run_sweep(sg_problem *owner, const Plan *pl, const LaunchCtl &c, hipStream_t s) {
-  if (owner && owner->tabpot) {
-    // a tabulated potential: the problem's own sweep over its single
-    // instance, reading the vector the plan's sweep would read
-    if (c.prec != SG_FP64 || pl->inst.size() != 1) return hipErrorInvalidValue;
-    const InstDev &I = pl->inst[0];
-    double2 *x0 = c.x0o ? c.x0o + I.vec_off : I.x0;
-    double2 *x1 = c.x1o ? c.x1o + I.vec_off : I.x1;
-    const double2 *in = c.mode == Mode::Apply ? x0 : (((c.k - 1) & 1) ? x1 : x0);
-    return timed(owner, 0, s, c, [&](const LaunchCtl &ct) {
-      return launch_tab_sweep(*owner->tabpot, in, I.tm, s, ct.ev0, ct.ev1);
-    });
-  }
   if (!owner) return launch_sweep(pl, c, s);
   return timed(owner, 0, s, c, [&](const LaunchCtl &ct) { return launch_sweep(pl, ct, s); });
 }
@@ -323,7 +311,7 @@ sg_status sg_problem_info(const sg_problem *p, sg_info *out) {
   out->pad = 0;
   const double ns = (double)h.MB.size(), ncs = (double)h.ncs;
   out->sweep_bytes = 16.0 * ncs + 4.0 * ns + 16.0 * ns + 4.0 * kTermHdrDwords * (double)h.nterms +
-                     (p->tabpot ? 8.0 * (double)h.grid_active : split ? 24.0 * (double)h.nfib : 0.0);
+                     (p->d_veff ? 8.0 * (double)h.grid_active : split ? 24.0 * (double)h.nfib : 0.0);
   out->reduce_bytes = 16.0 * ns + 4.0 * ns + 8.0 * ncs + 16.0 * ncs + (split ? 8.0 * ncs : 0.0) +
                       16.0 * ncs;
   return SG_OK;
@@ -391,7 +379,7 @@ sg_status sg_apply_H(sg_problem *p, const void *psi_in, void *psi_out, sg_precis
   if (psi_in == psi_out) return fail(SG_EINVAL, "psi_in and psi_out must differ");
   if (p->host_only) return fail(SG_EINVAL, "handle was built without device tables");
   if (prec != SG_FP64 && prec != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
-  if (p->tabpot && prec != SG_FP64) return fail(SG_EINVAL, "a tabulated potential runs in FP64");
+  if (p->d_veff && prec != SG_FP64) return fail(SG_EINVAL, "a tabulated potential runs in FP64");
   hipStream_t s = (hipStream_t)stream;
   LaunchCtl c;
   c.mode = Mode::Apply;
@@ -425,6 +413,10 @@ sg_status rebuild_plan(sg_problem *p) {
 }
 }  // namespace
 
+namespace sg {
+sg_status problem_replan(sg_problem *p) { return rebuild_plan(p); }
+}  // namespace sg
+
 extern "C" {
 
 sg_status sg_set_mixed_threshold(sg_problem *p, int32_t max_fp32_coeff) {
@@ -445,7 +437,7 @@ sg_status sg_set_schedule(sg_problem *p, int32_t block_min_grid, int32_t packs_p
 sg_status sg_set_operator_form(sg_problem *p, int32_t grid_kinetic) {
   if (!p) return fail(SG_EINVAL, "NULL problem");
   if (grid_kinetic != 0 && grid_kinetic != 1) return fail(SG_EINVAL, "grid_kinetic must be 0 or 1");
-  if (p->tabpot && grid_kinetic)
+  if (p->d_veff && grid_kinetic)
     return fail(SG_EINVAL, "a tabulated potential needs the split operator form");
   p->grid_kinetic = grid_kinetic;
   return rebuild_plan(p);

@@ -59,7 +59,7 @@ sg_status sg_batch_create(sg_problem *const *problems, int32_t n, sg_batch **out
   for (int i = 0; i < n; ++i) {
     if (!problems[i] || problems[i]->host_only) return fail(SG_EINVAL, "invalid problem handle");
     if (problems[i]->device != dev) return fail(SG_EINVAL, "problems must be on the current device");
-    if (problems[i]->tabpot) return fail(SG_EINVAL, "a problem with a tabulated potential runs on its own");
+    if (problems[i]->d_veff) return fail(SG_EINVAL, "a problem with a tabulated potential runs on its own");
     for (int j = 0; j < i; ++j)
       if (problems[j] == problems[i]) return fail(SG_EINVAL, "a problem appears twice");
   }

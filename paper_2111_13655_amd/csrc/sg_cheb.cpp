@@ -154,7 +154,7 @@ sg_status sg_propagate_chebyshev(sg_problem *p, void *psi, double dt, int32_t ns
   if (!(dt > 0.0) || !std::isfinite(dt) || nsteps < 0 || check_every < 0)
     return fail(SG_EINVAL, "dt must be > 0, nsteps and check_every >= 0");
   if (prec != SG_FP64 && prec != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
-  if (p->tabpot && prec != SG_FP64) return fail(SG_EINVAL, "a tabulated potential runs in FP64");
+  if (p->d_veff && prec != SG_FP64) return fail(SG_EINVAL, "a tabulated potential runs in FP64");
   if (p->host_only) return fail(SG_EINVAL, "handle was built without device tables");
   hipStream_t s = (hipStream_t)stream;
   if (std::isnan(emin) || std::isnan(emax)) {

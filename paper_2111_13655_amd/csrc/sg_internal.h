@@ -129,6 +129,8 @@ struct InstDev {
   int64_t vec_off;          // added to the launch's vector overrides (x0o, x1o) for this
                             // instance: the electronic states of a two-state problem
                             // are instances over consecutive halves of one vector
+  const double *veff;       // tabulated coupling potential, or null (polynomial couplings)
+  const int64_t *voff;      //   term t's V_eff from veff + voff[t]
 };
 
 // Term-sweep packing.  A workgroup (kSweepThreads threads, eight wavefronts)
@@ -269,7 +271,6 @@ struct Plan;
 }  // namespace sg
 
 namespace sg {
-struct TabLaunch;
 // A problem's own term packs and reduce items, kept so that plans over many
 // problems (batches, the server) concatenate them instead of packing every
 // term again.  Built for a fixed mixed threshold and operator form.
@@ -317,7 +318,10 @@ struct sg_problem {
   double *h_result = nullptr;      // pinned host mirror of d_result
   int64_t device_bytes = 0;
   sg::Plan *plan = nullptr;        // launch plan of this problem alone
-  sg::TabLaunch *tabpot = nullptr; // tabulated coupling potential (sg_set_potential), or none
+  // tabulated coupling potential (sg_set_potential), or none: V_eff of every
+  // term on its active grid (mode 0 fastest), term t's from d_voff[t]
+  double *d_veff = nullptr;
+  int64_t *d_voff = nullptr;
   // optional per-kernel timing with HIP events (sg_set_timing)
   struct Timing {
     bool on = false;
@@ -351,6 +355,7 @@ struct Plan {
   bool any32 = false;              // some term of some instance runs in FP32
   bool fp64_split = false;         // SG_FP64 launches use the split form
   bool any_round32 = false;        // some instance's FP64 terms use rounded tables
+  bool any_tab = false;            // the (single) instance has a tabulated potential
   // standard-map tables for levels 0..stab_L (stab_L < 0: no standard-map instance)
   int stab_L = -1;
   std::vector<double> stab64, stab32r;
@@ -467,7 +472,7 @@ constexpr int kVibSurf = 17 + kMaxPairs;   // 45
 constexpr int kVibCoef = 104;              // 2 kVibSurf + kMaxActive, padded
 static_assert(2 * kVibSurf + kMaxActive <= kVibCoef, "vibronic coefficient block");
 // Launch shapes of the term sweeps that run one term per workgroup (the
-// two-state operator, tabulated potentials): threads per term, the largest
+// two-state operator): threads per term, the largest
 // term grid and the highest active level a shape's kernel takes.  With the
 // standard maps and L <= 6 every term fits one of them (grids above 1024
 // points have levels <= 2, above 256 levels <= 3).  Every shape is one
@@ -505,24 +510,9 @@ hipError_t launch_vib_sweep(const VibLaunch &v, const double2 *vin, double2 *tm,
 hipError_t run_vib_sweep(sg_problem *owner, const VibLaunch &v, const double2 *vin, double2 *tm,
                          hipStream_t s);
 
-// A problem's tabulated coupling potential (sg_tabpot.cpp): V_eff of every
-// term on its active grid (mode 0 fastest), and the sweep's launch groups.
-struct TabLaunch {
-  const TermDev *terms = nullptr;
-  const int32_t *mb = nullptr;
-  const double *tab = nullptr;     // standard-map tables, levels 0..L
-  double *veff = nullptr;          // device, owned: [n_veff]
-  int64_t *voff = nullptr;         // device, owned: [nterms], term t's V_eff from voff[t]
-  int32_t *order = nullptr;        // device, owned: terms in group order
-  std::vector<TermGroup> groups;
-  int tab_elems = 0;
-  int64_t n_veff = 0;
-};
-void tabpot_free(TabLaunch *t);   // the device buffers and the record
-// vin: [N_cs]; tm: [N_s].  ev0 / ev1 (nullable) attach to the first / last
-// dispatch.
-hipError_t launch_tab_sweep(const TabLaunch &v, const double2 *vin, double2 *tm, hipStream_t s,
-                            hipEvent_t ev0, hipEvent_t ev1);
+// Rebuilds and re-uploads a problem's own launch plan after one of its
+// settings changed (the device is synchronised first).
+sg_status problem_replan(sg_problem *p);
 
 // Work buffers of one sg_propagate call (sg_step.cpp): allocated for the call
 // (owned), or carved out of a region the caller provides (not owned).

@@ -278,6 +278,8 @@ void inst_from_problem(const sg_problem *p, InstDev *d) {
   d->partials = p->d_partials;
   d->abc = p->d_abc;
   d->nfib = p->h.nfib;
+  d->veff = p->d_veff;
+  d->voff = p->d_voff;
   d->result = p->d_result;
   d->cheb_a = p->d_cheb_a;
   d->ncs = h.ncs;
@@ -384,6 +386,7 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
   pl->scratch_bytes = 0;
   pl->any32 = false;
   pl->fp64_split = false;
+  pl->any_tab = false;
   const bool multi = probs.size() > 1;
   std::vector<Cand> cg64, cs64, m64, m32;
   bool split_all = true;
@@ -415,6 +418,11 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
     }
     pl->inst[i].round32 = inst32 ? 1 : 0;
     pl->any32 = pl->any32 || inst32;
+    pl->any_tab = pl->any_tab || p->d_veff != nullptr;
+  }
+  if (pl->any_tab && multi) {
+    *err = "a problem with a tabulated potential runs on its own";
+    return SG_EINVAL;
   }
   pl->fp64_split = split_all;
   // standard-map tables (identical for every such instance) for LDS

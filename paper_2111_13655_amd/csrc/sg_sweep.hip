@@ -61,6 +61,7 @@ struct TermCtx {
   glb_p<const double> abc;   // per-fiber A, B, C (variant chosen; FP64 terms)
   const void *gtab;          // the standard-map tables in HBM (variant chosen)
   int64_t nfib;              // stride between the A, B and C arrays
+  glb_p<const double> vt;    // tabulated potential: the term's V_eff (null: polynomial)
 };
 
 struct SweepArgs {
@@ -739,7 +740,7 @@ __device__ __forceinline__ void run_term(const TermCtx &a, cptr<TermDev> T, P ba
   const double cf = T->coeff;
   if (na == 0) {  // every mode at a one-function level: a scalar term
     if (G::tid() == 0) {
-      const double c0 = T->c0[a.split ? kPotSplit : kPotFull];
+      const double c0 = a.vt ? a.vt[0] : T->c0[a.split ? kPotSplit : kPotFull];
       const Z64 x = ldc<Z64>(a.psi + a.mb[off]);
       stc(a.tm + off, Z64{cf * c0 * x.x, cf * c0 * x.y});
     }
@@ -1196,6 +1197,7 @@ __device__ __forceinline__ FiberABC<R, inplace_fpt(NQ)> load_abc(const TermCtx &
                                                                  int base = 0) {
   constexpr int FPT = inplace_fpt(NQ);
   FiberABC<R, FPT> r;
+  if (a.vt) return r;   // a tabulated potential reads V_eff instead
   if constexpr (sizeof(R) == sizeof(double)) {
     const int nj = min(FPT, (nfib - base + G::N - 1) / G::N);
     const glb_p<const double> A = a.abc + T.foff();
@@ -1218,7 +1220,7 @@ template <typename G, typename R, int NQ, int NB, bool STORE, int FPT>
 __device__ __forceinline__ void pot_g2b0_chunk(const TermHdr &T, lds_p<typename Cx<R>::T> buf,
                                                lds_p<const R> lt, lds_p<const R> cf, int nfib,
                                                Out o, double dl, const FiberABC<R, FPT> &pre,
-                                               int base) {
+                                               int base, glb_p<const double> vt) {
   typedef typename Cx<R>::T C;
   const int na = T.na();
   const int l0 = T.lev(0);
@@ -1227,7 +1229,15 @@ __device__ __forceinline__ void pot_g2b0_chunk(const TermHdr &T, lds_p<typename 
   int fb[FPT], rem[FPT];
   R A[FPT], B[FPT], Cl[FPT];
   R xq[FPT][kMaxActive];
-  if (pre.have) {
+  if (vt) {   // tabulated potential: V_eff is read per point below
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      const int f = base + G::tid() + j * G::N;
+      ok[j] = f < nfib && j < nj;
+      fb[j] = ok[j] ? f : 0;
+      A[j] = B[j] = Cl[j] = (R)0;
+    }
+  } else if (pre.have) {
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
       const int f = base + G::tid() + j * G::N;
@@ -1298,7 +1308,7 @@ __device__ __forceinline__ void pot_g2b0_chunk(const TermHdr &T, lds_p<typename 
       const int kk = wrap_add(k, sk, NQ);
       const C v = ldc<C>(buf + fb[j] * NQ + kk);
       const R xv = x0[kk];
-      const R V = fma(fma(B[j], xv, Cl[j]), xv, A[j]);
+      const R V = vt ? (R)vt[fb[j] * NQ + kk] : fma(fma(B[j], xv, Cl[j]), xv, A[j]);
       x[j][k] = Cx<R>::make(V * v.x, V * v.y);
     }
   }
@@ -1331,7 +1341,7 @@ __device__ __forceinline__ void pot_g2b0_ip(const TermCtx &a, const TermHdr &T,
                                             lds_p<const R> cf, int nfib, Out o, double dl,
                                             const FiberABC<R, inplace_fpt(NQ)> &pre0) {
   constexpr int FPT = inplace_fpt(NQ);
-  pot_g2b0_chunk<G, R, NQ, NB, STORE, FPT>(T, buf, lt, cf, nfib, o, dl, pre0, 0);
+  pot_g2b0_chunk<G, R, NQ, NB, STORE, FPT>(T, buf, lt, cf, nfib, o, dl, pre0, 0, a.vt);
   for (int base = FPT * G::N; base < nfib; base += G::N) {
     if (!STORE) G::sync();
     FiberABC<R, 1> pre;
@@ -1345,7 +1355,7 @@ __device__ __forceinline__ void pot_g2b0_ip(const TermCtx &a, const TermHdr &T,
         pre.have = true;
       }
     }
-    pot_g2b0_chunk<G, R, NQ, NB, STORE, 1>(T, buf, lt, cf, nfib, o, dl, pre, base);
+    pot_g2b0_chunk<G, R, NQ, NB, STORE, 1>(T, buf, lt, cf, nfib, o, dl, pre, base, a.vt);
   }
 }
 
@@ -1466,7 +1476,7 @@ __device__ __forceinline__ void run_any(const TermCtx &a, cptr<TermDev> T, const
                                         P base, int inplace, char *lds_raw) {
   if (T->na == 0) {
     if (G::tid() == 0) {
-      const double c0 = T->c0[a.split ? kPotSplit : kPotFull];
+      const double c0 = a.vt ? a.vt[0] : T->c0[a.split ? kPotSplit : kPotFull];
       const Z64 x = ldc<Z64>(a.psi + a.mb[T->off]);
       stc(a.tm + T->off, Z64{T->coeff * c0 * x.x, T->coeff * c0 * x.y});
     }
@@ -1489,7 +1499,7 @@ __device__ __forceinline__ const double2 *input_of(const SweepArgs &a, cptr<Inst
   return ((a.k - 1) & 1) ? x1 : x0;   // phi_{k-1}
 }
 
-template <typename R>
+template <typename R, bool TAB>
 __device__ __forceinline__ TermCtx make_ctx(const SweepArgs &a, cptr<InstDev> I, int t) {
   TermCtx c;
   c.mb = (glb_p<const int32_t>)I->mb;
@@ -1507,12 +1517,15 @@ __device__ __forceinline__ TermCtx make_ctx(const SweepArgs &a, cptr<InstDev> I,
   c.pcoef = (glb_p<const double>)(I->potc + ((size_t)t * 2 + (r32 ? 1 : 0)) * kCoefStride);
   c.abc = (glb_p<const double>)(I->abc + (r32 ? 3 * I->nfib : 0));
   c.nfib = I->nfib;
+  c.vt = nullptr;
+  if constexpr (TAB) c.vt = (glb_p<const double>)(I->veff + I->voff[t]);
   return c;
 }
 
-// IP: every term of the launch runs in place.  Two workgroups per compute
-// unit: at most 128 VGPRs per lane.
-template <typename R, bool IP>
+// IP: every term of the launch runs in place.  TAB: the instance's coupling
+// potential is tabulated (V_eff per term, read along the fibers).  Two
+// workgroups per compute unit: at most 128 VGPRs per lane.
+template <typename R, bool IP, bool TAB>
 __global__ __launch_bounds__(kThreads, 4) void sweep_kernel(SweepArgs a) {
   extern __shared__ char lds_raw[];
   typedef typename Cx<R>::T C;
@@ -1527,7 +1540,7 @@ __global__ __launch_bounds__(kThreads, 4) void sweep_kernel(SweepArgs a) {
   const int t = P->term[w];
   const cptr<TermDev> T = (cptr<TermDev>)(I->terms + t);
   const TermHdr hdr = load_hdr(T);
-  TermCtx c = make_ctx<R>(a, I, t);
+  TermCtx c = make_ctx<R, TAB>(a, I, t);
   c.mbt = (glb_p<const int32_t>)P->mbt[w];
   // the standard-map tables into LDS (every wavefront takes part): the
   // exact set at 0, the FP32-rounded FP64 set (if any) at tab_a, levels up to
@@ -1562,29 +1575,36 @@ __global__ __launch_bounds__(kThreads, 4) void sweep_kernel(SweepArgs a) {
   run_any<WaveGroup, R, lds_p<C>, IP>(c, T, hdr, (lds_p<C>)(pack_lds + P->lds_off[w]),
                                       P->inplace[w], lds_raw);
 }
-template <typename R, bool IP>
+template <typename R, bool IP, bool TAB>
 hipError_t launch_packs_as(const SweepArgs &a, int npacks, int lds, hipStream_t s,
                            hipEvent_t ev0, hipEvent_t ev1) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)sweep_kernel<R, IP>,
+    hipError_t e = hipFuncSetAttribute((const void *)sweep_kernel<R, IP, TAB>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   if (ev0 || ev1)
-    hipExtLaunchKernelGGL((sweep_kernel<R, IP>), dim3((unsigned)npacks), dim3(kThreads), lds, s,
+    hipExtLaunchKernelGGL((sweep_kernel<R, IP, TAB>), dim3((unsigned)npacks), dim3(kThreads), lds, s,
                           ev0, ev1, 0, a);
   else
-    hipLaunchKernelGGL((sweep_kernel<R, IP>), dim3((unsigned)npacks), dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((sweep_kernel<R, IP, TAB>), dim3((unsigned)npacks), dim3(kThreads), lds, s,
+                       a);
   return hipGetLastError();
 }
 
+// tab: the plan's single instance has a tabulated potential (FP64, in place)
 template <typename R>
 hipError_t launch_packs(const SweepArgs &a, const PackSet &ps, hipStream_t s, hipEvent_t ev0,
-                        hipEvent_t ev1) {
-  if (ps.all_inplace) return launch_packs_as<R, true>(a, ps.count, ps.lds_bytes, s, ev0, ev1);
-  return launch_packs_as<R, false>(a, ps.count, ps.lds_bytes, s, ev0, ev1);
+                        hipEvent_t ev1, bool tab = false) {
+  if constexpr (sizeof(R) == sizeof(double))
+    if (tab) {
+      if (!ps.all_inplace) return hipErrorInvalidValue;
+      return launch_packs_as<R, true, true>(a, ps.count, ps.lds_bytes, s, ev0, ev1);
+    }
+  if (ps.all_inplace) return launch_packs_as<R, true, false>(a, ps.count, ps.lds_bytes, s, ev0, ev1);
+  return launch_packs_as<R, false, false>(a, ps.count, ps.lds_bytes, s, ev0, ev1);
 }
 
 }  // namespace
@@ -1663,8 +1683,9 @@ hipError_t launch_sweep(const Plan *pl, const LaunchCtl &c, hipStream_t s) {
     a.packs = (cptr<PackDev>)(pl->d_packs + ps.first);
     a.stab = pl->d_stab64;
     a.tab_a = ps.tab_bytes;
-    return launch_packs<double>(a, ps, s, c.ev0, c.ev1);
+    return launch_packs<double>(a, ps, s, c.ev0, c.ev1, pl->any_tab);
   }
+  if (pl->any_tab) return hipErrorInvalidValue;   // tabulated potentials run in FP64
   // mixed: terms with large |D_l| in FP64, the rest in FP32.  The FP64 terms
   // of an instance that also has FP32 terms read the FP32-rounded tables, so
   // that all its terms apply the same one-mode operators and the Smolyak

@@ -7,8 +7,9 @@
 // level-0 mode has one basis function, so its basis -> grid pass multiplies by
 // b_0(Q_u) and its grid -> basis pass by wt_u b_0(Q_u).  sg_set_potential
 // evaluates the caller's V on every term's literal grid (host, batched),
-// forms these per-term tables V_eff,l and uploads them with the launch groups
-// of the tabulated sweep (sg_tabpot.hip).
+// forms these per-term tables V_eff,l and uploads them; the problem's term
+// sweep then multiplies each grid value by V_eff read along its fiber instead
+// of forming the polynomial couplings (the kernel's tabulated instantiation).
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -17,14 +18,6 @@
 #include "sg_internal.h"
 
 namespace sg {
-
-void tabpot_free(TabLaunch *t) {
-  if (!t) return;
-  hipFree(t->veff);
-  hipFree(t->voff);
-  hipFree(t->order);
-  delete t;
-}
 
 namespace {
 
@@ -114,11 +107,14 @@ extern "C" sg_status sg_set_potential(sg_problem *p, sg_potential_fn fn, void *u
   if (!p) return fail(SG_EINVAL, "NULL problem");
   if (p->host_only) return fail(SG_EINVAL, "handle was built without device tables");
   if (!fn) {
-    if (p->tabpot) {
+    if (p->d_veff) {
       hipError_t e = hipDeviceSynchronize();
       if (e != hipSuccess) return hip_fail(e, "synchronize");
-      tabpot_free(p->tabpot);
-      p->tabpot = nullptr;
+      hipFree(p->d_veff);
+      hipFree(p->d_voff);
+      p->d_veff = nullptr;
+      p->d_voff = nullptr;
+      return problem_replan(p);
     }
     return SG_OK;
   }
@@ -128,6 +124,8 @@ extern "C" sg_status sg_set_potential(sg_problem *p, sg_potential_fn fn, void *u
   if (h.L > 6) return fail(SG_EINVAL, "a tabulated potential takes L <= 6");
   if (!p->plan || !p->plan->fp64_split || p->grid_kinetic)
     return fail(SG_EINVAL, "a tabulated potential needs the split operator form");
+  if (!p->plan->sets[kSetSplit64].all_inplace)
+    return fail(SG_EINVAL, "a tabulated potential needs every term in place");
   if (p->plan->stab_L < h.L) return fail(SG_EINVAL, "standard-map tables missing");
   if ((double)h.grid_literal > kMaxPoints)
     return fail(SG_EINVAL, "more than 1e11 grid points to evaluate");
@@ -135,40 +133,38 @@ extern "C" sg_status sg_set_potential(sg_problem *p, sg_potential_fn fn, void *u
   std::vector<int64_t> voff;
   sg_status st = tabulate(h, p->plan->stab64, fn, user, &veff, &voff);
   if (st != SG_OK) return st;
-  TabLaunch *t = new (std::nothrow) TabLaunch();
-  if (!t) return fail(SG_ENOMEM, "host allocation failed");
-  std::vector<int32_t> order;
-  if (!group_terms(h, &order, &t->groups)) {
-    delete t;
-    return fail(SG_EINVAL, "a term fits no launch shape");
-  }
-  hipError_t e = hipMalloc((void **)&t->veff, std::max<size_t>(1, veff.size()) * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void **)&t->voff, voff.size() * sizeof(int64_t));
-  if (e == hipSuccess) e = hipMalloc((void **)&t->order, order.size() * sizeof(int32_t));
+  double *dv = nullptr;
+  int64_t *doff = nullptr;
+  hipError_t e = hipMalloc((void **)&dv, std::max<size_t>(1, veff.size()) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void **)&doff, voff.size() * sizeof(int64_t));
   if (e != hipSuccess) {
-    tabpot_free(t);
+    hipFree(dv);
+    hipFree(doff);
     return fail(SG_ENOMEM, "device allocation failed");
   }
-  e = hipMemcpy(t->veff, veff.data(), veff.size() * sizeof(double), hipMemcpyHostToDevice);
+  e = hipMemcpy(dv, veff.data(), veff.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = hipMemcpy(t->voff, voff.data(), voff.size() * sizeof(int64_t), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(t->order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    e = hipMemcpy(doff, voff.data(), voff.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
-    tabpot_free(t);
+    hipFree(dv);
+    hipFree(doff);
     return hip_fail(e, "upload potential tables");
   }
-  t->terms = p->d_terms;
-  t->mb = p->d_mb;
-  t->tab = p->plan->d_stab64;
-  t->tab_elems = (int)((p->plan->stab64.size() + 1) & ~(size_t)1);
-  t->n_veff = (int64_t)veff.size();
-  e = hipDeviceSynchronize();
-  if (e != hipSuccess) {
-    tabpot_free(t);
-    return hip_fail(e, "synchronize");
+  double *old_v = p->d_veff;
+  int64_t *old_off = p->d_voff;
+  p->d_veff = dv;
+  p->d_voff = doff;
+  st = problem_replan(p);   // synchronises before it replaces the plan
+  if (st != SG_OK) {
+    p->d_veff = old_v;
+    p->d_voff = old_off;
+    hipFree(dv);
+    hipFree(doff);
+    problem_replan(p);
+    return st;
   }
-  tabpot_free(p->tabpot);
-  p->tabpot = t;
+  hipFree(old_v);
+  hipFree(old_off);
   return SG_OK;
 }

@@ -1,6 +1,6 @@
-// Device building blocks of the term sweeps that run one Smolyak term per
-// workgroup over NS coupled states (the two-state operator, tabulated
-// potentials).  Alg. 1 per term, for every state s = 0..NS-1:
+// Device building blocks of term sweeps that run one Smolyak term per
+// workgroup over NS coupled states (the two-state operator: NS = 2).  Alg. 1
+// per term, for every state s = 0..NS-1:
 //   1. gather the term's coefficients through M^B, fused with the basis ->
 //      grid contraction along the first active mode (fibers along that mode
 //      are contiguous in the term-major layout);
