@@ -167,3 +167,23 @@ def test_tabulated_bench_workload_full_vector():
     ref = O.apply_literal(psi)
     with _problem(sg, inst, V) as P:
         assert max_rel(_apply(P, psi), ref) < TOL
+
+
+@pytest.mark.parametrize("method,order", [("taylor", 12), ("sil", 10), ("rk", 4), ("bs", 3)])
+def test_tabulated_other_propagators_vs_oracle(method, order):
+    """The other propagators on a tabulated potential (they apply H through
+    the same sweep) against the oracle's steppers on Route 1."""
+    from oracle import stepping
+    sg = _sg()
+    inst = sg_inputs.small_instance(3, 3, seed=31)
+    V = sg_inputs.general_potential(3, seed=31)
+    O = Oracle(inst, coupling=V)
+    psi0 = rand_state(O.S.n_cs, 12)
+    ref = stepping.propagate(method, O.apply_literal, psi0, 0.02, 5, order)
+    codes = {"taylor": "SG_PROP_TAYLOR", "sil": "SG_PROP_SIL", "rk": "SG_PROP_RK", "bs": "SG_PROP_BS"}
+    with _problem(sg, inst, V) as P:
+        x = to_dev(psi0)
+        status, _, _, _ = sg.sg_propagate(P.handle, x, 0.02, 5, getattr(sg, codes[method]), order)
+        out = to_host(x)
+    assert status == 0
+    assert max_rel(out, ref) < 1e-11
