@@ -458,10 +458,13 @@ sg_status sg_set_operator_form(sg_problem *p, int32_t grid_kinetic);
  * polynomial couplings.
  * Requirements: a device handle with the standard size maps (nb = 1 + 2l,
  * nq = 2 + 2l), L <= 6, the split operator form, and at most 1e11 grid points.
- * Such a problem runs in FP64 only (SG_MIXED calls fail with SG_EINVAL) and on
- * its own (sg_batch_create refuses it).  Errors: SG_EINVAL (requirements, a
+ * Such a problem runs in FP64 only: SG_MIXED calls on it fail with SG_EINVAL,
+ * and so do mixed batch calls whose batch has FP32 terms (in a batch without
+ * any, SG_MIXED is the FP64 split path).  sg_set_operator_form(p, 1) is
+ * refused while a potential is set.  Errors: SG_EINVAL (requirements, a
  * non-finite V), SG_ENOMEM, SG_EDEVICE; on error the previous potential stays.
- * Synchronous: the device is synchronised before the tables are replaced. */
+ * Synchronous: the device is synchronised before the tables are replaced.
+ * A batch created afterwards takes the problem with its potential. */
 typedef void (*sg_potential_fn)(int64_t n, const double *Q, double *out, void *user);
 sg_status sg_set_potential(sg_problem *p, sg_potential_fn V, void *user);
 

@@ -30,6 +30,12 @@ sg_precision launch_precision(const Plan &pl, sg_precision prec) {
   return (prec == SG_MIXED && !pl.any32 && pl.fp64_split) ? SG_FP64 : prec;
 }
 
+// A tabulated potential runs in FP64: a mixed batch holding one runs only
+// when no term of the batch is in FP32 (then it is the FP64 split path).
+bool precision_ok(const Plan &pl, sg_precision prec) {
+  return !(pl.any_tab && launch_precision(pl, prec) == SG_MIXED);
+}
+
 sg_status batch_step_launches(sg_batch *b, sg_precision prec, int kmax, hipStream_t s) {
   LaunchCtl c;
   c.mode = Mode::Cheb;
@@ -59,7 +65,6 @@ sg_status sg_batch_create(sg_problem *const *problems, int32_t n, sg_batch **out
   for (int i = 0; i < n; ++i) {
     if (!problems[i] || problems[i]->host_only) return fail(SG_EINVAL, "invalid problem handle");
     if (problems[i]->device != dev) return fail(SG_EINVAL, "problems must be on the current device");
-    if (problems[i]->d_veff) return fail(SG_EINVAL, "a problem with a tabulated potential runs on its own");
     for (int j = 0; j < i; ++j)
       if (problems[j] == problems[i]) return fail(SG_EINVAL, "a problem appears twice");
   }
@@ -99,6 +104,8 @@ sg_status sg_batch_tune_schedule(sg_batch *b, void *const *psi, int32_t n_psi, i
     return fail(SG_EINVAL, "the number of states must equal the batch's number of instances");
   if (reps < 1) return fail(SG_EINVAL, "reps must be >= 1");
   if (prec != SG_FP64 && prec != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
+  if (!precision_ok(b->plan, (sg_precision)prec))
+    return fail(SG_EINVAL, "a tabulated potential runs in FP64 (the batch has FP32 terms)");
   for (int i = 0; i < n_psi; ++i)
     if (!psi[i]) return fail(SG_EINVAL, "NULL state");
   hipStream_t s = (hipStream_t)stream;
@@ -228,6 +235,8 @@ sg_status sg_batch_propagate(sg_batch *b, void *const *psi, int32_t n_psi, const
     return fail(SG_EINVAL, "the number of states must equal the batch's number of instances");
   if (nsteps < 0 || check_every < 0) return fail(SG_EINVAL, "nsteps, check_every must be >= 0");
   if (prec != SG_FP64 && prec != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
+  if (!precision_ok(b->plan, prec))
+    return fail(SG_EINVAL, "a tabulated potential runs in FP64 (the batch has FP32 terms)");
   hipStream_t s = (hipStream_t)stream;
   const int n = (int)b->probs.size();
   Plan &pl = b->plan;

@@ -355,7 +355,7 @@ struct Plan {
   bool any32 = false;              // some term of some instance runs in FP32
   bool fp64_split = false;         // SG_FP64 launches use the split form
   bool any_round32 = false;        // some instance's FP64 terms use rounded tables
-  bool any_tab = false;            // the (single) instance has a tabulated potential
+  bool any_tab = false;            // some instance has a tabulated potential
   // standard-map tables for levels 0..stab_L (stab_L < 0: no standard-map instance)
   int stab_L = -1;
   std::vector<double> stab64, stab32r;

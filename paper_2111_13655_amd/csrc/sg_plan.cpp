@@ -420,10 +420,6 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
     pl->any32 = pl->any32 || inst32;
     pl->any_tab = pl->any_tab || p->d_veff != nullptr;
   }
-  if (pl->any_tab && multi) {
-    *err = "a problem with a tabulated potential runs on its own";
-    return SG_EINVAL;
-  }
   pl->fp64_split = split_all;
   // standard-map tables (identical for every such instance) for LDS
   pl->stab_L = -1;

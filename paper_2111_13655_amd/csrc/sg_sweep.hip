@@ -1518,7 +1518,8 @@ __device__ __forceinline__ TermCtx make_ctx(const SweepArgs &a, cptr<InstDev> I,
   c.abc = (glb_p<const double>)(I->abc + (r32 ? 3 * I->nfib : 0));
   c.nfib = I->nfib;
   c.vt = nullptr;
-  if constexpr (TAB) c.vt = (glb_p<const double>)(I->veff + I->voff[t]);
+  if constexpr (TAB)
+    if (I->veff) c.vt = (glb_p<const double>)(I->veff + I->voff[t]);
   return c;
 }
 
@@ -1594,14 +1595,15 @@ hipError_t launch_packs_as(const SweepArgs &a, int npacks, int lds, hipStream_t 
   return hipGetLastError();
 }
 
-// tab: the plan's single instance has a tabulated potential (FP64, in place)
+// tab: some instance of the plan has a tabulated potential (FP64; its terms
+// run in place, the others as they would)
 template <typename R>
 hipError_t launch_packs(const SweepArgs &a, const PackSet &ps, hipStream_t s, hipEvent_t ev0,
                         hipEvent_t ev1, bool tab = false) {
   if constexpr (sizeof(R) == sizeof(double))
     if (tab) {
-      if (!ps.all_inplace) return hipErrorInvalidValue;
-      return launch_packs_as<R, true, true>(a, ps.count, ps.lds_bytes, s, ev0, ev1);
+      if (ps.all_inplace) return launch_packs_as<R, true, true>(a, ps.count, ps.lds_bytes, s, ev0, ev1);
+      return launch_packs_as<R, false, true>(a, ps.count, ps.lds_bytes, s, ev0, ev1);
     }
   if (ps.all_inplace) return launch_packs_as<R, true, false>(a, ps.count, ps.lds_bytes, s, ev0, ev1);
   return launch_packs_as<R, false, false>(a, ps.count, ps.lds_bytes, s, ev0, ev1);

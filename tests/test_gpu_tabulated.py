@@ -135,8 +135,6 @@ def test_tabulated_refusals():
         with pytest.raises(sg.SgError):
             P.apply(x, y, sg.SG_MIXED)
         with pytest.raises(sg.SgError):
-            sg.sg_batch_create([P.handle])
-        with pytest.raises(sg.SgError):
             sg.sg_set_operator_form(P.handle, True)
 
         def bad(Q):
@@ -187,3 +185,32 @@ def test_tabulated_other_propagators_vs_oracle(method, order):
         out = to_host(x)
     assert status == 0
     assert max_rel(out, ref) < 1e-11
+
+
+def test_tabulated_in_a_batch_is_bitwise_its_own_propagation():
+    """A batch holding a tabulated problem and a polynomial one: each
+    instance's result is bitwise the one it gets propagated alone (the batch
+    runs the tabulated instantiation of the sweep for both)."""
+    sg = _sg()
+    inst_t = sg_inputs.small_instance(4, 4, seed=41)
+    V = sg_inputs.general_potential(4, seed=41)
+    inst_p = sg_inputs.small_instance(5, 3, seed=42)
+    with _problem(sg, inst_t, V) as PT, sg.Problem.from_instance(inst_p) as PP:
+        probs = [PT, PP]
+        psi0 = [rand_state(P.n_cs, 50 + i) for i, P in enumerate(probs)]
+        bounds = [sg.sg_spectral_bounds(P.handle, 40) for P in probs]
+        alone = []
+        for P, x0, (lo, hi) in zip(probs, psi0, bounds):
+            x = to_dev(x0)
+            st, _, _, _ = sg.sg_propagate_chebyshev(P.handle, x, 0.05, 6, lo, hi, tol=1e-6)
+            assert st == 0
+            alone.append(to_host(x))
+        b = sg.sg_batch_create([P.handle for P in probs])
+        xs = [to_dev(x0) for x0 in psi0]
+        status, _ = sg.sg_batch_propagate(b, xs, [0.05, 0.05], 6, [lo for lo, _ in bounds],
+                                          [hi for _, hi in bounds], tol=1e-6)
+        out = [to_host(x) for x in xs]
+        sg.sg_batch_free(b)
+    assert status == 0
+    for a_, o in zip(alone, out):
+        assert np.array_equal(a_, o)
