@@ -464,7 +464,8 @@ sg_status sg_set_operator_form(sg_problem *p, int32_t grid_kinetic);
  * refused while a potential is set.  Errors: SG_EINVAL (requirements, a
  * non-finite V), SG_ENOMEM, SG_EDEVICE; on error the previous potential stays.
  * Synchronous: the device is synchronised before the tables are replaced.
- * A batch created afterwards takes the problem with its potential. */
+ * A batch created afterwards takes the problem with its potential; a batch
+ * created before refuses to run (SG_EINVAL) once the potential changed. */
 typedef void (*sg_potential_fn)(int64_t n, const double *Q, double *out, void *user);
 sg_status sg_set_potential(sg_problem *p, sg_potential_fn V, void *user);
 

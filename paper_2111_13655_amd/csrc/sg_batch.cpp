@@ -30,6 +30,16 @@ sg_precision launch_precision(const Plan &pl, sg_precision prec) {
   return (prec == SG_MIXED && !pl.any32 && pl.fp64_split) ? SG_FP64 : prec;
 }
 
+// The batch's instance records still name every problem's current potential
+// tables (a potential set, changed or cleared after the batch was created
+// would leave them naming other, possibly freed, tables).
+bool potentials_current(const sg_batch *b) {
+  for (size_t i = 0; i < b->probs.size(); ++i)
+    if (b->plan.inst[i].veff != b->probs[i]->d_veff || b->plan.inst[i].voff != b->probs[i]->d_voff)
+      return false;
+  return true;
+}
+
 // A tabulated potential runs in FP64: a mixed batch holding one runs only
 // when no term of the batch is in FP32 (then it is the FP64 split path).
 bool precision_ok(const Plan &pl, sg_precision prec) {
@@ -106,6 +116,8 @@ sg_status sg_batch_tune_schedule(sg_batch *b, void *const *psi, int32_t n_psi, i
   if (prec != SG_FP64 && prec != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
   if (!precision_ok(b->plan, (sg_precision)prec))
     return fail(SG_EINVAL, "a tabulated potential runs in FP64 (the batch has FP32 terms)");
+  if (!potentials_current(b))
+    return fail(SG_EINVAL, "a problem's potential changed after the batch was created");
   for (int i = 0; i < n_psi; ++i)
     if (!psi[i]) return fail(SG_EINVAL, "NULL state");
   hipStream_t s = (hipStream_t)stream;
@@ -237,6 +249,8 @@ sg_status sg_batch_propagate(sg_batch *b, void *const *psi, int32_t n_psi, const
   if (prec != SG_FP64 && prec != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
   if (!precision_ok(b->plan, prec))
     return fail(SG_EINVAL, "a tabulated potential runs in FP64 (the batch has FP32 terms)");
+  if (!potentials_current(b))
+    return fail(SG_EINVAL, "a problem's potential changed after the batch was created");
   hipStream_t s = (hipStream_t)stream;
   const int n = (int)b->probs.size();
   Plan &pl = b->plan;

@@ -210,6 +210,11 @@ def test_tabulated_in_a_batch_is_bitwise_its_own_propagation():
         status, _ = sg.sg_batch_propagate(b, xs, [0.05, 0.05], 6, [lo for lo, _ in bounds],
                                           [hi for _, hi in bounds], tol=1e-6)
         out = [to_host(x) for x in xs]
+        # a potential changed after the batch was created: the batch refuses
+        sg.sg_set_potential(PP.handle, sg_inputs.general_potential(5).at_points)
+        with pytest.raises(sg.SgError):
+            sg.sg_batch_propagate(b, xs, [0.05, 0.05], 1, [lo for lo, _ in bounds],
+                                  [hi for _, hi in bounds], tol=1e-6)
         sg.sg_batch_free(b)
     assert status == 0
     for a_, o in zip(alone, out):
