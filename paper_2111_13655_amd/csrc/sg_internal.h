@@ -160,6 +160,8 @@ struct PackDev {
   int32_t lds_off[kPackTerms];  // byte offset of each wavefront's LDS slice
   int32_t inplace[kPackTerms];  // 1: in place (one buffer), 0: ping-pong
   int32_t maxlev;               // highest level of an active mode of the pack's terms
+  int32_t slices;               // LDS bytes of the pack's term buffers (after its tables)
+  int32_t lds_base;             // byte offset of those buffers in LDS (pack_lds_base)
   int32_t pad;
   int64_t scratch_off;          // kPackBlockScratch: byte offset in the plan's scratch
   const int32_t *mbt[kPackTerms];  // each term's first M^B entry (device), for its gather
@@ -177,6 +179,16 @@ struct PackSet {
 // nodes (nq), at element offset std_table_base(l).
 __host__ __device__ constexpr int std_table_base(int l) {
   return 8 * ((l - 1) * l * (2 * l - 1) / 6) + 7 * l * (l - 1) + 6 * l;
+}
+// Where a pack's term buffers start in LDS.  The tables come first, laid out
+// by level.  With one table set (tab_b = 0) a pack holds the levels up to its
+// highest only, so its buffers start right after those; with two sets (the
+// exact and the FP32-rounded FP64 tables) after both whole sets.  elem_r:
+// bytes of one table entry.  The planner stores it in each pack.
+__host__ __device__ constexpr int pack_lds_base(int tab_a, int tab_b, int elem_r, int maxlev) {
+  return tab_b > 0 ? tab_a + tab_b
+                   : (((elem_r * std_table_base(maxlev + 1) < tab_a ? elem_r * std_table_base(maxlev + 1)
+                                                                     : tab_a) + 15) & ~15);
 }
 // Pack sets: FP64 with the kinetic matrices on the grid (all terms); FP64
 // with the separable part split off (all terms); the mixed path's FP64 terms;
@@ -279,7 +291,6 @@ struct PackCache {
   int32_t thr = -1, grid_kinetic = -1, block_grid = -1;
   std::vector<PackDev> packs[kPackSets];   // inst = 0
   std::vector<double> cost[kPackSets];
-  int32_t pack_lds[kPackSets] = {0, 0, 0, 0};   // largest pack, tables excluded
   int64_t scratch[kPackSets] = {0, 0, 0, 0};    // scratch bytes of each set
   std::vector<RedItem> items;              // inst = 0
   bool inst32 = false;

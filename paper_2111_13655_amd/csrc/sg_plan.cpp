@@ -5,13 +5,16 @@
 //   * one wavefront, for in-place terms of at most kWaveMaxGrid points (a
 //     contraction over more fibers than the lanes hold runs in chunks) and
 //     for small ping-pong terms;
-//   * the four wavefronts of a workgroup otherwise, with its buffer in LDS
+//   * the eight wavefronts of a workgroup otherwise, with its buffer in LDS
 //     when it fits under the per-workgroup cap, else in global scratch.
+// A pack's LDS holds the one-mode tables of the levels up to its highest,
+// then its terms' buffers, under the cap of two workgroups per compute unit.
 // Wave terms are dealt, most expensive first, to the least loaded of enough
 // packs (at most kPackTerms terms and the LDS cap each) to give every compute
-// unit work.  Terms of different instances mix freely: every term is
-// computed by the same code whatever its pack, so results do not depend on
-// the mix.
+// unit work; terms taking more than a quarter of the cap instead fill packs
+// as densely as the cap allows, so that more of them run at once.  Terms of
+// different instances mix freely: every term is computed by the same code
+// whatever its pack, so results do not depend on the mix.
 //
 // Reduce items (one per wavefront): a workgroup's worth per long row, one per
 // eight short rows, in each instance's row order, padded to
@@ -105,21 +108,25 @@ Cand make_cand(int32_t inst, int32_t term, const Compiled &h, bool split, int el
 // otherwise enough packs to give every compute unit `spread` workgroups (one
 // by default: the wavefronts of a sparsely filled pack then have their CU's
 // SIMDs to themselves).  costs (nullable) receives the estimated cost of each
-// pack appended to out.
-void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vector<PackDev> *out,
-              PackSet *set, int64_t *scratch_bytes, bool dense = false,
+// pack appended to out.  tab_bytes: the set's tables in LDS, two_sets: they
+// are two sets of tab_bytes / 2 (then a pack keeps room for both whole).
+void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, bool two_sets,
+              std::vector<PackDev> *out, PackSet *set, int64_t *scratch_bytes, bool dense = false,
               std::vector<double> *costs = nullptr, int spread = 1) {
   set->first = (int32_t)out->size();
   set->count = 0;
   set->lds_bytes = 0;
   set->tab_bytes = 0;
   if (cands.empty()) return;
-  // two workgroups per compute unit (FP64), four (FP32); the tables come first
+  // two workgroups per compute unit (FP64), four (FP32); a pack's tables come
+  // first, the levels up to its highest (pack_lds_base)
   const int cap_total = elem >= 16 ? kLdsPerCU / 2 : kLdsPerCU / 4;
   const int per_cu = kLdsPerCU / cap_total;
-  const int cap = cap_total - tab_bytes;
+  const int tab_a = two_sets ? tab_bytes / 2 : tab_bytes, tab_b = two_sets ? tab_bytes / 2 : 0;
+  auto tables = [&](int maxlev) { return pack_lds_base(tab_a, tab_b, elem / 2, maxlev); };
+  auto fits = [&](int64_t bytes, int maxlev) { return bytes + tables(maxlev) <= cap_total; };
   std::vector<Cand> big, small;
-  for (const Cand &c : cands) (c.wave && c.slice <= cap ? small : big).push_back(c);
+  for (const Cand &c : cands) (c.wave && fits(c.slice, c.maxlev) ? small : big).push_back(c);
   auto by_cost = [](const Cand &a, const Cand &b) { return a.cost > b.cost; };
   std::stable_sort(big.begin(), big.end(), by_cost);
   std::stable_sort(small.begin(), small.end(), by_cost);
@@ -151,16 +158,34 @@ void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vect
     std::push_heap(heap.begin(), heap.end(), worse);
   };
   for (int64_t i = 0; i < nbins; ++i) new_bin();
+  // terms taking more than a quarter of a pack's LDS fill packs as densely as
+  // LDS allows (first fit), so that more of them run at once on a compute
+  // unit; cur is the pack they are filling, held out of the heap meanwhile
+  int64_t cur = -1;
+  auto release_cur = [&]() {
+    if (cur >= 0 && bins[cur].n < kPackTerms) {
+      heap.push_back({bin_load[cur], cur});
+      std::push_heap(heap.begin(), heap.end(), worse);
+    }
+    cur = -1;
+  };
   for (const Cand &c : small) {
-    // least loaded bin with room (bins without room leave the heap for good
-    // once full; bins short of LDS are set aside for this term only)
-    std::vector<Bin> aside;
+    const bool heavy = 4 * c.slice > cap_total;
     Bin b{0.0, -1};
-    while (!heap.empty()) {
+    if (heavy && cur >= 0 && bins[cur].n < kPackTerms &&
+        fits(bin_bytes[cur] + c.slice, std::max<int32_t>(bins[cur].maxlev, c.maxlev)))
+      b = {bin_load[cur], cur};
+    else
+      release_cur();
+    // otherwise the least loaded bin with room (bins without room leave the
+    // heap for good once full; bins short of LDS are set aside for this term
+    // only)
+    std::vector<Bin> aside;
+    while (b.id < 0 && !heap.empty()) {
       std::pop_heap(heap.begin(), heap.end(), worse);
       Bin t = heap.back();
       heap.pop_back();
-      if (bin_bytes[t.id] + c.slice <= cap) {
+      if (fits(bin_bytes[t.id] + c.slice, std::max<int32_t>(bins[t.id].maxlev, c.maxlev))) {
         b = t;
         break;
       }
@@ -187,11 +212,14 @@ void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vect
     pk.n += 1;
     b.load += c.cost;
     bin_load[b.id] = b.load;
-    if (pk.n < kPackTerms) {
+    if (heavy)
+      cur = b.id;
+    else if (pk.n < kPackTerms) {
       heap.push_back(b);
       std::push_heap(heap.begin(), heap.end(), worse);
     }
   }
+  release_cur();
   for (const Cand &c : big) {
     PackDev pk;
     std::memset(&pk, 0, sizeof(pk));
@@ -203,9 +231,9 @@ void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vect
     }
     pk.inplace[0] = c.inplace;
     pk.maxlev = c.maxlev;
-    if (c.slice <= cap) {
+    if (fits(c.slice, c.maxlev)) {
       pk.block = kPackBlockLds;
-      lds = std::max<int>(lds, (int)c.slice);
+      pk.slices = (int32_t)c.slice;
     } else {
       // global scratch holds the two ping-pong buffers
       pk.block = kPackBlockScratch;
@@ -213,6 +241,8 @@ void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vect
       pk.scratch_off = *scratch_bytes;
       *scratch_bytes += (2 * c.ngrid * elem + 255) & ~(int64_t)255;
     }
+    pk.lds_base = tables(pk.maxlev);
+    lds = std::max<int>(lds, pk.lds_base + pk.slices);
     out->push_back(pk);
     if (costs) costs->push_back(c.cost);
   }
@@ -230,13 +260,15 @@ void pack_set(const std::vector<Cand> &cands, int elem, int tab_bytes, std::vect
       pk.term[w] = pk.term[0];
       pk.mbt[w] = pk.mbt[0];
     }
+    pk.slices = (int32_t)bin_bytes[i];
+    pk.lds_base = tables(pk.maxlev);
     out->push_back(pk);
     if (costs) costs->push_back(bin_load[i]);
-    lds = std::max<int>(lds, (int)bin_bytes[i]);
+    lds = std::max<int>(lds, pk.lds_base + pk.slices);
   }
   set->count = (int32_t)(out->size() - set->first);
   set->tab_bytes = tab_bytes;
-  set->lds_bytes = tab_bytes + lds;
+  set->lds_bytes = lds;
 }
 
 template <typename T>
@@ -349,8 +381,8 @@ void build_cache(sg_problem *p) {
     c.cost[k].clear();
     PackSet ps;
     c.scratch[k] = 0;
-    pack_set(*cs[k], elem[k], tab[k], &c.packs[k], &ps, &c.scratch[k], true, &c.cost[k]);
-    c.pack_lds[k] = ps.count ? ps.lds_bytes - ps.tab_bytes : 0;
+    pack_set(*cs[k], elem[k], tab[k], k == kSetMixed64 && c.inst32, &c.packs[k], &ps,
+             &c.scratch[k], true, &c.cost[k]);
   }
   c.items.clear();
   reduce_items(p, 0, &c.items);
@@ -465,14 +497,14 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
     // the set SG_FP64 launches do not use stays empty
     if (split_all) cg64.clear(); else cs64.clear();
     const int sp = probs[0]->packs_per_cu;
-    pack_set(cg64, 16, tabs[kSetGrid64], &pl->packs, &pl->sets[kSetGrid64], &pl->scratch_bytes,
-             false, nullptr, sp);
-    pack_set(cs64, 16, tabs[kSetSplit64], &pl->packs, &pl->sets[kSetSplit64], &pl->scratch_bytes,
-             false, nullptr, sp);
-    pack_set(m64, 16, tabs[kSetMixed64], &pl->packs, &pl->sets[kSetMixed64], &pl->scratch_bytes,
-             false, nullptr, sp);
-    pack_set(m32, 8, tabs[kSetMixed32], &pl->packs, &pl->sets[kSetMixed32], &pl->scratch_bytes,
-             false, nullptr, sp);
+    pack_set(cg64, 16, tabs[kSetGrid64], false, &pl->packs, &pl->sets[kSetGrid64],
+             &pl->scratch_bytes, false, nullptr, sp);
+    pack_set(cs64, 16, tabs[kSetSplit64], false, &pl->packs, &pl->sets[kSetSplit64],
+             &pl->scratch_bytes, false, nullptr, sp);
+    pack_set(m64, 16, tabs[kSetMixed64], pl->any_round32, &pl->packs, &pl->sets[kSetMixed64],
+             &pl->scratch_bytes, false, nullptr, sp);
+    pack_set(m32, 8, tabs[kSetMixed32], false, &pl->packs, &pl->sets[kSetMixed32],
+             &pl->scratch_bytes, false, nullptr, sp);
     mark_inplace_sets(pl);
     return SG_OK;
   }
@@ -485,7 +517,6 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
     set.lds_bytes = 0;
     if ((k == kSetGrid64 && split_all) || (k == kSetSplit64 && !split_all)) continue;
     std::vector<std::pair<double, PackDev>> all;
-    int pack_lds = 0;
     for (size_t i = 0; i < probs.size(); ++i) {
       const PackCache &c = probs[i]->pcache;
       const int64_t base = pl->scratch_bytes;
@@ -496,18 +527,22 @@ sg_status plan_build(Plan *pl, const std::vector<sg_problem *> &probs, std::stri
         all.push_back({c.cost[k][q], pk});
       }
       pl->scratch_bytes += c.scratch[k];
-      pack_lds = std::max(pack_lds, c.pack_lds[k]);
     }
     std::stable_sort(all.begin(), all.end(),
                      [](const std::pair<double, PackDev> &a, const std::pair<double, PackDev> &b) {
                        return a.first > b.first;
                      });
-    for (const auto &x : all) pl->packs.push_back(x.second);
-    set.count = (int32_t)all.size();
-    if (set.count) {
-      set.tab_bytes = tabs[k];
-      set.lds_bytes = tabs[k] + pack_lds;
+    // the launch's table layout (two sets: the mixed FP64 terms of a plan
+    // with FP32-rounded instances), and each pack's buffers after it
+    const bool two = k == kSetMixed64 && pl->any_round32;
+    const int tab_a = two ? tabs[k] / 2 : tabs[k], tab_b = two ? tabs[k] / 2 : 0;
+    for (auto &x : all) {
+      x.second.lds_base = pack_lds_base(tab_a, tab_b, k == kSetMixed32 ? 4 : 8, x.second.maxlev);
+      set.lds_bytes = std::max(set.lds_bytes, x.second.lds_base + x.second.slices);
+      pl->packs.push_back(x.second);
     }
+    set.count = (int32_t)all.size();
+    if (set.count) set.tab_bytes = tabs[k];
   }
   mark_inplace_sets(pl);
   return SG_OK;

@@ -1545,7 +1545,7 @@ __global__ __launch_bounds__(kThreads, 4) void sweep_kernel(SweepArgs a) {
   c.mbt = (glb_p<const int32_t>)P->mbt[w];
   // the standard-map tables into LDS (every wavefront takes part): the
   // exact set at 0, the FP32-rounded FP64 set (if any) at tab_a, levels up to
-  // the pack's highest only
+  // the pack's highest only; the pack's term buffers follow (at lds_base)
   {
     const lds_p<Z64> dst = (lds_p<Z64>)lds_raw;
     const glb_p<const Z64> sa = (glb_p<const Z64>)a.stab;
@@ -1558,7 +1558,7 @@ __global__ __launch_bounds__(kThreads, 4) void sweep_kernel(SweepArgs a) {
     if (na16 + nb16 > 0) __syncthreads();
   }
   if (!has_term || !live(a, I)) return;
-  char *const pack_lds = lds_raw + a.tab_a + a.tab_b;
+  char *const pack_lds = lds_raw + __builtin_amdgcn_readfirstlane(P->lds_base);
   if (kind != kPackWaves) {
     if constexpr (IP) {
       run_any<BlockGroup, R, lds_p<C>, true>(c, T, hdr, (lds_p<C>)pack_lds, 1, lds_raw);

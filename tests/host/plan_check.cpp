@@ -8,6 +8,7 @@
 // dereferenced.  Built and run by the host test suite.
 #include <cstdio>
 #include <cstdint>
+#include <algorithm>
 #include "sg_internal.h"
 using namespace sg;
 
@@ -46,6 +47,33 @@ int main() {
     return (uintptr_t)x >= (uintptr_t)base && (uintptr_t)x + sz <= (uintptr_t)base + n * sz;
   };
   auto check = [&](const Plan &pl, const std::vector<sg_problem *> &probs) {
+    // every pack's tables (levels up to its highest) and term buffers fit
+    // the launch's LDS, and that stays within two workgroups per compute unit
+    for (int k = 0; k < kPackSets; ++k) {
+      const PackSet &set = pl.sets[k];
+      const bool two = k == kSetMixed64 && pl.any_round32;
+      const int ta = two ? set.tab_bytes / 2 : set.tab_bytes, tb = two ? set.tab_bytes / 2 : 0;
+      const int er = k == kSetMixed32 ? 4 : 8;
+      if (set.count && set.lds_bytes > kLdsPerCU / (k == kSetMixed32 ? 4 : 2)) {
+        printf("set %d lds %d\n", k, set.lds_bytes); bad++;
+      }
+      for (int q = set.first; q < set.first + set.count; ++q) {
+        const PackDev &pk = pl.packs[q];
+        if (pk.lds_base != pack_lds_base(ta, tb, er, pk.maxlev) || pk.lds_base + pk.slices > set.lds_bytes) {
+          printf("pack %d lds\n", q); bad++;
+        }
+        if (pk.block == kPackWaves)
+          for (int w = 0; w < pk.n; ++w) {
+            const sg_problem *p = probs[pk.inst[w]];
+            const TermDev &T = p->h.terms[pk.term[w]];
+            int ml = 0;
+            for (int m = 0; m < T.na; ++m) ml = std::max<int>(ml, T.lev[m]);
+            if (ml > pk.maxlev || pk.lds_off[w] < 0 || pk.lds_off[w] > pk.slices) {
+              printf("pack %d slot %d maxlev/offset\n", q, w); bad++;
+            }
+          }
+      }
+    }
     for (const PackDev &pk : pl.packs) {
       const int slots = pk.block == kPackWaves ? kPackTerms : 1;
       for (int w = 0; w < slots; ++w) {
