@@ -42,6 +42,26 @@ def test_schedules_agree_bitwise(prec):
             assert np.array_equal(o.view(np.float64), outs[0].view(np.float64))
 
 
+def test_schedules_agree_bitwise_config2():
+    """(D, L) = (12, 6): the default packing (1536-point terms three to a
+    wavefront pack) against schedules that run those terms, or every term
+    above 512 points, on whole workgroups: bitwise the same H|psi>."""
+    import torch
+    sg = _sg()
+    inst = sg_inputs.config2()
+    say("schedules (12,6)")
+    with sg.Problem.from_instance(inst) as P:
+        x = _random_state(P.n_cs, 4)
+        y = torch.empty_like(x)
+        outs = []
+        for g, spread in ((0, 1), (1025, 1), (513, 2), (4096, 1)):
+            sg.sg_set_schedule(P.handle, g, spread)
+            sg.sg_apply_H(P.handle, x, y, 0)
+            outs.append(to_host(y).copy())
+        for o in outs[1:]:
+            assert np.array_equal(o.view(np.float64), outs[0].view(np.float64))
+
+
 def test_tuned_schedule_matches_oracle():
     import torch
     sg = _sg()
